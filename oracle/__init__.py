@@ -1,0 +1,262 @@
+"""CPU oracle for the batch transaction engine -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
+leg may import this package.  It shares no code with the HIP engine: the serial
+executor is plain C (``oracle.c``), the closed forms below are plain numpy.
+
+Correctness criterion: every scheme guarantees serializable isolation (Section
+3, "CC Schemes Migration and Implementation"; Section 4.1, "CC Scheme
+Selection").  Non-deterministic schemes may legitimately produce different
+outcomes for the same batch (Section 2, "conflict graph-based schemes being
+deterministic, while others are non-deterministic"), so the oracle does not
+predict one outcome.  It checks what is unique -- the set of committed
+transactions, and the final tables of add-only batches (``final_add_only``,
+a closed form that needs no order) -- and checks that the rest is valid: the
+run's reported serial order, replayed serially, must reproduce every read value
+and the final tables bit-exactly (``check_run``), and on tiny batches some
+order out of all k! must do so (``bruteforce_count``).  The paper's own check
+is acyclicity of a conflict graph built from an event log (Section 3.4,
+"Measurements and Verification"); replaying a total order is a stronger form
+of the same test.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+# Outcome status values and op kinds, as the engine's interface defines them.
+COMMITTED = 1
+READ, ADD, COND_ADD, WRITE_SLOT = 0, 1, 2, 3
+
+_P = ctypes.c_void_p
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc into oracle/liboracle.so."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp"
+        subprocess.run(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC", _SRC, "-o", tmp],
+                       check=True)
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_SO)
+        lib.oracle_replay.restype = ctypes.c_int
+        lib.oracle_replay.argtypes = [ctypes.c_uint32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                      ctypes.c_uint64, _P, ctypes.c_uint64, _P]
+        lib.oracle_bruteforce.restype = ctypes.c_int64
+        lib.oracle_bruteforce.argtypes = [ctypes.c_uint32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                          ctypes.c_uint64, _P, ctypes.c_int, _P, ctypes.c_uint64]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _batch_arrays(batch):
+    return [np.ascontiguousarray(batch.first_op, np.uint64), np.ascontiguousarray(batch.n_ops, np.uint32),
+            np.ascontiguousarray(batch.row, np.uint32), np.ascontiguousarray(batch.table, np.uint16),
+            np.ascontiguousarray(batch.field, np.uint8), np.ascontiguousarray(batch.kind, np.uint8),
+            np.ascontiguousarray(batch.arg, np.int64)]
+
+
+def _table_args(tables):
+    tabs = [np.ascontiguousarray(t, dtype=np.int64) for t in tables]
+    n_rows = np.array([t.shape[0] for t in tabs], np.uint64)
+    n_fields = np.array([t.shape[1] for t in tabs], np.uint32)
+    ptrs = (ctypes.c_void_p * max(len(tabs), 1))(*[t.ctypes.data for t in tabs])
+    return tabs, n_rows, n_fields, ptrs
+
+
+_ERR = {-2: "row/field/table out of range", -3: "unknown op kind", -4: "WRITE_SLOT source not earlier",
+        -5: "out of memory", -6: "bad argument"}
+
+
+def replay(tables, batch, order):
+    """Serially execute ``batch`` transactions ``order`` (in that order) from ``tables``.
+
+    Returns (final_tables, reads); reads[op] is the value op read, for ops of
+    replayed transactions (other entries are 0).  Inputs are not modified.
+    """
+    lib = _load()
+    tabs, n_rows, n_fields, ptrs = _table_args([np.array(t, dtype=np.int64, copy=True) for t in tables])
+    arrs = _batch_arrays(batch)
+    order = np.ascontiguousarray(order, dtype=np.int64)
+    reads = np.zeros(max(batch.total_ops, 1), np.int64)
+    rc = lib.oracle_replay(len(tabs), _ptr(n_rows), _ptr(n_fields), ptrs, *[_ptr(a) for a in arrs],
+                           batch.n_txns, _ptr(order), len(order), _ptr(reads))
+    if rc != 0:
+        raise ValueError(f"oracle_replay: {_ERR.get(rc, rc)}")
+    return tabs, reads[:batch.total_ops]
+
+
+def serial_execute(tables, batch):
+    """Execute every transaction of the batch serially in id order (no concurrency)."""
+    return replay(tables, batch, np.arange(batch.n_txns, dtype=np.int64))
+
+
+def serial_order(status, serial_hi, serial_lo):
+    """Committed transaction ids sorted by their (serial_hi, serial_lo) keys.
+
+    Raises ValueError if two committed transactions report the same key (the
+    reported order would not be a total order).
+    """
+    status = np.asarray(status)
+    idx = np.nonzero(status == COMMITTED)[0]
+    hi = np.asarray(serial_hi, np.uint64)[idx]
+    lo = np.asarray(serial_lo, np.uint64)[idx]
+    o = np.lexsort((lo, hi))
+    hs, ls = hi[o], lo[o]
+    if len(o) > 1 and np.any((hs[1:] == hs[:-1]) & (ls[1:] == ls[:-1])):
+        raise ValueError("duplicate serial keys among committed transactions")
+    return idx[o].astype(np.int64)
+
+
+def final_add_only(tables, batch, committed=None):
+    """Closed-form final tables for a batch of READ and ADD operations only.
+
+    Adds commute, so the final value of every cell is its initial value plus
+    the arguments of all committed ADDs on it, whatever the serial order.
+    """
+    if np.any((batch.kind != READ) & (batch.kind != ADD)):
+        raise ValueError("closed form needs READ/ADD operations only")
+    out = [np.array(t, dtype=np.int64, copy=True) for t in tables]
+    txn_of_op = np.repeat(np.arange(batch.n_txns), batch.n_ops.astype(np.int64))
+    m = batch.kind == ADD
+    if committed is not None:
+        m &= np.asarray(committed, bool)[txn_of_op]
+    for t, tab in enumerate(out):
+        mt = m & (batch.table == t)
+        flat = tab.reshape(-1)
+        idx = batch.row[mt].astype(np.int64) * tab.shape[1] + batch.field[mt].astype(np.int64)
+        with np.errstate(over="ignore"):
+            np.add.at(flat, idx, batch.arg[mt])
+    return out
+
+
+def bruteforce_count(tables, batch, txn_ids, got_reads, got_final) -> int:
+    """Number of serial orders of ``txn_ids`` (k <= 8) reproducing the reads and final tables."""
+    lib = _load()
+    init, n_rows, n_fields, ptrs = _table_args(tables)
+    fin, _, _, fptrs = _table_args(got_final)
+    arrs = _batch_arrays(batch)
+    txn_ids = np.ascontiguousarray(txn_ids, np.int64)
+    got_reads = np.ascontiguousarray(got_reads, np.int64)
+    rc = lib.oracle_bruteforce(len(init), _ptr(n_rows), _ptr(n_fields), ptrs, fptrs, *[_ptr(a) for a in arrs],
+                               batch.n_txns, _ptr(txn_ids), len(txn_ids), _ptr(got_reads), batch.total_ops)
+    if rc < 0:
+        raise ValueError(f"oracle_bruteforce: {_ERR.get(int(rc), rc)}")
+    return int(rc)
+
+
+@dataclass
+class CheckReport:
+    ok: bool
+    n_committed: int
+    read_mismatches: int = 0
+    table_mismatches: int = 0
+    closed_form_ok: bool | None = None
+    problems: list = field(default_factory=list)
+
+    def __str__(self):
+        return (f"ok={self.ok} committed={self.n_committed} read_mismatch={self.read_mismatches} "
+                f"table_mismatch={self.table_mismatches} closed_form={self.closed_form_ok} "
+                f"problems={self.problems[:6]}")
+
+
+def check_run(init_tables, batch, status, serial_hi, serial_lo, got_reads, got_final,
+              require_all_committed=True) -> CheckReport:
+    """Check one run of the engine against the definition of serializability.
+
+    1. Every transaction committed (when required: the paper's batch model
+       retries each transaction until it commits, Section 4.1).
+    2. Committed transactions carry distinct serial keys.
+    3. Replaying them serially in key order reproduces, element by element,
+       every value the run reported as read, and the final tables.
+    4. For add-only batches, the final tables equal the order-free closed form.
+    """
+    status = np.asarray(status)
+    committed = status == COMMITTED
+    rep = CheckReport(ok=True, n_committed=int(committed.sum()))
+    if require_all_committed and not committed.all():
+        rep.ok = False
+        rep.problems.append(f"{int((~committed).sum())} transactions did not commit")
+    try:
+        order = serial_order(status, serial_hi, serial_lo)
+    except ValueError as e:
+        rep.ok = False
+        rep.problems.append(str(e))
+        return rep
+    exp_final, exp_reads = replay(init_tables, batch, order)
+    txn_of_op = np.repeat(np.arange(batch.n_txns), batch.n_ops.astype(np.int64))
+    opm = committed[txn_of_op]
+    got_reads = np.asarray(got_reads, np.int64)
+    bad = np.nonzero(opm & (exp_reads != got_reads))[0]
+    rep.read_mismatches = int(len(bad))
+    for op in bad[:5]:
+        rep.problems.append(f"txn {int(txn_of_op[op])} op {int(op)}: expected {int(exp_reads[op])} "
+                            f"got {int(got_reads[op])}")
+    for t, (e, g) in enumerate(zip(exp_final, got_final)):
+        nb = int(np.count_nonzero(np.asarray(g, np.int64) != e))
+        rep.table_mismatches += nb
+        if nb:
+            rep.problems.append(f"table {t}: {nb} cells differ from the serial replay")
+    if np.all((batch.kind == READ) | (batch.kind == ADD)):
+        cf = final_add_only(init_tables, batch, committed)
+        rep.closed_form_ok = all(np.array_equal(c, np.asarray(g, np.int64)) for c, g in zip(cf, got_final))
+        if not rep.closed_form_ok:
+            rep.problems.append("final tables differ from the add-only closed form")
+    rep.ok = rep.ok and rep.read_mismatches == 0 and rep.table_mismatches == 0 and rep.closed_form_ok is not False
+    return rep
+
+
+def order_entry_invariants(init_tables, final_tables, batch, committed) -> list:
+    """Closed-form invariants of the order-entry workload; returns a list of violations.
+
+    * warehouse ytd == sum of its districts' ytd (payments add the same amount to both);
+    * sum(customer balance) + sum(warehouse ytd) is unchanged (payments move money);
+    * district next-order-id growth == committed new-orders of that district;
+    * total stock order-count growth == committed order lines.
+    """
+    from paper_2406_10158_amd import workload as wl  # table/field numbering only
+    committed = np.asarray(committed, bool)
+    out = []
+    wh0, di0, cu0 = init_tables[wl.T_WAREHOUSE], init_tables[wl.T_DISTRICT], init_tables[wl.T_CUSTOMER]
+    wh, di, cu, st = (np.asarray(final_tables[i], np.int64) for i in
+                      (wl.T_WAREHOUSE, wl.T_DISTRICT, wl.T_CUSTOMER, wl.T_STOCK))
+    st0 = init_tables[wl.T_STOCK]
+    W = wh.shape[0]
+    dsum = di[:, wl.D_YTD].reshape(W, wl.DISTRICTS_PER_W).sum(axis=1)
+    if not np.array_equal(wh[:, wl.W_YTD], dsum):
+        out.append("warehouse ytd != sum of district ytd")
+    if cu[:, wl.C_BALANCE].sum() + wh[:, wl.W_YTD].sum() != cu0[:, wl.C_BALANCE].sum() + wh0[:, wl.W_YTD].sum():
+        out.append("customer balance + warehouse ytd not conserved")
+    is_no = np.asarray(batch.meta["is_new_order"], bool)
+    txn_of_op = np.repeat(np.arange(batch.n_txns), batch.n_ops.astype(np.int64))
+    dop = (batch.table == wl.T_DISTRICT) & (batch.field == wl.D_NEXT_O_ID) & committed[txn_of_op]
+    per_d = np.bincount(batch.row[dop].astype(np.int64), minlength=di.shape[0])
+    if not np.array_equal(di[:, wl.D_NEXT_O_ID] - di0[:, wl.D_NEXT_O_ID], per_d):
+        out.append("district next_o_id growth != committed new-orders")
+    lines = int(((batch.table == wl.T_ORDER_LINE) & (batch.field == wl.OL_AMOUNT) & committed[txn_of_op]).sum())
+    if int(st[:, wl.S_ORDER_CNT].sum() - st0[:, wl.S_ORDER_CNT].sum()) != lines:
+        out.append("stock order_cnt growth != committed order lines")
+    if int(committed[is_no].sum()) != int(((batch.table == wl.T_ORDER) & (batch.field == wl.O_ID)
+                                           & committed[txn_of_op]).sum()):
+        out.append("order slot count != committed new-orders")
+    return out

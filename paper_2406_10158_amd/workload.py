@@ -1,0 +1,401 @@
+"""Seeded synthetic inputs for the batch transaction engine.
+
+This module only draws inputs: tables, transactions and their operations.  It
+holds none of the concurrency-control arithmetic and none of the operation
+semantics; both the HIP engine and the CPU oracle consume what it returns.
+
+Workload shapes follow the paper's evaluation setup (Section 4.1, "Benchmark
+Selection"): YCSB-style key-value transactions of single-tuple accesses with
+Zipfian keys, a write proportion, and TPC-C-style NewOrder / Payment
+transactions.  Neither suite's own code is reproduced; these generators are
+stand-ins with the same shapes, sizes and distributions.
+
+Random numbers come from ``numpy.random.Generator(PCG64(seed))`` in a fixed
+draw order, so a (config, seed) pair always yields the same bytes.
+"""
+from __future__ import annotations
+
+import functools
+import math
+from dataclasses import dataclass, field as dc_field
+
+import numpy as np
+
+# Operation kinds (the numbering is part of the C-ABI, see include/cc.h).
+READ, ADD, COND_ADD, WRITE_SLOT = 0, 1, 2, 3
+
+# Order-entry table ids and field layouts.
+T_WAREHOUSE, T_DISTRICT, T_CUSTOMER, T_ITEM, T_STOCK, T_ORDER, T_ORDER_LINE = range(7)
+W_TAX, W_YTD = 0, 1
+D_TAX, D_YTD, D_NEXT_O_ID = 0, 1, 2
+C_DISCOUNT, C_BALANCE, C_YTD_PAYMENT, C_PAYMENT_CNT = 0, 1, 2, 3
+I_PRICE = 0
+S_QUANTITY, S_YTD, S_ORDER_CNT, S_REMOTE_CNT = 0, 1, 2, 3
+O_ID, O_C_ID, O_OL_CNT = 0, 1, 2
+OL_AMOUNT, OL_QUANTITY = 0, 1
+OE_FIELDS = (2, 3, 4, 1, 4, 3, 2)
+DISTRICTS_PER_W = 10
+CUSTOMERS_PER_D = 3000
+N_ITEMS = 100_000
+STOCK_PER_W = 100_000
+INIT_W_YTD = 30_000_000       # cents; equals 10 districts x INIT_D_YTD
+INIT_D_YTD = 3_000_000
+INIT_NEXT_O_ID = 3001
+INIT_C_BALANCE = -1_000       # cents
+INIT_S_QUANTITY_RANGE = (10, 100)
+
+
+@dataclass
+class Batch:
+    """A batch of transactions in structure-of-arrays form.
+
+    Transaction ``t`` owns operations ``first_op[t] .. first_op[t]+n_ops[t]-1``
+    (in program order).  Operation ``i`` touches field ``field[i]`` of row
+    ``row[i]`` of table ``table[i]`` with kind ``kind[i]`` and argument
+    ``arg[i]``.
+    """
+    first_op: np.ndarray  # uint64 [n_txns]
+    n_ops: np.ndarray     # uint32 [n_txns]
+    row: np.ndarray       # uint32 [total_ops]
+    table: np.ndarray     # uint16 [total_ops]
+    field: np.ndarray     # uint8  [total_ops]
+    kind: np.ndarray      # uint8  [total_ops]
+    arg: np.ndarray       # int64  [total_ops]
+    meta: dict = dc_field(default_factory=dict)
+
+    @property
+    def n_txns(self) -> int:
+        return int(self.n_ops.shape[0])
+
+    @property
+    def total_ops(self) -> int:
+        return int(self.row.shape[0])
+
+    def txn_slice(self, t: int) -> slice:
+        a = int(self.first_op[t])
+        return slice(a, a + int(self.n_ops[t]))
+
+    def subset(self, txn_ids) -> "Batch":
+        """A new batch holding the given transactions, re-packed contiguously."""
+        txn_ids = np.asarray(txn_ids, dtype=np.int64)
+        n = self.n_ops[txn_ids].astype(np.uint32)
+        first = np.zeros(len(txn_ids), dtype=np.uint64)
+        if len(txn_ids):
+            first[1:] = np.cumsum(n[:-1], dtype=np.uint64)
+        if len(txn_ids):
+            idx = np.concatenate([np.arange(int(self.first_op[t]), int(self.first_op[t]) + int(self.n_ops[t]))
+                                  for t in txn_ids]).astype(np.int64)
+        else:
+            idx = np.zeros(0, dtype=np.int64)
+        return Batch(first, n, self.row[idx].copy(), self.table[idx].copy(), self.field[idx].copy(),
+                     self.kind[idx].copy(), self.arg[idx].copy(), dict(self.meta))
+
+
+def _empty_batch() -> Batch:
+    return Batch(np.zeros(0, np.uint64), np.zeros(0, np.uint32), np.zeros(0, np.uint32),
+                 np.zeros(0, np.uint16), np.zeros(0, np.uint8), np.zeros(0, np.uint8),
+                 np.zeros(0, np.int64))
+
+
+# ----------------------------------------------------------------------------
+# Key distributions
+# ----------------------------------------------------------------------------
+
+@functools.lru_cache(maxsize=8)
+def zipf_cdf(n: int, theta: float) -> np.ndarray:
+    """Cumulative probabilities of ranks 1..n with weight r^-theta (exact, normalised)."""
+    if theta == 0.0:
+        return np.arange(1, n + 1, dtype=np.float64) / n
+    w = np.arange(1, n + 1, dtype=np.float64) ** (-float(theta))
+    c = np.cumsum(w)
+    c /= c[-1]
+    c[-1] = 1.0
+    return c
+
+
+def zipf_p1(n: int, theta: float) -> float:
+    """Probability of the hottest rank, 1 / zeta(n, theta)."""
+    c = zipf_cdf(n, theta)
+    return float(c[0])
+
+
+def scramble_multiplier(n: int) -> int:
+    """Multiplier A with gcd(A, n) == 1 so that rank -> (rank * A) mod n is a bijection."""
+    if n <= 1:
+        return 1
+    a = 2654435761 % n
+    if a == 0:
+        a = 1
+    while math.gcd(a, n) != 1:
+        a += 1
+    return a
+
+
+def draw_keys(rng: np.random.Generator, n: int, theta: float, size: int, scramble: bool = True) -> np.ndarray:
+    """Draw ``size`` row ids in [0, n) with Zipf(theta) popularity (theta=0 is uniform).
+
+    Rank 0 is the hottest key.  With ``scramble`` the rank is mapped to a row by
+    a fixed multiplicative bijection, so hot rows do not share cache lines.
+    """
+    if theta == 0.0:
+        ranks = rng.integers(0, n, size=size, dtype=np.int64)
+    else:
+        u = rng.random(size)
+        ranks = np.searchsorted(zipf_cdf(n, theta), u, side="right").astype(np.int64)
+        np.minimum(ranks, n - 1, out=ranks)
+    if not scramble:
+        return ranks.astype(np.uint32)
+    a = np.uint64(scramble_multiplier(n))
+    return ((ranks.astype(np.uint64) * a) % np.uint64(n)).astype(np.uint32)
+
+
+def rank_to_row(rank: int, n: int) -> int:
+    return (rank * scramble_multiplier(n)) % n
+
+
+def _distinct_rows(rng, n, theta, lengths, scramble=True, max_rounds=10_000):
+    """Row ids per transaction, distinct within each transaction (redrawing duplicates)."""
+    lengths = np.asarray(lengths, dtype=np.int64)
+    b = len(lengths)
+    if b == 0:
+        return np.zeros(0, np.uint32)
+    m = int(lengths.max()) if b else 0
+    if m > n:
+        raise ValueError("a transaction needs more distinct rows than the table has")
+    valid = np.arange(m)[None, :] < lengths[:, None]
+    rows = np.zeros((b, m), dtype=np.int64)
+    rows[valid] = draw_keys(rng, n, theta, int(valid.sum()), scramble)
+    # Padding slots get values >= n, unique per column, so they never collide.
+    pad = n + np.broadcast_to(np.arange(m), (b, m))
+    rows[~valid] = pad[~valid]
+    todo = np.arange(b)
+    for _ in range(max_rounds):
+        sub = rows[todo]
+        order = np.argsort(sub, axis=1, kind="stable")
+        ss = np.take_along_axis(sub, order, 1)
+        dup_sorted = np.zeros_like(ss, dtype=bool)
+        dup_sorted[:, 1:] = ss[:, 1:] == ss[:, :-1]
+        if not dup_sorted.any():
+            break
+        has = dup_sorted.any(axis=1)
+        todo = todo[has]
+        order, dup_sorted, sub = order[has], dup_sorted[has], sub[has]
+        dup = np.zeros_like(dup_sorted)
+        np.put_along_axis(dup, order, dup_sorted, 1)
+        sub[dup] = draw_keys(rng, n, theta, int(dup.sum()), scramble)
+        rows[todo] = sub
+    else:  # pragma: no cover - only reachable with absurd theta and tiny tables
+        raise RuntimeError("could not draw distinct rows")
+    return rows[valid].astype(np.uint32)
+
+
+def _pack(lengths, row, table, field, kind, arg, meta) -> Batch:
+    n_ops = np.asarray(lengths, dtype=np.uint32)
+    first = np.zeros(len(n_ops), dtype=np.uint64)
+    if len(n_ops) > 1:
+        first[1:] = np.cumsum(n_ops[:-1], dtype=np.uint64)
+    return Batch(first, n_ops, np.ascontiguousarray(row, np.uint32), np.ascontiguousarray(table, np.uint16),
+                 np.ascontiguousarray(field, np.uint8), np.ascontiguousarray(kind, np.uint8),
+                 np.ascontiguousarray(arg, np.int64), meta)
+
+
+# ----------------------------------------------------------------------------
+# Key-value (YCSB-style) workloads
+# ----------------------------------------------------------------------------
+
+def kv_table(n_rows: int, n_fields: int, identity: bool = False) -> np.ndarray:
+    """Initial key-value table: value[r][f] = 16 r + f (or r when ``identity``)."""
+    r = np.arange(n_rows, dtype=np.int64)[:, None]
+    if identity:
+        return np.repeat(r, n_fields, axis=1)
+    return r * 16 + np.arange(n_fields, dtype=np.int64)[None, :]
+
+
+def kv_batch(n_rows: int, n_fields: int, n_txns: int, ops=16, read_ratio: float = 0.5,
+             theta: float = 0.0, arg_range=(-100, 100), seed: int = 0, scramble: bool = True,
+             table_id: int = 0) -> Batch:
+    """YCSB-style batch: each operation reads one field or adds a random int to it.
+
+    ``ops`` is an int (fixed length) or a (lo, hi) pair (uniform length per txn).
+    Rows are Zipf(theta) and distinct within a transaction; the field is
+    uniform; an operation is a READ with probability ``read_ratio``, else an
+    ADD whose argument is uniform on ``arg_range`` (inclusive).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if isinstance(ops, (tuple, list)):
+        lengths = rng.integers(int(ops[0]), int(ops[1]) + 1, size=n_txns, dtype=np.int64)
+    else:
+        lengths = np.full(n_txns, int(ops), dtype=np.int64)
+    total = int(lengths.sum())
+    row = _distinct_rows(rng, n_rows, theta, lengths, scramble)
+    field = rng.integers(0, n_fields, size=total, dtype=np.int64).astype(np.uint8)
+    kind = np.where(rng.random(total) < read_ratio, READ, ADD).astype(np.uint8)
+    arg = rng.integers(int(arg_range[0]), int(arg_range[1]) + 1, size=total, dtype=np.int64)
+    arg[kind == READ] = 0
+    table = np.full(total, table_id, dtype=np.uint16)
+    meta = dict(workload="kv", n_rows=n_rows, n_fields=n_fields, theta=theta, read_ratio=read_ratio,
+                seed=seed, ops=ops)
+    return _pack(lengths, row, table, field, kind, arg, meta)
+
+
+def tiny_workload(seed: int = 0):
+    """1,024 rows x 1 field (value = row id); 4,096 txns x 4 ops, 50% read / 50% +1."""
+    tab = kv_table(1024, 1, identity=True)
+    b = kv_batch(1024, 1, 4096, ops=4, read_ratio=0.5, theta=0.0, arg_range=(1, 1), seed=seed)
+    b.meta["workload"] = "tiny"
+    return [tab], b
+
+
+def kv_workload(n_rows=10_000_000, n_fields=10, n_txns=1_000_000, ops=16, read_ratio=0.5,
+                theta=0.9, seed=0, scramble=True):
+    tab = kv_table(n_rows, n_fields)
+    b = kv_batch(n_rows, n_fields, n_txns, ops=ops, read_ratio=read_ratio, theta=theta,
+                 arg_range=(-100, 100), seed=seed, scramble=scramble)
+    return [tab], b
+
+
+def hottest_row_writes(batch: Batch, table_id: int = 0) -> tuple[int, int]:
+    """(row, number of write ops) of the most written row: the serial chain length H."""
+    m = (batch.kind != READ) & (batch.table == table_id)
+    if not m.any():
+        return -1, 0
+    rows, counts = np.unique(batch.row[m], return_counts=True)
+    i = int(np.argmax(counts))
+    return int(rows[i]), int(counts[i])
+
+
+# ----------------------------------------------------------------------------
+# Order-entry (TPC-C-style NewOrder / Payment) workloads
+# ----------------------------------------------------------------------------
+
+def slot_arg(src: int, mul: int, add: int) -> int:
+    """Encode a WRITE_SLOT argument: value = read[src] * mul + add (see include/cc.h)."""
+    if not (0 <= src < 256 and -(1 << 23) <= mul < (1 << 23) and -(1 << 31) <= add < (1 << 31)):
+        raise ValueError("WRITE_SLOT argument out of range")
+    v = (src & 0xFF) | ((mul & 0xFFFFFF) << 8) | ((add & 0xFFFFFFFF) << 32)
+    if v >= 1 << 63:
+        v -= 1 << 64
+    return v
+
+
+def order_entry_tables(n_warehouses: int, n_new_orders: int, n_order_lines: int, seed: int = 0):
+    """Initial order-entry tables (int64 fixed-point cents), consistent with the invariants."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1_000_003))
+    W = n_warehouses
+    wh = np.zeros((W, OE_FIELDS[T_WAREHOUSE]), np.int64)
+    wh[:, W_TAX] = rng.integers(0, 2001, size=W)            # basis points
+    wh[:, W_YTD] = INIT_W_YTD
+    di = np.zeros((W * DISTRICTS_PER_W, OE_FIELDS[T_DISTRICT]), np.int64)
+    di[:, D_TAX] = rng.integers(0, 2001, size=len(di))
+    di[:, D_YTD] = INIT_D_YTD
+    di[:, D_NEXT_O_ID] = INIT_NEXT_O_ID
+    nc = W * DISTRICTS_PER_W * CUSTOMERS_PER_D
+    cu = np.zeros((nc, OE_FIELDS[T_CUSTOMER]), np.int64)
+    cu[:, C_DISCOUNT] = rng.integers(0, 5001, size=nc)
+    cu[:, C_BALANCE] = INIT_C_BALANCE
+    cu[:, C_YTD_PAYMENT] = 1_000
+    cu[:, C_PAYMENT_CNT] = 1
+    it = np.zeros((N_ITEMS, OE_FIELDS[T_ITEM]), np.int64)
+    it[:, I_PRICE] = rng.integers(100, 10_001, size=N_ITEMS)
+    st = np.zeros((W * STOCK_PER_W, OE_FIELDS[T_STOCK]), np.int64)
+    st[:, S_QUANTITY] = rng.integers(INIT_S_QUANTITY_RANGE[0], INIT_S_QUANTITY_RANGE[1] + 1, size=len(st))
+    od = np.zeros((max(n_new_orders, 1), OE_FIELDS[T_ORDER]), np.int64)
+    ol = np.zeros((max(n_order_lines, 1), OE_FIELDS[T_ORDER_LINE]), np.int64)
+    return [wh, di, cu, it, st, od, ol]
+
+
+def order_entry_workload(n_warehouses: int, n_txns: int, seed: int = 0, new_order_frac: float = 0.5,
+                         remote_stock_p: float = 0.01, remote_customer_p: float = 0.15,
+                         lines=(5, 15), quantity=(1, 8), amount=(1, 100_000)):
+    """TPC-C-style NewOrder / Payment mix over seven tables.
+
+    NewOrder (per transaction, in program order): read warehouse tax; read
+    district tax and add 1 to its next order id (the pre-image is the order
+    id); read the customer discount; per line read the item price and update
+    the stock row (quantity by the replenishing conditional add, ytd, order
+    count, remote count); then fill the transaction's own pre-assigned order
+    slot and order-line slots from values read earlier (no inserts).
+    Payment: add the amount to warehouse ytd and district ytd; subtract it
+    from the customer's balance and add it to ytd-payment, payment count +1.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    W = int(n_warehouses)
+    is_no = rng.random(n_txns) < new_order_frac
+    n_no = int(is_no.sum())
+    n_lines = np.zeros(n_txns, np.int64)
+    n_lines[is_no] = rng.integers(lines[0], lines[1] + 1, size=n_no)
+    total_lines = int(n_lines.sum())
+    lengths, row, table, field, kind, arg = [], [], [], [], [], []
+    order_slot = 0
+    line_slot = 0
+    for t in range(n_txns):
+        r, tb, fl, kd, ag = [], [], [], [], []
+
+        def op(tab, rw, fld, k, a=0):
+            r.append(rw); tb.append(tab); fl.append(fld); kd.append(k); ag.append(a)
+
+        w = int(rng.integers(0, W))
+        d = int(rng.integers(0, DISTRICTS_PER_W))
+        drow = w * DISTRICTS_PER_W + d
+        if is_no[t]:
+            c = int(rng.integers(0, CUSTOMERS_PER_D))
+            crow = drow * CUSTOMERS_PER_D + c
+            nl = int(n_lines[t])
+            items = rng.choice(N_ITEMS, size=nl, replace=False)
+            remote = rng.random(nl) < remote_stock_p
+            qty = rng.integers(quantity[0], quantity[1] + 1, size=nl)
+            op(T_WAREHOUSE, w, W_TAX, READ)
+            op(T_DISTRICT, drow, D_TAX, READ)
+            src_oid = len(r)
+            op(T_DISTRICT, drow, D_NEXT_O_ID, ADD, 1)
+            op(T_CUSTOMER, crow, C_DISCOUNT, READ)
+            price_src = []
+            for l in range(nl):
+                sw = w
+                if remote[l] and W > 1:
+                    sw = int(rng.integers(0, W - 1))
+                    sw = sw + 1 if sw >= w else sw
+                price_src.append(len(r))
+                op(T_ITEM, int(items[l]), I_PRICE, READ)
+                srow = sw * STOCK_PER_W + int(items[l])
+                op(T_STOCK, srow, S_QUANTITY, COND_ADD, -int(qty[l]))
+                op(T_STOCK, srow, S_YTD, ADD, int(qty[l]))
+                op(T_STOCK, srow, S_ORDER_CNT, ADD, 1)
+                if sw != w:
+                    op(T_STOCK, srow, S_REMOTE_CNT, ADD, 1)
+            op(T_ORDER, order_slot, O_ID, WRITE_SLOT, slot_arg(src_oid, 1, 0))
+            op(T_ORDER, order_slot, O_C_ID, WRITE_SLOT, slot_arg(0, 0, crow))
+            op(T_ORDER, order_slot, O_OL_CNT, WRITE_SLOT, slot_arg(0, 0, nl))
+            order_slot += 1
+            for l in range(nl):
+                op(T_ORDER_LINE, line_slot, OL_AMOUNT, WRITE_SLOT, slot_arg(price_src[l], int(qty[l]), 0))
+                op(T_ORDER_LINE, line_slot, OL_QUANTITY, WRITE_SLOT, slot_arg(0, 0, int(qty[l])))
+                line_slot += 1
+        else:
+            h = int(rng.integers(amount[0], amount[1] + 1))
+            if rng.random() < remote_customer_p:
+                if W > 1:
+                    cw = int(rng.integers(0, W - 1))
+                    cw = cw + 1 if cw >= w else cw
+                    cd = int(rng.integers(0, DISTRICTS_PER_W))
+                else:
+                    cw = w
+                    cd = int(rng.integers(0, DISTRICTS_PER_W - 1))
+                    cd = cd + 1 if cd >= d else cd
+            else:
+                cw, cd = w, d
+            c = int(rng.integers(0, CUSTOMERS_PER_D))
+            crow = (cw * DISTRICTS_PER_W + cd) * CUSTOMERS_PER_D + c
+            op(T_WAREHOUSE, w, W_YTD, ADD, h)
+            op(T_DISTRICT, drow, D_YTD, ADD, h)
+            op(T_CUSTOMER, crow, C_BALANCE, ADD, -h)
+            op(T_CUSTOMER, crow, C_YTD_PAYMENT, ADD, h)
+            op(T_CUSTOMER, crow, C_PAYMENT_CNT, ADD, 1)
+        lengths.append(len(r))
+        row += r; table += tb; field += fl; kind += kd; arg += ag
+    tables = order_entry_tables(W, order_slot, line_slot, seed)
+    meta = dict(workload="order_entry", n_warehouses=W, seed=seed, n_new_orders=order_slot,
+                n_order_lines=line_slot, is_new_order=is_no)
+    b = _pack(lengths, np.array(row, np.int64), np.array(table, np.int64), np.array(field, np.int64),
+              np.array(kind, np.int64), np.array(arg, np.int64), meta)
+    return tables, b

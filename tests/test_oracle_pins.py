@@ -1,0 +1,198 @@
+"""Pins for the CPU oracle: checks against facts that do not come from the oracle itself.
+
+* hand-worked serial executions (tests/golden/hand_schedules.json);
+* the order-free closed form of add-only batches (numpy, independent of the C replay);
+* closed forms of read-only and disjoint-key batches (every read is the initial value 16 r + f);
+* brute force: a set of mutually disjoint transactions matches all k! orders, classic
+  non-serializable outcomes (lost update, write skew) match none;
+* planted errors in a run's outcome are detected by ``check_run``;
+* order-entry invariants hold on a serial execution and catch a perturbed table.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_10158_amd import workload as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_schedules.json")
+
+
+def _batch_from_json(txns):
+    row, table, field, kind, arg, lengths = [], [], [], [], [], []
+    for ops in txns:
+        lengths.append(len(ops))
+        for (t, r, f, k, a) in ops:
+            table.append(t); row.append(r); field.append(f); kind.append(k)
+            arg.append(wl.slot_arg(a["src"], a["mul"], a["add"]) if isinstance(a, dict) else a)
+    return wl._pack(lengths, np.array(row, np.int64), np.array(table, np.int64), np.array(field, np.int64),
+                    np.array(kind, np.int64), np.array(arg, dtype=object).astype(np.int64), {})
+
+
+def _tables(js):
+    return [np.array(t, dtype=np.int64) for t in js]
+
+
+def _golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("case", _golden()["replays"], ids=lambda c: c["name"])
+def test_hand_worked_replays(case):
+    tabs = _tables(case["tables"])
+    b = _batch_from_json(case["txns"])
+    for c in case["cases"]:
+        fin, reads = oracle.replay(tabs, b, c["order"])
+        assert reads.tolist() == c["reads"], c["order"]
+        for got, exp in zip(fin, c["final"]):
+            assert got.tolist() == exp
+    # inputs are not modified by the replay
+    assert all(np.array_equal(a, b_) for a, b_ in zip(tabs, _tables(case["tables"])))
+
+
+@pytest.mark.parametrize("case", _golden()["bruteforce"], ids=lambda c: c["name"])
+def test_bruteforce_hand_outcomes(case):
+    tabs = _tables(case["tables"])
+    b = _batch_from_json(case["txns"])
+    for o in case["outcomes"]:
+        n = oracle.bruteforce_count(tabs, b, np.arange(b.n_txns), np.array(o["reads"], np.int64),
+                                    _tables(o["final"]))
+        assert n == o["orders"], o
+
+
+def test_add_only_closed_form_matches_replay_in_any_order():
+    tabs, b = wl.kv_workload(n_rows=500, n_fields=3, n_txns=2000, ops=8, theta=0.9, seed=3)
+    cf = oracle.final_add_only(tabs, b)
+    fin_id, reads_id = oracle.serial_execute(tabs, b)
+    rng = np.random.default_rng(7)
+    fin_perm, reads_perm = oracle.replay(tabs, b, rng.permutation(b.n_txns))
+    assert np.array_equal(cf[0], fin_id[0])
+    assert np.array_equal(cf[0], fin_perm[0])
+    # the closed form is not trivially the initial table, and reads depend on the order
+    assert not np.array_equal(cf[0], tabs[0])
+    assert not np.array_equal(reads_id, reads_perm)
+
+
+def test_closed_form_respects_committed_mask():
+    tabs, b = wl.kv_workload(n_rows=50, n_fields=2, n_txns=40, ops=4, theta=0.0, seed=1)
+    committed = np.zeros(b.n_txns, bool)
+    committed[::2] = True
+    order = np.nonzero(committed)[0]
+    fin, _ = oracle.replay(tabs, b, order)
+    assert np.array_equal(oracle.final_add_only(tabs, b, committed)[0], fin[0])
+
+
+def test_read_only_batch_reads_initial_values():
+    tabs, b = wl.kv_workload(n_rows=1000, n_fields=10, n_txns=3000, ops=16, read_ratio=1.0, theta=0.99, seed=2)
+    fin, reads = oracle.serial_execute(tabs, b)
+    assert np.array_equal(reads, 16 * b.row.astype(np.int64) + b.field.astype(np.int64))
+    assert np.array_equal(fin[0], tabs[0])
+
+
+def test_disjoint_transactions_read_initial_values_in_any_order():
+    n_txn, ops = 64, 4
+    rows = np.random.default_rng(5).permutation(n_txn * ops).astype(np.uint32)
+    b = wl.kv_batch(n_txn * ops, 2, n_txn, ops=ops, seed=4)
+    b.row[:] = rows  # every row used by exactly one transaction
+    tabs = [wl.kv_table(n_txn * ops, 2)]
+    init_vals = 16 * b.row.astype(np.int64) + b.field.astype(np.int64)
+    for order in (np.arange(n_txn), np.arange(n_txn)[::-1].copy()):
+        fin, reads = oracle.replay(tabs, b, order)
+        assert np.array_equal(reads, init_vals)
+        assert np.array_equal(fin[0], oracle.final_add_only(tabs, b)[0])
+
+
+def test_bruteforce_counts_every_order_of_commuting_transactions():
+    # five transactions on five disjoint rows: all 5! orders reproduce the serial outcome
+    b = wl.kv_batch(5, 1, 5, ops=1, read_ratio=0.0, arg_range=(1, 9), seed=0)
+    b.row[:] = np.arange(5, dtype=np.uint32)
+    tabs = [wl.kv_table(5, 1)]
+    fin, reads = oracle.serial_execute(tabs, b)
+    assert oracle.bruteforce_count(tabs, b, np.arange(5), reads, fin) == math.factorial(5)
+
+
+def test_bruteforce_finds_exactly_the_serial_orders_on_a_random_tiny_batch():
+    tabs, b = wl.kv_workload(n_rows=3, n_fields=1, n_txns=6, ops=2, theta=0.0, seed=11)
+    for seed in range(5):
+        order = np.random.default_rng(seed).permutation(6)
+        fin, reads = oracle.replay(tabs, b, order)
+        n = oracle.bruteforce_count(tabs, b, np.arange(6), reads, fin)
+        assert 1 <= n <= math.factorial(6)
+        # a read value off by one is reproduced by no order
+        bad = reads.copy()
+        bad[3] += 1
+        assert oracle.bruteforce_count(tabs, b, np.arange(6), bad, fin) == 0
+
+
+def _fake_run(tabs, b, order):
+    """Outcome arrays of a correct run that committed everything in ``order``."""
+    fin, reads = oracle.replay(tabs, b, order)
+    status = np.full(b.n_txns, oracle.COMMITTED, np.uint32)
+    lo = np.zeros(b.n_txns, np.uint64)
+    lo[np.asarray(order)] = np.arange(1, b.n_txns + 1, dtype=np.uint64) * 3  # gaps are fine
+    return status, np.zeros(b.n_txns, np.uint64), lo, reads, fin
+
+
+def test_check_run_accepts_a_correct_run_and_flags_planted_errors():
+    tabs, b = wl.kv_workload(n_rows=200, n_fields=4, n_txns=500, ops=8, theta=0.9, seed=9)
+    order = np.random.default_rng(1).permutation(b.n_txns)
+    status, hi, lo, reads, fin = _fake_run(tabs, b, order)
+    assert oracle.check_run(tabs, b, status, hi, lo, reads, fin).ok
+
+    r2 = reads.copy(); r2[17] += 1
+    rep = oracle.check_run(tabs, b, status, hi, lo, r2, fin)
+    assert not rep.ok and rep.read_mismatches == 1
+
+    f2 = [fin[0].copy()]; f2[0][5, 2] -= 1
+    rep = oracle.check_run(tabs, b, status, hi, lo, reads, f2)
+    assert not rep.ok and rep.table_mismatches == 1 and rep.closed_form_ok is False
+
+    lo2 = lo.copy(); lo2[order[1]] = lo2[order[0]]
+    assert not oracle.check_run(tabs, b, status, hi, lo2, reads, fin).ok
+
+    s2 = status.copy(); s2[3] = 0
+    assert not oracle.check_run(tabs, b, s2, hi, lo, reads, fin).ok
+
+    # a valid order that is not the one reported: reads disagree with the reported order
+    lo3 = lo.copy(); lo3[order[0]], lo3[order[-1]] = lo[order[-1]], lo[order[0]]
+    assert not oracle.check_run(tabs, b, status, hi, lo3, reads, fin).ok
+
+
+def test_serial_order_uses_hi_then_lo():
+    st = np.ones(4, np.uint32)
+    hi = np.array([2, 1, 1, 0], np.uint64)
+    lo = np.array([0, 9, 3, 100], np.uint64)
+    assert oracle.serial_order(st, hi, lo).tolist() == [3, 2, 1, 0]
+
+
+def test_order_entry_invariants_on_serial_execution():
+    tabs, b = wl.order_entry_workload(2, 300, seed=5)
+    fin, _ = oracle.serial_execute(tabs, b)
+    committed = np.ones(b.n_txns, bool)
+    assert oracle.order_entry_invariants(tabs, fin, b, committed) == []
+    bad = [t.copy() for t in fin]
+    bad[wl.T_WAREHOUSE][0, wl.W_YTD] += 1
+    assert oracle.order_entry_invariants(tabs, bad, b, committed)
+    bad = [t.copy() for t in fin]
+    bad[wl.T_STOCK][0, wl.S_ORDER_CNT] += 1
+    assert oracle.order_entry_invariants(tabs, bad, b, committed)
+
+
+def test_order_entry_slot_values_follow_district_counter():
+    tabs, b = wl.order_entry_workload(1, 60, seed=2)
+    fin, reads = oracle.serial_execute(tabs, b)
+    # in id order the k-th committed new-order of a district gets order id INIT_NEXT_O_ID + k
+    o_ids = fin[wl.T_ORDER][:b.meta["n_new_orders"], wl.O_ID]
+    assert o_ids.min() >= wl.INIT_NEXT_O_ID
+    per_d = {}
+    for t in range(b.n_txns):
+        s = b.txn_slice(t)
+        m = (b.table[s] == wl.T_DISTRICT) & (b.field[s] == wl.D_NEXT_O_ID)
+        if m.any():
+            d = int(b.row[s][m][0])
+            per_d[d] = per_d.get(d, 0) + 1
+            assert int(reads[s][m][0]) == wl.INIT_NEXT_O_ID + per_d[d] - 1

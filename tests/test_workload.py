@@ -1,0 +1,93 @@
+"""Generator properties: determinism, distinct rows per transaction, Zipf frequencies, shapes."""
+import numpy as np
+
+from paper_2406_10158_amd import workload as wl
+
+
+def test_same_seed_same_bytes():
+    a = wl.kv_batch(10_000, 10, 2_000, ops=16, theta=0.9, seed=0)
+    b = wl.kv_batch(10_000, 10, 2_000, ops=16, theta=0.9, seed=0)
+    c = wl.kv_batch(10_000, 10, 2_000, ops=16, theta=0.9, seed=1)
+    for k in ("row", "field", "kind", "arg", "first_op", "n_ops"):
+        assert np.array_equal(getattr(a, k), getattr(b, k))
+    assert not np.array_equal(a.row, c.row)
+
+
+def test_rows_distinct_within_each_transaction():
+    b = wl.kv_batch(1_000, 10, 5_000, ops=(2, 64), theta=0.99, seed=3)
+    for t in range(0, b.n_txns, 7):
+        r = b.row[b.txn_slice(t)]
+        assert len(np.unique(r)) == len(r)
+    assert b.n_ops.min() >= 2 and b.n_ops.max() <= 64
+    assert int(b.first_op[-1]) + int(b.n_ops[-1]) == b.total_ops
+
+
+def test_zipf_hottest_rank_frequency_matches_closed_form():
+    n, theta, size = 1000, 0.9, 400_000
+    rng = np.random.Generator(np.random.PCG64(0))
+    keys = wl.draw_keys(rng, n, theta, size, scramble=False)
+    p1 = 1.0 / sum(r ** -theta for r in range(1, n + 1))
+    f1 = np.mean(keys == 0)
+    assert abs(f1 - p1) < 5 * np.sqrt(p1 * (1 - p1) / size)
+    p2 = 2 ** -theta * p1
+    assert abs(np.mean(keys == 1) - p2) < 5 * np.sqrt(p2 / size)
+
+
+def test_uniform_when_theta_zero_and_scramble_is_a_bijection():
+    n = 10_007 * 3
+    a = wl.scramble_multiplier(n)
+    rows = (np.arange(n, dtype=np.uint64) * np.uint64(a)) % np.uint64(n)
+    assert len(np.unique(rows)) == n
+    rng = np.random.Generator(np.random.PCG64(1))
+    k = wl.draw_keys(rng, 100, 0.0, 200_000)
+    counts = np.bincount(k, minlength=100)
+    assert counts.min() > 1700 and counts.max() < 2300
+
+
+def test_read_ratio_and_arg_range():
+    b = wl.kv_batch(100_000, 10, 20_000, ops=16, read_ratio=0.5, theta=0.6, seed=0)
+    frac_read = np.mean(b.kind == wl.READ)
+    assert abs(frac_read - 0.5) < 0.01
+    adds = b.arg[b.kind == wl.ADD]
+    assert adds.min() == -100 and adds.max() == 100
+    assert np.all(b.arg[b.kind == wl.READ] == 0)
+    assert b.field.max() == 9
+
+
+def test_tiny_workload_shape():
+    (tab,), b = wl.tiny_workload()
+    assert tab.shape == (1024, 1) and np.array_equal(tab[:, 0], np.arange(1024))
+    assert b.n_txns == 4096 and b.total_ops == 4096 * 4
+    assert set(np.unique(b.arg[b.kind == wl.ADD])) == {1}
+
+
+def test_order_entry_shape():
+    tabs, b = wl.order_entry_workload(8, 400, seed=0)
+    assert [t.shape[1] for t in tabs] == list(wl.OE_FIELDS)
+    assert tabs[wl.T_STOCK].shape[0] == 8 * wl.STOCK_PER_W
+    is_no = b.meta["is_new_order"]
+    assert 0.4 < is_no.mean() < 0.6
+    # ops on the same (table,row) are adjacent, and no (table,row,field) repeats within a txn
+    for t in range(b.n_txns):
+        s = b.txn_slice(t)
+        keys = list(zip(b.table[s].tolist(), b.row[s].tolist()))
+        seen = set()
+        prev = None
+        for k in keys:
+            if k != prev:
+                assert k not in seen
+                seen.add(k)
+            prev = k
+        cells = list(zip(b.table[s].tolist(), b.row[s].tolist(), b.field[s].tolist()))
+        assert len(set(cells)) == len(cells)
+    # warehouse ytd equals the sum of district ytd initially
+    assert np.array_equal(tabs[wl.T_WAREHOUSE][:, wl.W_YTD],
+                          tabs[wl.T_DISTRICT][:, wl.D_YTD].reshape(8, 10).sum(1))
+
+
+def test_hottest_row_chain_length_grows_with_theta():
+    hs = []
+    for th in (0.0, 0.6, 0.9, 0.99):
+        b = wl.kv_batch(100_000, 10, 20_000, ops=16, theta=th, seed=0)
+        hs.append(wl.hottest_row_writes(b)[1])
+    assert hs == sorted(hs) and hs[-1] > 20 * hs[0]
