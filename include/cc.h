@@ -1,0 +1,258 @@
+/*
+ * cc.h -- C-ABI of the MI355X (gfx950) batch transaction engine.
+ *
+ * The engine executes a batch of read / read-modify-write transactions
+ * concurrently against tables resident in device memory (HBM), under one of
+ * five concurrency-control schemes, and reports per transaction a serial key
+ * that orders the committed transactions into an equivalent serial execution.
+ *
+ * Problem statement followed (paper Section 4.1, "Constraints" and
+ * "Experimental Procedure"): tables and transactions are in device memory
+ * before execution; transactions only read and write existing tuples (no
+ * insert or delete); every transaction's read and write set is fixed before
+ * execution; each transaction is restarted after a conflict until it
+ * commits; all schemes guarantee serializable isolation (Section 3, "CC
+ * Schemes Migration and Implementation").  The batch execution model with one
+ * worker per transaction is Section 3.3 ("An Overview").
+ *
+ * Conventions for every call:
+ *   - Return value: CC_OK (0) or a negative cc_status; no call throws, aborts
+ *     or exits.  cc_strerror() names a status, cc_last_error() gives the
+ *     message of the last failing call on a context.
+ *   - Pointers named *_host are host memory; a flag argument `on_device`
+ *     switches an array argument to a device pointer (for example a
+ *     torch.Tensor.data_ptr() on the context's device).  The caller owns every
+ *     array it passes; the engine copies inputs before the call returns and
+ *     never keeps a caller pointer.
+ *   - A context is used by one host thread at a time.  Work is issued on the
+ *     stream given at cc_init (the default stream if NULL); calls that return
+ *     results synchronise that stream.
+ *   - All table values are int64; arithmetic wraps in two's complement.
+ */
+#ifndef CC_H_
+#define CC_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cc_ctx cc_ctx;
+typedef int32_t cc_status;
+
+/* Status codes. */
+#define CC_OK 0
+#define CC_E_INVAL (-1)       /* malformed argument, unknown scheme/kind, bad run parameter */
+#define CC_E_RANGE (-2)       /* table, row or field out of range; size limit exceeded */
+#define CC_E_DUPROW (-3)      /* a (table,row) repeats non-adjacently, or a (table,row,field) repeats, within a txn */
+#define CC_E_NOMEM (-4)       /* device or host allocation failed */
+#define CC_E_TS_OVERFLOW (-5) /* a scheme's timestamp field would overflow; the run is invalid */
+#define CC_E_LIVELOCK (-6)    /* transactions still pending after max_attempts / max_epochs */
+#define CC_E_HIP (-7)         /* HIP runtime error (message in cc_last_error) */
+#define CC_E_NODEV (-8)       /* no usable gfx950 device */
+#define CC_E_STATE (-9)       /* call out of order (e.g. cc_create_table after the first cc_load) */
+#define CC_E_NOBATCH (-10)    /* unknown batch id */
+
+/* Concurrency-control schemes (paper Section 2 and Table 2; Section 3.5). */
+enum cc_scheme {
+  CC_OCC = 0,    /* Silo-style optimistic CC: lock bit + 63-bit TID per row */
+  CC_2PL_NW = 1, /* two-phase locking, no-wait */
+  CC_TO = 2,     /* basic timestamp ordering: commit bit + 31-bit RTS + 31-bit WTS */
+  CC_MVCC = 3,   /* multi-version timestamp ordering (TO word + version pointer) */
+  CC_TICTOC = 4  /* TicToc: lock bit + 15-bit delta + 48-bit WTS */
+};
+#define CC_N_SCHEMES 5
+
+/*
+ * Operation kinds.  An operation touches one field of one row.  Its read
+ * value (reported by cc_fetch_outcomes) is always the field's value before
+ * the operation (the pre-image).
+ *   CC_READ       no change.
+ *   CC_ADD        value + arg.
+ *   CC_COND_ADD   v = value + arg; if v < CC_COND_LO then v += CC_COND_HI
+ *                 (the stock-replenishing update of TPC-C NewOrder, a
+ *                 workload the paper evaluates in Section 4.1).
+ *   CC_WRITE_SLOT value := read[src] * mul + add, where read[src] is the read
+ *                 value of operation `src` (an index within the same
+ *                 transaction, smaller than this operation's index).  arg
+ *                 packs src in bits 0-7, mul as a signed 24-bit integer in
+ *                 bits 8-31 and add as a signed 32-bit integer in bits 32-63.
+ * Within a transaction all operations on one (table,row) must be adjacent and
+ * a (table,row,field) may appear at most once (else CC_E_DUPROW); the row
+ * group is one row access for concurrency control.
+ */
+enum cc_op_kind { CC_READ = 0, CC_ADD = 1, CC_COND_ADD = 2, CC_WRITE_SLOT = 3 };
+#define CC_COND_LO 10
+#define CC_COND_HI 91
+
+/* Limits. */
+#define CC_MAX_OPS_PER_TXN 256
+#define CC_MAX_TABLES 16
+#define CC_MAX_TOTAL_ROWS (1ull << 28)   /* summed over all tables */
+#define CC_MAX_TOTAL_CELLS (1ull << 32)  /* summed rows x fields over all tables */
+
+typedef struct {
+  uint32_t row;   /* row index within the table */
+  uint16_t table; /* table id from cc_create_table */
+  uint8_t field;  /* field index within the row */
+  uint8_t kind;   /* enum cc_op_kind */
+  int64_t arg;
+} cc_op; /* 16 bytes */
+
+typedef struct {
+  uint64_t first_op; /* index of the transaction's first op in the ops array */
+  uint32_t n_ops;    /* number of ops, 0..CC_MAX_OPS_PER_TXN */
+  uint32_t reserved; /* must be 0 */
+} cc_txn; /* 16 bytes */
+
+enum cc_txn_status { CC_PENDING = 0, CC_COMMITTED = 1 };
+
+/*
+ * Per-transaction outcome.  Sorting committed transactions by
+ * (serial_hi, serial_lo) gives a serial order equivalent to the run:
+ *   OCC, 2PL:  (0, ticket)  -- ticket drawn from one device counter while the
+ *                              transaction holds all its write locks;
+ *   TO, MVCC:  (0, ts)      -- the timestamp of the committing attempt;
+ *   TicToc:    (commit_ts, ticket).
+ * attempts counts executions of the transaction, so attempts-1 are aborts
+ * (the paper's abort rate is aborts / committed, Section 4.1 "Metric
+ * Selection").  commit_ns is the device wall-clock time of the commit,
+ * relative to the start of the run (CC initialisation).
+ */
+typedef struct {
+  uint32_t status;
+  uint32_t attempts;
+  uint64_t serial_hi;
+  uint64_t serial_lo;
+  int64_t commit_ns;
+} cc_outcome; /* 32 bytes */
+
+typedef struct {
+  int32_t device;  /* HIP device ordinal */
+  uint32_t flags;  /* must be 0 */
+  void *stream;    /* hipStream_t to issue work on (NULL: the null stream) */
+} cc_config;
+
+enum cc_mode { CC_MODE_PLAIN = 0, CC_MODE_EPOCH = 1 };
+
+/* Run flags. */
+#define CC_RUN_STRICT_FENCES 0x1u /* agent-scope acquire/release fences (cache invalidate/write-back) at
+                                     every ordering point instead of wait-for-completion only */
+
+typedef struct {
+  uint32_t lanes_per_txn; /* lanes cooperating on one transaction: 1, 4, 16, 64; 0 = smallest >= longest txn */
+  uint32_t waves_per_wg;  /* 64-lane wavefronts per workgroup, 1..16; 0 = 4 */
+  uint32_t grid;          /* workgroups launched; 0 = enough to fill every compute unit */
+  uint32_t mode;          /* enum cc_mode */
+  uint64_t max_attempts;  /* give up (CC_E_LIVELOCK) after this many attempts of one txn; 0 = 1<<24 */
+  uint32_t max_epochs;    /* CC_MODE_EPOCH: epochs before CC_E_LIVELOCK; 0 = 1<<20 */
+  uint32_t flags;         /* CC_RUN_* */
+  uint32_t backoff_ns;    /* base of the randomised exponential back-off after an abort; 0 = 200 ns */
+  uint32_t reserved;
+} cc_run_params;
+
+/* Counters reported by cc_stats (index: meaning). */
+enum cc_stat {
+  CC_STAT_COMMITTED = 0,   /* committed transactions */
+  CC_STAT_ATTEMPTS = 1,    /* transaction executions (commits + aborts) */
+  CC_STAT_ABORT_LOCK = 2,  /* aborts: a lock / word was held by another transaction */
+  CC_STAT_ABORT_VALID = 3, /* aborts: a read was invalidated, or a timestamp rule failed */
+  CC_STAT_KERNEL_NS = 4,   /* execution time of the transaction kernel(s), HIP events */
+  CC_STAT_RUN_NS = 5,      /* CC initialisation + execution (the paper's measured window) */
+  CC_STAT_TICKETS = 6,     /* serial tickets / timestamps drawn */
+  CC_STAT_MAX_ATTEMPTS = 7,/* largest attempts of one transaction */
+  CC_STAT_LAT_P50_NS = 8,  /* commit latency percentiles over the batch (commit_ns) */
+  CC_STAT_LAT_P99_NS = 9,
+  CC_STAT_EPOCHS = 10,     /* epochs run (CC_MODE_EPOCH) */
+  CC_N_STATS = 16
+};
+
+/* Library version and self-description. */
+const char *cc_version(void);
+const char *cc_strerror(cc_status status);
+const char *cc_last_error(const cc_ctx *ctx);
+
+/*
+ * Create a context on cfg->device (which must be a gfx950 GPU) issuing work
+ * on cfg->stream.  *out receives the context, or NULL on error.
+ */
+cc_status cc_init(cc_ctx **out, const cc_config *cfg);
+
+/* Free every device and host resource of the context.  NULL is accepted. */
+cc_status cc_destroy(cc_ctx *ctx);
+
+/*
+ * Declare a table of n_rows x n_fields int64 values (row store, paper
+ * Section 3.4 "DBMS Building Blocks": a table is an array of tuples of fixed
+ * size; all tables are laid out consecutively and share one row-id space).
+ * Tables must be declared before the first cc_load; *table_id receives
+ * 0, 1, 2, ... in declaration order.
+ */
+cc_status cc_create_table(cc_ctx *ctx, uint64_t n_rows, uint32_t n_fields, uint32_t *table_id);
+
+/*
+ * Copy n_rows x n_fields values (row-major) into a table.  n_rows must equal
+ * the table's row count.  rows is a host pointer, or a device pointer when
+ * rows_on_device is non-zero (device-to-device copy, e.g. a pristine copy
+ * kept in a torch tensor).  The first cc_load freezes the set of tables.
+ */
+cc_status cc_load(cc_ctx *ctx, uint32_t table_id, const int64_t *rows, uint64_t n_rows, int rows_on_device);
+
+/* Copy a table's current contents out (row-major), to host or device memory. */
+cc_status cc_read_table(cc_ctx *ctx, uint32_t table_id, int64_t *out, int out_on_device);
+
+/*
+ * Validate a batch of n_txns transactions over n_ops operations and stage it
+ * in device memory for `scheme`.  txns/ops are host arrays (on_device = 0).
+ * Errors: CC_E_INVAL (bad scheme/kind, op ranges outside the ops array,
+ * WRITE_SLOT source not earlier, too many ops in a txn), CC_E_RANGE,
+ * CC_E_DUPROW.  *batch_id receives a handle valid until cc_release_batch or
+ * cc_destroy.  Zero transactions is a valid (empty) batch.
+ */
+cc_status cc_submit_batch(cc_ctx *ctx, const cc_txn *txns, uint64_t n_txns, const cc_op *ops, uint64_t n_ops,
+                          int scheme, int on_device, uint64_t *batch_id);
+
+/*
+ * Host-only validation of a batch against table shapes (n_tables tables of
+ * n_rows[t] x n_fields[t]), with exactly the checks cc_submit_batch applies.
+ * Touches no device; usable without a GPU.  Returns CC_OK or the status
+ * cc_submit_batch would return for the same arrays.
+ */
+cc_status cc_check_batch(uint32_t n_tables, const uint64_t *n_rows, const uint32_t *n_fields, const cc_txn *txns,
+                         uint64_t n_txns, const cc_op *ops, uint64_t n_ops, int scheme);
+
+/*
+ * Execute a submitted batch and block until it finishes.  The run resets the
+ * scheme's control words (CC initialisation, inside the measured window as in
+ * the paper's throughput definition, Section 4.1 "Metric Selection") and then
+ * runs every transaction until it commits.  A batch may be run repeatedly;
+ * each run applies its writes to the current tables.
+ * params may be NULL (all defaults).  Returns CC_E_LIVELOCK if a transaction
+ * exhausted max_attempts (its status stays CC_PENDING and it left no writes),
+ * CC_E_TS_OVERFLOW if a timestamp field overflowed.
+ */
+cc_status cc_run(cc_ctx *ctx, uint64_t batch_id, const cc_run_params *params);
+
+/*
+ * Copy the last run's per-transaction outcomes (n_txns entries) and per-op
+ * read values (n_ops entries, indexed like the submitted ops array) out.
+ * Either pointer may be NULL.  dst_on_device selects device destinations.
+ */
+cc_status cc_fetch_outcomes(cc_ctx *ctx, uint64_t batch_id, cc_outcome *per_txn, int64_t *per_op_read,
+                            int dst_on_device);
+
+/* Copy up to n counters (enum cc_stat order) of the batch's last run. */
+cc_status cc_stats(cc_ctx *ctx, uint64_t batch_id, uint64_t *counters, uint32_t n);
+
+/* Free a batch's device buffers. */
+cc_status cc_release_batch(cc_ctx *ctx, uint64_t batch_id);
+
+/* Device properties the engine uses: compute units, wall-clock rate (kHz). */
+cc_status cc_device_info(cc_ctx *ctx, uint32_t *n_cu, uint32_t *wallclock_khz);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CC_H_ */

@@ -161,7 +161,7 @@ int64_t oracle_bruteforce(uint32_t n_tables, const uint64_t *n_rows, const uint3
   int64_t *reads = (int64_t *)malloc((total_ops ? total_ops : 1) * sizeof(int64_t));
   if (!work || !reads) { free(work); free(reads); return E_NOMEM; }
   for (uint32_t t = 0; t < n_tables; ++t) {
-    work[t] = (int64_t *)malloc((n_rows[t] * n_fields[t] ? n_rows[t] * n_fields[t] : 1) * sizeof(int64_t));
+    work[t] = (int64_t *)malloc((n_rows[t] * n_fields[t] > 0 ? n_rows[t] * n_fields[t] : 1) * sizeof(int64_t));
     if (!work[t]) { for (uint32_t u = 0; u < t; ++u) free(work[u]); free(work); free(reads); return E_NOMEM; }
   }
   int64_t perm[8];

@@ -1,0 +1,530 @@
+// C-ABI of the batch transaction engine: context, tables, batches, runs.
+// Declarations and the contract of every call are in include/cc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+
+using namespace cce;
+
+namespace {
+
+struct Table {
+  uint64_t n_rows;
+  uint32_t n_fields;
+  uint64_t row_base;   // first global row id
+  uint64_t elem_base;  // first cell in the value arena
+};
+
+struct Batch {
+  int scheme = 0;
+  uint64_t n_txns = 0, n_ops = 0;
+  uint32_t max_ops = 0;
+  bool has_slot = false;
+  DevOp *d_ops = nullptr;
+  DevTxn *d_txns = nullptr;
+  DevOutcome *d_out = nullptr;
+  int64_t *d_reads = nullptr;
+  bool ran = false;
+  uint64_t stats[CC_N_STATS] = {};
+};
+
+}  // namespace
+
+struct cc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int n_cu = 0;
+  uint32_t wallclock_khz = 0;
+  std::vector<Table> tables;
+  bool frozen = false;
+  uint64_t total_rows = 0, total_cells = 0;
+  int64_t *d_data = nullptr;
+  uint64_t *d_words = nullptr;
+  uint64_t *d_aux = nullptr;
+  Ctl *d_ctl = nullptr;
+  std::map<uint64_t, Batch> batches;
+  uint64_t next_batch = 1;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_init_err;
+
+cc_status fail(cc_ctx *c, cc_status st, const std::string &msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+cc_status hip_fail(cc_ctx *c, hipError_t e, const char *what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return fail(c, CC_E_NOMEM, m);
+  return fail(c, CC_E_HIP, m);
+}
+
+#define HIP_OR(ctx, call)                              \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+  } while (0)
+
+bool activate(cc_ctx *c) { return hipSetDevice(c->device) == hipSuccess; }
+
+cc_status freeze(cc_ctx *c) {
+  if (c->frozen) return CC_OK;
+  if (c->tables.empty()) return fail(c, CC_E_STATE, "no tables declared");
+  uint64_t rows = 0, cells = 0;
+  for (auto &t : c->tables) {
+    t.row_base = rows;
+    t.elem_base = cells;
+    rows += t.n_rows;
+    cells += t.n_rows * t.n_fields;
+  }
+  if (rows > CC_MAX_TOTAL_ROWS || cells > CC_MAX_TOTAL_CELLS) return fail(c, CC_E_RANGE, "tables too large");
+  c->total_rows = rows;
+  c->total_cells = cells;
+  HIP_OR(c, hipMalloc(&c->d_data, std::max<uint64_t>(cells, 1) * sizeof(int64_t)));
+  HIP_OR(c, hipMalloc(&c->d_words, std::max<uint64_t>(rows, 1) * sizeof(uint64_t)));
+  HIP_OR(c, hipMemsetAsync(c->d_data, 0, std::max<uint64_t>(cells, 1) * sizeof(int64_t), c->stream));
+  HIP_OR(c, hipStreamSynchronize(c->stream));
+  c->frozen = true;
+  return CC_OK;
+}
+
+void free_batch(Batch &b) {
+  if (b.d_ops) (void)hipFree(b.d_ops);
+  if (b.d_txns) (void)hipFree(b.d_txns);
+  if (b.d_out) (void)hipFree(b.d_out);
+  if (b.d_reads) (void)hipFree(b.d_reads);
+  b.d_ops = nullptr;
+  b.d_txns = nullptr;
+  b.d_out = nullptr;
+  b.d_reads = nullptr;
+}
+
+// Percentile of committed commit times (host side, after a run).
+void latency_percentiles(std::vector<cc_outcome> &o, uint64_t *p50, uint64_t *p99) {
+  std::vector<int64_t> lat;
+  lat.reserve(o.size());
+  for (auto &x : o)
+    if (x.status == CC_COMMITTED) lat.push_back(x.commit_ns);
+  if (lat.empty()) {
+    *p50 = *p99 = 0;
+    return;
+  }
+  auto pick = [&](double q) {
+    size_t i = (size_t)(q * (double)(lat.size() - 1) + 0.5);
+    std::nth_element(lat.begin(), lat.begin() + i, lat.end());
+    return (uint64_t)lat[i];
+  };
+  *p50 = pick(0.50);
+  *p99 = pick(0.99);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cc_version(void) { return "cc-gfx950 0.1"; }
+
+const char *cc_strerror(cc_status s) {
+  switch (s) {
+    case CC_OK: return "ok";
+    case CC_E_INVAL: return "invalid argument";
+    case CC_E_RANGE: return "out of range";
+    case CC_E_DUPROW: return "duplicate row access within a transaction";
+    case CC_E_NOMEM: return "out of memory";
+    case CC_E_TS_OVERFLOW: return "timestamp overflow";
+    case CC_E_LIVELOCK: return "transactions still pending (attempt or epoch limit reached)";
+    case CC_E_HIP: return "HIP runtime error";
+    case CC_E_NODEV: return "no usable gfx950 device";
+    case CC_E_STATE: return "call out of order";
+    case CC_E_NOBATCH: return "unknown batch";
+    default: return "unknown status";
+  }
+}
+
+const char *cc_last_error(const cc_ctx *ctx) { return ctx ? ctx->err.c_str() : g_init_err.c_str(); }
+
+cc_status cc_init(cc_ctx **out, const cc_config *cfg) {
+  if (!out) return CC_E_INVAL;
+  *out = nullptr;
+  g_init_err.clear();
+  int dev = cfg ? cfg->device : 0;
+  if (cfg && cfg->flags != 0) {
+    g_init_err = "cc_config.flags must be 0";
+    return CC_E_INVAL;
+  }
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+    g_init_err = "no HIP device";
+    return CC_E_NODEV;
+  }
+  if (dev < 0 || dev >= n) {
+    g_init_err = "device ordinal out of range";
+    return CC_E_NODEV;
+  }
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) {
+    g_init_err = "hipGetDeviceProperties failed";
+    return CC_E_NODEV;
+  }
+  if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0) {
+    g_init_err = std::string("device is ") + p.gcnArchName + ", the engine is built for gfx950";
+    return CC_E_NODEV;
+  }
+  cc_ctx *c = new (std::nothrow) cc_ctx();
+  if (!c) return CC_E_NOMEM;
+  c->device = dev;
+  c->stream = cfg ? (hipStream_t)cfg->stream : nullptr;
+  c->n_cu = p.multiProcessorCount;
+  int khz = 0;
+  if (hipSetDevice(dev) != hipSuccess ||
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) {
+    delete c;
+    g_init_err = "cannot read the device wall-clock rate";
+    return CC_E_HIP;
+  }
+  c->wallclock_khz = (uint32_t)khz;
+  if (hipMalloc(&c->d_ctl, sizeof(Ctl)) != hipSuccess) {
+    delete c;
+    g_init_err = "hipMalloc of the control block failed";
+    return CC_E_NOMEM;
+  }
+  for (auto &e : c->ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      cc_destroy(c);
+      g_init_err = "hipEventCreate failed";
+      return CC_E_HIP;
+    }
+  }
+  *out = c;
+  return CC_OK;
+}
+
+cc_status cc_destroy(cc_ctx *c) {
+  if (!c) return CC_OK;
+  activate(c);
+  (void)hipStreamSynchronize(c->stream);
+  for (auto &kv : c->batches) free_batch(kv.second);
+  if (c->d_data) (void)hipFree(c->d_data);
+  if (c->d_words) (void)hipFree(c->d_words);
+  if (c->d_aux) (void)hipFree(c->d_aux);
+  if (c->d_ctl) (void)hipFree(c->d_ctl);
+  for (auto &e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+  return CC_OK;
+}
+
+cc_status cc_device_info(cc_ctx *c, uint32_t *n_cu, uint32_t *khz) {
+  if (!c) return CC_E_INVAL;
+  if (n_cu) *n_cu = (uint32_t)c->n_cu;
+  if (khz) *khz = c->wallclock_khz;
+  return CC_OK;
+}
+
+cc_status cc_create_table(cc_ctx *c, uint64_t n_rows, uint32_t n_fields, uint32_t *table_id) {
+  if (!c || !table_id) return CC_E_INVAL;
+  if (c->frozen) return fail(c, CC_E_STATE, "tables must be declared before the first cc_load");
+  if (n_rows == 0 || n_fields == 0 || n_fields > 256) return fail(c, CC_E_INVAL, "bad table shape");
+  if (c->tables.size() >= CC_MAX_TABLES) return fail(c, CC_E_RANGE, "too many tables");
+  c->tables.push_back(Table{n_rows, n_fields, 0, 0});
+  *table_id = (uint32_t)(c->tables.size() - 1);
+  return CC_OK;
+}
+
+cc_status cc_load(cc_ctx *c, uint32_t tid, const int64_t *rows, uint64_t n_rows, int on_device) {
+  if (!c || !rows) return CC_E_INVAL;
+  if (tid >= c->tables.size()) return fail(c, CC_E_RANGE, "unknown table");
+  if (n_rows != c->tables[tid].n_rows) return fail(c, CC_E_INVAL, "row count differs from the table's");
+  if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
+  cc_status st = freeze(c);
+  if (st) return st;
+  const Table &t = c->tables[tid];
+  HIP_OR(c, hipMemcpyAsync(c->d_data + t.elem_base, rows, t.n_rows * t.n_fields * sizeof(int64_t),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  HIP_OR(c, hipStreamSynchronize(c->stream));
+  return CC_OK;
+}
+
+cc_status cc_read_table(cc_ctx *c, uint32_t tid, int64_t *out, int on_device) {
+  if (!c || !out) return CC_E_INVAL;
+  if (tid >= c->tables.size()) return fail(c, CC_E_RANGE, "unknown table");
+  if (!c->frozen) return fail(c, CC_E_STATE, "table not loaded");
+  if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
+  const Table &t = c->tables[tid];
+  HIP_OR(c, hipMemcpyAsync(out, c->d_data + t.elem_base, t.n_rows * t.n_fields * sizeof(int64_t),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  HIP_OR(c, hipStreamSynchronize(c->stream));
+  return CC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Validate a batch against table shapes and build its device descriptors.
+cc_status validate_and_pack(cc_ctx *c, const std::vector<Table> &tables, const cc_txn *txns, uint64_t n_txns,
+                            const cc_op *ops, uint64_t n_ops, std::vector<DevOp> *dops_out,
+                            std::vector<DevTxn> *dtx_out, uint32_t *max_ops_out, bool *has_slot_out) {
+  if ((n_txns && !txns) || (n_ops && !ops)) return fail(c, CC_E_INVAL, "null array");
+  if (n_txns > 0xFFFFFFFFull || n_ops > 0xFFFFFFFFull) return fail(c, CC_E_RANGE, "batch too large");
+  std::vector<DevOp> dummy_ops;
+  std::vector<DevTxn> dummy_tx;
+  std::vector<DevOp> &dops = dops_out ? *dops_out : dummy_ops;
+  std::vector<DevTxn> &dtx = dtx_out ? *dtx_out : dummy_tx;
+  dops.assign(n_ops, DevOp{0, 0, 0});
+  dtx.assign(n_txns, DevTxn{0, 0});
+  std::vector<uint8_t> used(n_ops, 0);  // every op belongs to at most one transaction
+  std::vector<uint64_t> keys;           // (table,row) of row leaders, for the duplicate check
+  uint32_t max_ops = 0;
+  bool has_slot = false;
+  for (uint64_t t = 0; t < n_txns; ++t) {
+    const cc_txn &x = txns[t];
+    if (x.reserved != 0) return fail(c, CC_E_INVAL, "cc_txn.reserved must be 0");
+    if (x.n_ops > CC_MAX_OPS_PER_TXN) return fail(c, CC_E_INVAL, "transaction has too many ops");
+    if (x.first_op > n_ops || x.n_ops > n_ops - x.first_op) return fail(c, CC_E_INVAL, "op range outside ops");
+    for (uint32_t i = 0; i < x.n_ops; ++i) {
+      if (used[x.first_op + i]) return fail(c, CC_E_INVAL, "transactions share operations");
+      used[x.first_op + i] = 1;
+    }
+    max_ops = std::max(max_ops, x.n_ops);
+    keys.clear();
+    uint32_t group_start = 0;
+    bool group_written = false;
+    for (uint32_t i = 0; i < x.n_ops; ++i) {
+      const cc_op &o = ops[x.first_op + i];
+      if (o.table >= tables.size()) return fail(c, CC_E_RANGE, "op table out of range");
+      const Table &tb = tables[o.table];
+      if (o.row >= tb.n_rows || o.field >= tb.n_fields) return fail(c, CC_E_RANGE, "op row/field out of range");
+      if (o.kind > CC_WRITE_SLOT) return fail(c, CC_E_INVAL, "unknown op kind");
+      if (o.kind == CC_WRITE_SLOT) {
+        has_slot = true;
+        if ((uint32_t)(o.arg & 0xFF) >= i) return fail(c, CC_E_INVAL, "WRITE_SLOT source is not an earlier op");
+      }
+      const bool follower = i > 0 && ops[x.first_op + i - 1].table == o.table && ops[x.first_op + i - 1].row == o.row;
+      if (!follower) {
+        for (uint32_t j = group_start; j < i; ++j)
+          if (group_written) dops[x.first_op + j].rowk |= WRITTEN_BIT;
+        group_start = i;
+        group_written = false;
+        keys.push_back(((uint64_t)o.table << 32) | o.row);
+      } else {
+        for (uint32_t j = group_start; j < i; ++j)
+          if (ops[x.first_op + j].field == o.field) return fail(c, CC_E_DUPROW, "field repeated within a txn");
+      }
+      group_written |= o.kind != CC_READ;
+      const uint64_t grow = tb.row_base + o.row;
+      DevOp d;
+      d.rowk = (uint32_t)grow | ((uint32_t)o.kind << KIND_SHIFT) | (follower ? FOLLOWER_BIT : 0u);
+      d.elem = (uint32_t)(tb.elem_base + (uint64_t)o.row * tb.n_fields + o.field);
+      d.arg = o.arg;
+      dops[x.first_op + i] = d;
+    }
+    for (uint32_t j = group_start; j < x.n_ops; ++j)
+      if (group_written) dops[x.first_op + j].rowk |= WRITTEN_BIT;
+    std::sort(keys.begin(), keys.end());
+    if (std::adjacent_find(keys.begin(), keys.end()) != keys.end())
+      return fail(c, CC_E_DUPROW, "row accessed twice (non-adjacent) within a txn");
+    dtx[t].first = (uint32_t)x.first_op;
+    dtx[t].n = x.n_ops;
+  }
+  if (max_ops_out) *max_ops_out = max_ops;
+  if (has_slot_out) *has_slot_out = has_slot;
+  return CC_OK;
+}
+
+std::vector<Table> layout_tables(uint32_t n_tables, const uint64_t *n_rows, const uint32_t *n_fields) {
+  std::vector<Table> v;
+  uint64_t rows = 0, cells = 0;
+  for (uint32_t t = 0; t < n_tables; ++t) {
+    v.push_back(Table{n_rows[t], n_fields[t], rows, cells});
+    rows += n_rows[t];
+    cells += n_rows[t] * n_fields[t];
+  }
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+cc_status cc_check_batch(uint32_t n_tables, const uint64_t *n_rows, const uint32_t *n_fields, const cc_txn *txns,
+                         uint64_t n_txns, const cc_op *ops, uint64_t n_ops, int scheme) {
+  if (n_tables > CC_MAX_TABLES || (n_tables && (!n_rows || !n_fields))) return CC_E_INVAL;
+  if (scheme < 0 || scheme >= CC_N_SCHEMES) return CC_E_INVAL;
+  uint64_t rows = 0, cells = 0;
+  for (uint32_t t = 0; t < n_tables; ++t) {
+    if (n_rows[t] == 0 || n_fields[t] == 0 || n_fields[t] > 256) return CC_E_INVAL;
+    rows += n_rows[t];
+    cells += n_rows[t] * n_fields[t];
+  }
+  if (rows > CC_MAX_TOTAL_ROWS || cells > CC_MAX_TOTAL_CELLS) return CC_E_RANGE;
+  return validate_and_pack(nullptr, layout_tables(n_tables, n_rows, n_fields), txns, n_txns, ops, n_ops, nullptr,
+                           nullptr, nullptr, nullptr);
+}
+
+cc_status cc_submit_batch(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, const cc_op *ops, uint64_t n_ops,
+                          int scheme, int on_device, uint64_t *batch_id) {
+  if (!c || !batch_id) return CC_E_INVAL;
+  *batch_id = 0;
+  if (scheme < 0 || scheme >= CC_N_SCHEMES) return fail(c, CC_E_INVAL, "unknown scheme");
+  if (on_device) return fail(c, CC_E_INVAL, "device-resident batch submission is not supported; pass host arrays");
+  if (!c->frozen) return fail(c, CC_E_STATE, "load the tables before submitting a batch");
+  if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
+  std::vector<DevOp> dops;
+  std::vector<DevTxn> dtx;
+  uint32_t max_ops = 0;
+  bool has_slot = false;
+  cc_status st = validate_and_pack(c, c->tables, txns, n_txns, ops, n_ops, &dops, &dtx, &max_ops, &has_slot);
+  if (st) return st;
+
+  Batch b;
+  b.scheme = scheme;
+  b.n_txns = n_txns;
+  b.n_ops = n_ops;
+  b.max_ops = max_ops;
+  b.has_slot = has_slot;
+  auto alloc = [&](void **p, size_t bytes) -> hipError_t { return hipMalloc(p, bytes ? bytes : 16); };
+  hipError_t e;
+  if ((e = alloc((void **)&b.d_ops, n_ops * sizeof(DevOp))) != hipSuccess ||
+      (e = alloc((void **)&b.d_txns, n_txns * sizeof(DevTxn))) != hipSuccess ||
+      (e = alloc((void **)&b.d_out, n_txns * sizeof(DevOutcome))) != hipSuccess ||
+      (e = alloc((void **)&b.d_reads, n_ops * sizeof(int64_t))) != hipSuccess) {
+    free_batch(b);
+    return hip_fail(c, e, "batch allocation");
+  }
+  if (n_ops) HIP_OR(c, hipMemcpyAsync(b.d_ops, dops.data(), n_ops * sizeof(DevOp), hipMemcpyHostToDevice, c->stream));
+  if (n_txns)
+    HIP_OR(c, hipMemcpyAsync(b.d_txns, dtx.data(), n_txns * sizeof(DevTxn), hipMemcpyHostToDevice, c->stream));
+  if (n_ops) HIP_OR(c, hipMemsetAsync(b.d_reads, 0, n_ops * sizeof(int64_t), c->stream));
+  HIP_OR(c, hipStreamSynchronize(c->stream));
+  const uint64_t id = c->next_batch++;
+  c->batches[id] = b;
+  *batch_id = id;
+  return CC_OK;
+}
+
+cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
+  if (!c) return CC_E_INVAL;
+  auto it = c->batches.find(batch_id);
+  if (it == c->batches.end()) return fail(c, CC_E_NOBATCH, "unknown batch");
+  Batch &b = it->second;
+  cc_run_params p{};
+  if (pp) p = *pp;
+  if (p.mode != CC_MODE_PLAIN) return fail(c, CC_E_INVAL, "unsupported mode");
+  uint32_t lanes = p.lanes_per_txn;
+  if (lanes == 0) {
+    lanes = 1;
+    while (lanes < 64 && lanes < b.max_ops) lanes *= 4;
+  }
+  if (lanes != 1 && lanes != 4 && lanes != 16 && lanes != 64) return fail(c, CC_E_INVAL, "lanes_per_txn must be 1, 4, 16 or 64");
+  const uint32_t wpw = p.waves_per_wg ? p.waves_per_wg : 4;
+  if (wpw < 1 || wpw > 16) return fail(c, CC_E_INVAL, "waves_per_wg must be 1..16");
+  if (p.flags & ~CC_RUN_STRICT_FENCES) return fail(c, CC_E_INVAL, "unknown run flag");
+  if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
+
+  RunArgs a{};
+  a.ops = b.d_ops;
+  a.txns = b.d_txns;
+  a.n_txns = b.n_txns;
+  a.data = c->d_data;
+  a.words = c->d_words;
+  a.aux = c->d_aux;
+  a.out = b.d_out;
+  a.reads = b.d_reads;
+  a.ctl = c->d_ctl;
+  a.max_attempts = p.max_attempts ? p.max_attempts : (1ull << 24);
+  const uint64_t backoff_ns = p.backoff_ns ? p.backoff_ns : 200;
+  a.backoff_ticks = (uint32_t)std::max<uint64_t>(1, backoff_ns * c->wallclock_khz / 1000000ull);
+  a.ns_per_tick_q16 = (uint32_t)((1000000ull << 16) / c->wallclock_khz);
+  a.has_slot = b.has_slot ? 1u : 0u;
+
+  HIP_OR(c, hipEventRecord(c->ev[0], c->stream));
+  HIP_OR(c, launch_init(c->stream, c->d_words, c->total_rows, nullptr, 0, b.d_out, b.n_txns, c->d_ctl));
+  HIP_OR(c, hipEventRecord(c->ev[1], c->stream));
+  int grid_used = 0;
+  if (b.n_txns) {
+    hipError_t e = launch_txn(c->stream, b.scheme, (int)lanes, (int)b.max_ops, (int)wpw, (int)p.grid,
+                              (p.flags & CC_RUN_STRICT_FENCES) != 0, a, c->n_cu, &grid_used);
+    if (e == hipErrorInvalidValue) return fail(c, CC_E_INVAL, "scheme or (lanes_per_txn, ops per txn) not supported");
+    if (e == hipErrorInvalidConfiguration)
+      return fail(c, CC_E_INVAL, "waves_per_wg too large for the register slots this lanes_per_txn needs");
+    if (e != hipSuccess) return hip_fail(c, e, "transaction kernel launch");
+  }
+  HIP_OR(c, hipEventRecord(c->ev[2], c->stream));
+  HIP_OR(c, hipStreamSynchronize(c->stream));
+
+  Ctl h;
+  HIP_OR(c, hipMemcpy(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+  float ms_run = 0, ms_kern = 0;
+  HIP_OR(c, hipEventElapsedTime(&ms_run, c->ev[0], c->ev[2]));
+  HIP_OR(c, hipEventElapsedTime(&ms_kern, c->ev[1], c->ev[2]));
+  std::memset(b.stats, 0, sizeof(b.stats));
+  b.stats[CC_STAT_COMMITTED] = h.stats[DS_COMMITTED];
+  b.stats[CC_STAT_ATTEMPTS] = h.stats[DS_ATTEMPTS];
+  b.stats[CC_STAT_ABORT_LOCK] = h.stats[DS_ABORT_LOCK];
+  b.stats[CC_STAT_ABORT_VALID] = h.stats[DS_ABORT_VALID];
+  b.stats[CC_STAT_KERNEL_NS] = (uint64_t)((double)ms_kern * 1e6);
+  b.stats[CC_STAT_RUN_NS] = (uint64_t)((double)ms_run * 1e6);
+  b.stats[CC_STAT_TICKETS] = h.ticket;
+  b.stats[CC_STAT_MAX_ATTEMPTS] = h.stats[DS_MAX_ATTEMPTS];
+  b.ran = true;
+  if (b.n_txns) {
+    std::vector<cc_outcome> o(b.n_txns);
+    HIP_OR(c, hipMemcpy(o.data(), b.d_out, b.n_txns * sizeof(cc_outcome), hipMemcpyDeviceToHost));
+    latency_percentiles(o, &b.stats[CC_STAT_LAT_P50_NS], &b.stats[CC_STAT_LAT_P99_NS]);
+  }
+  if (h.stats[DS_TS_OVERFLOW]) return fail(c, CC_E_TS_OVERFLOW, "timestamp overflow during the run");
+  if (h.stats[DS_COMMITTED] != b.n_txns) {
+    char msg[160];
+    std::snprintf(msg, sizeof msg, "%llu of %llu transactions committed (attempt limit reached)",
+                  (unsigned long long)h.stats[DS_COMMITTED], (unsigned long long)b.n_txns);
+    return fail(c, CC_E_LIVELOCK, msg);
+  }
+  return CC_OK;
+}
+
+cc_status cc_fetch_outcomes(cc_ctx *c, uint64_t batch_id, cc_outcome *per_txn, int64_t *per_op, int on_device) {
+  if (!c) return CC_E_INVAL;
+  auto it = c->batches.find(batch_id);
+  if (it == c->batches.end()) return fail(c, CC_E_NOBATCH, "unknown batch");
+  Batch &b = it->second;
+  if (!b.ran) return fail(c, CC_E_STATE, "batch has not been run");
+  if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
+  const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (per_txn && b.n_txns) HIP_OR(c, hipMemcpyAsync(per_txn, b.d_out, b.n_txns * sizeof(cc_outcome), k, c->stream));
+  if (per_op && b.n_ops) HIP_OR(c, hipMemcpyAsync(per_op, b.d_reads, b.n_ops * sizeof(int64_t), k, c->stream));
+  HIP_OR(c, hipStreamSynchronize(c->stream));
+  return CC_OK;
+}
+
+cc_status cc_stats(cc_ctx *c, uint64_t batch_id, uint64_t *counters, uint32_t n) {
+  if (!c || (!counters && n)) return CC_E_INVAL;
+  auto it = c->batches.find(batch_id);
+  if (it == c->batches.end()) return fail(c, CC_E_NOBATCH, "unknown batch");
+  for (uint32_t i = 0; i < n && i < CC_N_STATS; ++i) counters[i] = it->second.stats[i];
+  return CC_OK;
+}
+
+cc_status cc_release_batch(cc_ctx *c, uint64_t batch_id) {
+  if (!c) return CC_E_INVAL;
+  auto it = c->batches.find(batch_id);
+  if (it == c->batches.end()) return fail(c, CC_E_NOBATCH, "unknown batch");
+  activate(c);
+  (void)hipStreamSynchronize(c->stream);
+  free_batch(it->second);
+  c->batches.erase(it);
+  return CC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Internal layout shared by the host runtime (api.cpp) and the kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/cc.h"
+
+namespace cce {
+
+// ---- device operation descriptor (16 B) ------------------------------------
+// rowk packs the global row id (row within its table + the table's first row
+// in the shared row-id space) with the op kind and two flags computed at
+// submission:
+//   FOLLOWER  the op touches the same row as the previous op of its txn, so
+//             the row's first op ("leader") does the concurrency control;
+//   WRITTEN   some op of the row group writes the row.
+// elem is the cell index in the value arena (table base + row*fields + field).
+struct DevOp {
+  uint32_t rowk;
+  uint32_t elem;
+  int64_t arg;
+};
+static_assert(sizeof(DevOp) == 16, "DevOp is 16 bytes");
+
+constexpr uint32_t ROW_BITS = 28;
+constexpr uint32_t ROW_MASK = (1u << ROW_BITS) - 1u;
+constexpr uint32_t KIND_SHIFT = 28;
+constexpr uint32_t FOLLOWER_BIT = 1u << 30;
+constexpr uint32_t WRITTEN_BIT = 1u << 31;
+
+struct DevTxn {
+  uint32_t first;  // first op
+  uint32_t n;      // op count
+};
+
+struct DevOutcome {  // same layout as cc_outcome
+  uint32_t status;
+  uint32_t attempts;
+  uint64_t serial_hi;
+  uint64_t serial_lo;
+  int64_t commit_ns;
+};
+static_assert(sizeof(DevOutcome) == sizeof(cc_outcome), "outcome layout");
+
+// ---- device control block, cleared by the init kernel ----------------------
+enum DevStat {
+  DS_COMMITTED = 0,
+  DS_ATTEMPTS = 1,
+  DS_ABORT_LOCK = 2,
+  DS_ABORT_VALID = 3,
+  DS_GAVE_UP = 4,
+  DS_MAX_ATTEMPTS = 5,
+  DS_TS_OVERFLOW = 6,
+  DS_N = 8
+};
+
+struct Ctl {
+  uint64_t queue;        // next transaction index to hand out
+  uint64_t ticket;       // serial ticket / timestamp counter (last value drawn)
+  uint64_t start_clock;  // device wall clock at CC initialisation
+  uint64_t pad0;
+  uint64_t stats[DS_N];
+};
+
+// Kernel arguments for a transaction run.
+struct RunArgs {
+  const DevOp *ops;
+  const DevTxn *txns;
+  uint64_t n_txns;
+  int64_t *data;    // value arena
+  uint64_t *words;  // one control word per global row
+  uint64_t *aux;    // second word per row (MVCC version pointer)
+  DevOutcome *out;
+  int64_t *reads;   // per op read value
+  Ctl *ctl;
+  uint64_t max_attempts;
+  uint32_t backoff_ticks;  // wall-clock ticks
+  uint32_t ns_per_tick_q16;  // wall-clock tick length in ns, 16.16 fixed point
+  uint32_t has_slot;       // batch contains WRITE_SLOT ops
+  uint32_t pad;
+};
+
+// Host-side launchers (kernels.hip).
+hipError_t launch_init(hipStream_t s, uint64_t *words, uint64_t n_words, uint64_t *aux, uint64_t n_aux,
+                       DevOutcome *out, uint64_t n_out, Ctl *ctl);
+
+// Runs one plain batch: returns hipErrorInvalidValue for an unsupported
+// (lanes, ops-per-lane) combination.
+hipError_t launch_txn(hipStream_t s, int scheme, int lanes, int max_ops, int waves_per_wg, int grid,
+                      bool strict, const RunArgs &a, int n_cu, int *grid_used);
+
+}  // namespace cce

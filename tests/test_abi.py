@@ -1,0 +1,133 @@
+"""The C-ABI library without a GPU: it loads, exports every declared entry point, and its
+host-only validation rejects malformed batches with the documented status codes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from helpers import ROOT
+
+HEADER = os.path.join(ROOT, "include", "cc.h")
+LIB = os.path.join(ROOT, "paper_2406_10158_amd", "libcc.so")
+
+
+@pytest.fixture(scope="module")
+def b():
+    if not os.path.exists(LIB):
+        from paper_2406_10158_amd import build
+        build.build()
+    from paper_2406_10158_amd import binding
+    return binding
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(cc_[a-z_0-9]+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("cc_init", "cc_destroy", "cc_create_table", "cc_load", "cc_submit_batch", "cc_run",
+              "cc_fetch_outcomes", "cc_read_table", "cc_stats", "cc_strerror", "cc_check_batch"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(b):
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing
+
+
+def test_strerror_and_version(b):
+    assert b.cc_strerror(0) == "ok"
+    assert "duplicate" in b.cc_strerror(b.CC_E_DUPROW)
+    assert b.cc_strerror(-999) == "unknown status"
+    assert b.cc_version().startswith("cc-gfx950")
+
+
+def test_struct_layouts_match_header(b):
+    assert b.OP_DTYPE.itemsize == 16 and b.TXN_DTYPE.itemsize == 16 and b.OUTCOME_DTYPE.itemsize == 32
+    assert ctypes.sizeof(b.cc_run_params) == 40
+
+
+def _batch(rows, tables=None, fields=None, kinds=None, args=None, txn_lens=None):
+    from paper_2406_10158_amd.binding import OP_DTYPE, TXN_DTYPE
+    n = len(rows)
+    ops = np.zeros(n, OP_DTYPE)
+    ops["row"] = rows
+    ops["table"] = tables if tables is not None else 0
+    ops["field"] = fields if fields is not None else 0
+    ops["kind"] = kinds if kinds is not None else 0
+    ops["arg"] = args if args is not None else 0
+    lens = txn_lens if txn_lens is not None else [n]
+    txns = np.zeros(len(lens), TXN_DTYPE)
+    txns["n_ops"] = lens
+    txns["first_op"] = np.concatenate([[0], np.cumsum(lens)[:-1]]) if len(lens) else []
+    return txns, ops
+
+
+SHAPES = [(100, 4), (10, 2)]
+
+
+@pytest.mark.parametrize("case,status", [
+    (dict(rows=[1, 2, 3]), 0),
+    (dict(rows=[1, 100]), -2),                                   # row out of range
+    (dict(rows=[1, 2], fields=[0, 4]), -2),                      # field out of range
+    (dict(rows=[1, 2], tables=[0, 2]), -2),                      # table out of range
+    (dict(rows=[1, 2], kinds=[0, 4]), -1),                       # unknown kind
+    (dict(rows=[1, 2, 1]), -3),                                  # non-adjacent repeat of a row
+    (dict(rows=[1, 1], fields=[0, 1]), 0),                       # adjacent ops on one row: one row access
+    (dict(rows=[1, 1], fields=[2, 2]), -3),                      # a field repeated
+    (dict(rows=[5, 5], tables=[0, 1]), 0),                       # same row id, different tables
+    (dict(rows=[1, 2], kinds=[0, 3], args=[0, 0]), 0),           # WRITE_SLOT from op 0
+    (dict(rows=[1, 2], kinds=[3, 0], args=[0, 0]), -1),          # WRITE_SLOT from itself
+    (dict(rows=[1, 2, 3, 1], txn_lens=[2, 2]), 0),               # the same row in different txns is fine
+    (dict(rows=list(range(80)) * 4, fields=[0] * 80 + [1] * 80 + [2] * 80 + [3] * 80, txn_lens=[80] * 4), 0),
+])
+def test_check_batch_statuses(b, case, status):
+    txns, ops = _batch(**case)
+    assert b.cc_check_batch(SHAPES, txns, ops, 0) == status
+
+
+def test_check_batch_structural_errors(b):
+    txns, ops = _batch(rows=[1, 2, 3])
+    assert b.cc_check_batch(SHAPES, txns, ops, 7) == b.CC_E_INVAL         # unknown scheme
+    t2 = txns.copy(); t2["n_ops"] = 4
+    assert b.cc_check_batch(SHAPES, t2, ops, 0) == b.CC_E_INVAL           # op range past the end
+    t3 = np.concatenate([txns, txns])
+    assert b.cc_check_batch(SHAPES, t3, ops, 0) == b.CC_E_INVAL           # two txns share ops
+    t4 = txns.copy(); t4["reserved"] = 1
+    assert b.cc_check_batch(SHAPES, t4, ops, 0) == b.CC_E_INVAL
+    big = np.zeros(300, b.OP_DTYPE); big["row"] = np.arange(300) % 100; big["field"] = np.arange(300) // 100
+    t5 = np.zeros(1, b.TXN_DTYPE); t5["n_ops"] = 300
+    assert b.cc_check_batch(SHAPES, t5, big, 0) == b.CC_E_INVAL           # more than 256 ops
+    empty_t, empty_o = np.zeros(0, b.TXN_DTYPE), np.zeros(0, b.OP_DTYPE)
+    assert b.cc_check_batch(SHAPES, empty_t, empty_o, 0) == 0             # empty batch
+    zero = np.zeros(1, b.TXN_DTYPE)
+    assert b.cc_check_batch(SHAPES, zero, empty_o, 0) == 0                # a txn with no ops
+    assert b.cc_check_batch([(1 << 28, 1), (1, 1)], empty_t, empty_o, 0) == b.CC_E_RANGE
+
+
+def test_check_batch_accepts_generated_workloads(b):
+    from paper_2406_10158_amd import workload as wl
+    tabs, bt = wl.order_entry_workload(2, 200, seed=1)
+    txns, ops = b.pack_batch(bt)
+    assert b.cc_check_batch([t.shape for t in tabs], txns, ops, 0) == 0
+    (tab,), kb = wl.kv_workload(n_rows=1000, n_fields=10, n_txns=500, ops=(2, 64), theta=0.99)
+    txns, ops = b.pack_batch(kb)
+    assert b.cc_check_batch([tab.shape], txns, ops, 4) == 0
+
+
+def test_init_without_a_gpu_fails_cleanly(b):
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    with pytest.raises(b.CCError) as e:
+        b.cc_init(0)
+    assert e.value.status == b.CC_E_NODEV

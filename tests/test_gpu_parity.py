@@ -1,0 +1,177 @@
+"""GPU parity: every run of the HIP engine is checked against the CPU oracle.
+
+Per run: all transactions commit, serial keys are distinct, the serial replay
+in key order reproduces every read value and the final tables element by
+element, and add-only batches end in the order-free closed form.  Special
+cases pin outputs with no GPU input at all (single team = serial execution,
+read-only batches, disjoint keys), and tiny batches are brute-forced.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import SCHEMES, binding, check, run_and_check, run_batch
+from paper_2406_10158_amd import workload as wl
+
+pytestmark = pytest.mark.gpu
+
+IMPLEMENTED = ["occ"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _announce(request):
+    print(f"\n[gpu] module {request.module.__name__}", flush=True)
+
+
+@pytest.mark.parametrize("scheme", IMPLEMENTED)
+def test_tiny_config(scheme):
+    tabs, b = wl.tiny_workload(seed=0)
+    out, reads, final, st = run_and_check(tabs, b, scheme)
+    # the tiny config is add-only: final table is the closed form, independent of order
+    assert np.array_equal(final[0], oracle.final_add_only(tabs, b)[0])
+
+
+@pytest.mark.parametrize("scheme", IMPLEMENTED)
+@pytest.mark.parametrize("theta", [0.0, 0.6, 0.9, 0.99])
+def test_kv_parity(scheme, theta):
+    tabs, b = wl.kv_workload(n_rows=200_000, n_fields=10, n_txns=30_001, ops=16, theta=theta, seed=1)
+    out, reads, final, st = run_and_check(tabs, b, scheme)
+    print(f"{scheme} theta={theta}: attempts={st['attempts']} kernel_ms={st['kernel_ns']/1e6:.3f}")
+
+
+@pytest.mark.parametrize("scheme", IMPLEMENTED)
+@pytest.mark.parametrize("lanes,waves", [(1, 1), (1, 4), (4, 2), (4, 4), (16, 1), (16, 8), (64, 1), (64, 16)])
+def test_launch_shapes(scheme, lanes, waves):
+    ops = (1, 16) if lanes == 1 else (2, 64)
+    tabs, b = wl.kv_workload(n_rows=5_000, n_fields=4, n_txns=7_777, ops=ops, theta=0.9, seed=lanes * 31 + waves)
+    run_and_check(tabs, b, scheme, lanes_per_txn=lanes, waves_per_wg=waves)
+
+
+@pytest.mark.parametrize("scheme", IMPLEMENTED)
+def test_grid_sizes(scheme):
+    tabs, b = wl.kv_workload(n_rows=2_000, n_fields=2, n_txns=5_000, ops=8, theta=0.99, seed=2)
+    for grid in (1, 3, 64, 4096):
+        run_and_check(tabs, b, scheme, grid=grid, waves_per_wg=2)
+
+
+@pytest.mark.parametrize("scheme", IMPLEMENTED)
+def test_single_team_is_serial_execution(scheme):
+    # one workgroup of one wavefront with one 64-lane team: transactions run one at a time in id
+    # order, so the result is the oracle's own serial execution, with no GPU input to the oracle
+    tabs, b = wl.kv_workload(n_rows=300, n_fields=3, n_txns=400, ops=(1, 40), theta=0.9, seed=3)
+    out, reads, final, st = run_batch(tabs, b, scheme, lanes_per_txn=64, waves_per_wg=1, grid=1)
+    assert "error" not in st
+    exp_final, exp_reads = oracle.serial_execute(tabs, b)
+    assert np.array_equal(reads, exp_reads)
+    assert np.array_equal(final[0], exp_final[0])
+    assert st["attempts"] == b.n_txns  # zero aborts
+    assert np.all(np.diff(oracle.serial_order(out["status"], out["serial_hi"], out["serial_lo"])) == 1)
+
+
+@pytest.mark.parametrize("scheme", IMPLEMENTED)
+def test_read_only_batch(scheme):
+    tabs, b = wl.kv_workload(n_rows=50_000, n_fields=10, n_txns=20_000, ops=16, read_ratio=1.0, theta=0.99, seed=4)
+    out, reads, final, st = run_and_check(tabs, b, scheme)
+    assert np.array_equal(reads, 16 * b.row.astype(np.int64) + b.field.astype(np.int64))
+    assert np.array_equal(final[0], tabs[0])
+
+
+@pytest.mark.parametrize("scheme", IMPLEMENTED)
+def test_disjoint_keys(scheme):
+    n_txn, ops = 4_096, 8
+    b = wl.kv_batch(n_txn * ops, 2, n_txn, ops=ops, seed=5)
+    b.row[:] = np.random.default_rng(5).permutation(n_txn * ops).astype(np.uint32)
+    tabs = [wl.kv_table(n_txn * ops, 2)]
+    out, reads, final, st = run_and_check(tabs, b, scheme)
+    assert np.array_equal(reads, 16 * b.row.astype(np.int64) + b.field.astype(np.int64))
+    assert st["attempts"] == n_txn  # nothing conflicts, nothing aborts
+
+
+@pytest.mark.parametrize("scheme", IMPLEMENTED)
+def test_bruteforce_tiny_batches(scheme):
+    # <= 7 transactions on 3 rows, all in one wavefront (1 lane each): every outcome must be one
+    # of the k! serial executions
+    for seed in range(12):
+        tabs, b = wl.kv_workload(n_rows=3, n_fields=1, n_txns=7, ops=(1, 3), theta=0.0, seed=100 + seed)
+        out, reads, final, st = run_batch(tabs, b, scheme, lanes_per_txn=1, waves_per_wg=1)
+        assert "error" not in st
+        assert np.all(out["status"] == 1)
+        assert oracle.bruteforce_count(tabs, b, np.arange(b.n_txns), reads, final) >= 1
+        assert check(tabs, b, out, reads, final).ok
+
+
+@pytest.mark.parametrize("scheme", IMPLEMENTED)
+def test_two_hot_rows_stress(scheme):
+    # every transaction adds to both of two rows: a total order of 20k conflicting updates
+    n = 20_000
+    b = wl.kv_batch(2, 1, n, ops=2, read_ratio=0.3, arg_range=(-5, 5), seed=6)
+    tabs = [wl.kv_table(2, 1)]
+    out, reads, final, st = run_and_check(tabs, b, scheme, lanes_per_txn=4)
+    assert st["attempts"] > n  # there was contention
+
+
+@pytest.mark.parametrize("scheme", IMPLEMENTED)
+def test_edge_sizes(scheme):
+    tabs = [wl.kv_table(64, 2)]
+    # empty batch
+    b0 = wl.kv_batch(64, 2, 0, ops=4, seed=0)
+    out, reads, final, st = run_batch(tabs, b0, scheme)
+    assert "error" not in st and st["committed"] == 0 and np.array_equal(final[0], tabs[0])
+    # one transaction; a transaction with no ops among others
+    b1 = wl.kv_batch(64, 2, 1, ops=5, seed=1)
+    run_and_check(tabs, b1, scheme)
+    b2 = wl.kv_batch(64, 2, 50, ops=(0, 3), seed=2)
+    assert (b2.n_ops == 0).any()
+    run_and_check(tabs, b2, scheme)
+    # the largest transaction (256 ops) next to small ones
+    tabs3 = [wl.kv_table(4_000, 1)]
+    b3 = wl.kv_batch(4_000, 1, 40, ops=(1, 256), theta=0.6, seed=3)
+    assert b3.n_ops.max() > 192
+    run_and_check(tabs3, b3, scheme, lanes_per_txn=64, waves_per_wg=2)
+
+
+@pytest.mark.parametrize("scheme", IMPLEMENTED)
+def test_strict_fences(scheme):
+    b_ = binding()
+    tabs, b = wl.kv_workload(n_rows=20_000, n_fields=4, n_txns=20_000, ops=16, theta=0.99, seed=7)
+    run_and_check(tabs, b, scheme, flags=b_.CC_RUN_STRICT_FENCES)
+
+
+@pytest.mark.parametrize("scheme", IMPLEMENTED)
+def test_repeated_runs_accumulate(scheme):
+    tabs, b = wl.kv_workload(n_rows=10_000, n_fields=2, n_txns=8_000, ops=8, theta=0.9, seed=8)
+    bb = binding()
+    with bb.Engine(tabs) as eng:
+        bid = eng.submit(b, scheme)
+        cur = tabs
+        for _ in range(3):
+            eng.run(bid)
+            out, reads = eng.outcomes(bid, b.n_txns, b.total_ops)
+            final = eng.tables()
+            rep = check(cur, b, out, reads, final)
+            assert rep.ok, rep
+            cur = final
+
+
+@pytest.mark.parametrize("scheme", IMPLEMENTED)
+def test_attempt_limit_reports_livelock_and_leaves_no_partial_writes(scheme):
+    bb = binding()
+    n = 4_000
+    b = wl.kv_batch(2, 1, n, ops=2, read_ratio=0.0, seed=9)
+    tabs = [wl.kv_table(2, 1)]
+    out, reads, final, st = run_batch(tabs, b, scheme, max_attempts=1, lanes_per_txn=4)
+    assert isinstance(st.get("error"), bb.CCError) and st["error"].status == bb.CC_E_LIVELOCK
+    committed = out["status"] == 1
+    assert 0 < committed.sum() < n
+    # the committed subset is serializable and the aborted ones left nothing behind
+    rep = check(tabs, b, out, reads, final, require_all_committed=False)
+    assert rep.ok, rep
+    assert np.all(out["attempts"][~committed] == 1)
+
+
+@pytest.mark.parametrize("scheme", IMPLEMENTED)
+def test_full_size_kv_config(scheme):
+    # the headline configuration: 10M rows x 10 fields, 1M transactions x 16 ops, Zipf 0.9
+    tabs, b = wl.kv_workload(theta=0.9, seed=0)
+    out, reads, final, st = run_and_check(tabs, b, scheme)
+    print(f"full {scheme}: {b.n_txns / (st['run_ns'] * 1e-9):.3e} txn/s attempts={st['attempts']}")
