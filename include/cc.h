@@ -149,7 +149,9 @@ typedef struct {
   uint32_t max_epochs;    /* CC_MODE_EPOCH: epochs before CC_E_LIVELOCK; 0 = 1<<20 */
   uint32_t flags;         /* CC_RUN_* */
   uint32_t backoff_ns;    /* base of the randomised exponential back-off after an abort; 0 = 200 ns */
-  uint32_t reserved;
+  uint32_t defer_after;   /* CC_MODE_PLAIN: attempts of a transaction within one pass before it is deferred
+                             to the next pass, which runs 8x fewer workgroups (the last pass runs one
+                             wavefront and never defers); 0 = 16 */
 } cc_run_params;
 
 /* Counters reported by cc_stats (index: meaning). */
@@ -165,6 +167,9 @@ enum cc_stat {
   CC_STAT_LAT_P50_NS = 8,  /* commit latency percentiles over the batch (commit_ns) */
   CC_STAT_LAT_P99_NS = 9,
   CC_STAT_EPOCHS = 10,     /* epochs run (CC_MODE_EPOCH) */
+  CC_STAT_PASSES = 11,     /* kernel passes run (CC_MODE_PLAIN) */
+  CC_STAT_DEFERRED = 12,   /* transactions deferred to a later pass */
+  CC_STAT_GRID = 13,       /* workgroups of the first pass */
   CC_N_STATS = 16
 };
 
@@ -247,6 +252,36 @@ cc_status cc_stats(cc_ctx *ctx, uint64_t batch_id, uint64_t *counters, uint32_t 
 
 /* Free a batch's device buffers. */
 cc_status cc_release_batch(cc_ctx *ctx, uint64_t batch_id);
+
+/*
+ * Memory micro-benchmarks that measure the roofline of the transaction
+ * kernels, whose work is random 8-byte accesses and 64-bit atomics (not
+ * streaming, not arithmetic).  kind:
+ *   CC_PROBE_STREAM        16-byte streaming copy over footprint_bytes (reads + writes)
+ *   CC_PROBE_GATHER        n_ops random 8-byte agent-scope (coherent) loads
+ *   CC_PROBE_GATHER_PLAIN  n_ops random 8-byte plain loads
+ *   CC_PROBE_SCATTER       n_ops random 8-byte agent-scope stores
+ *   CC_PROBE_ATOMIC        n_ops random 64-bit fetch_or (agent scope)
+ *   CC_PROBE_SAME_WORD     n_ops 64-bit fetch_add on one word, every lane
+ *   CC_PROBE_WAVE_COUNTER  n_ops / 64 fetch_adds on one word, one per wavefront
+ *   CC_PROBE_HANDOFF       n_ops ping-pong rounds on one word between two
+ *                          workgroups `peer` apart (peer 1: another XCD; 8: same XCD)
+ * Random addresses are uniform over the largest power-of-two number of words
+ * that fits footprint_bytes.  *ms receives the kernel time (HIP events).
+ * Allocates and frees its own buffers.  CC_E_LIVELOCK if a hand-off turn
+ * exceeded its bounded wait.
+ */
+enum cc_probe_kind {
+  CC_PROBE_STREAM = 0,
+  CC_PROBE_GATHER = 1,
+  CC_PROBE_GATHER_PLAIN = 2,
+  CC_PROBE_SCATTER = 3,
+  CC_PROBE_ATOMIC = 4,
+  CC_PROBE_SAME_WORD = 5,
+  CC_PROBE_WAVE_COUNTER = 6,
+  CC_PROBE_HANDOFF = 7
+};
+cc_status cc_probe(cc_ctx *ctx, int kind, uint64_t footprint_bytes, uint64_t n_ops, int peer, double *ms);
 
 /* Device properties the engine uses: compute units, wall-clock rate (kHz). */
 cc_status cc_device_info(cc_ctx *ctx, uint32_t *n_cu, uint32_t *wallclock_khz);

@@ -31,7 +31,7 @@ CC_PENDING, CC_COMMITTED = 0, 1
 CC_MODE_PLAIN, CC_MODE_EPOCH = 0, 1
 CC_RUN_STRICT_FENCES = 0x1
 STAT_NAMES = ["committed", "attempts", "abort_lock", "abort_valid", "kernel_ns", "run_ns", "tickets",
-              "max_attempts", "lat_p50_ns", "lat_p99_ns", "epochs"]
+              "max_attempts", "lat_p50_ns", "lat_p99_ns", "epochs", "passes", "deferred", "grid"]
 CC_N_STATS = 16
 
 OP_DTYPE = np.dtype([("row", "<u4"), ("table", "<u2"), ("field", "u1"), ("kind", "u1"), ("arg", "<i8")])
@@ -48,7 +48,7 @@ class cc_config(ctypes.Structure):
 class cc_run_params(ctypes.Structure):
     _fields_ = [("lanes_per_txn", ctypes.c_uint32), ("waves_per_wg", ctypes.c_uint32), ("grid", ctypes.c_uint32),
                 ("mode", ctypes.c_uint32), ("max_attempts", ctypes.c_uint64), ("max_epochs", ctypes.c_uint32),
-                ("flags", ctypes.c_uint32), ("backoff_ns", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("backoff_ns", ctypes.c_uint32), ("defer_after", ctypes.c_uint32)]
 
 
 _P = ctypes.c_void_p
@@ -70,6 +70,8 @@ _SIGS = {
     "cc_stats": (_S, [_P, ctypes.c_uint64, _P, ctypes.c_uint32]),
     "cc_release_batch": (_S, [_P, ctypes.c_uint64]),
     "cc_device_info": (_S, [_P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]),
+    "cc_probe": (_S, [_P, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+                      ctypes.POINTER(ctypes.c_double)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -131,6 +133,19 @@ def cc_device_info(ctx):
     return int(n_cu.value), int(khz.value)
 
 
+PROBES = {"stream": 0, "gather": 1, "gather_plain": 2, "scatter": 3, "atomic": 4, "same_word": 5,
+          "wave_counter": 6, "handoff": 7}
+
+
+def cc_probe(ctx, kind, footprint_bytes: int, n_ops: int, peer: int = 1) -> float:
+    """Run one memory micro-benchmark; returns its kernel time in ms."""
+    if isinstance(kind, str):
+        kind = PROBES[kind]
+    ms = ctypes.c_double()
+    _check(lib.cc_probe(ctx, kind, footprint_bytes, n_ops, peer, ctypes.byref(ms)), ctx)
+    return float(ms.value)
+
+
 def cc_create_table(ctx, n_rows: int, n_fields: int) -> int:
     tid = ctypes.c_uint32()
     _check(lib.cc_create_table(ctx, n_rows, n_fields, ctypes.byref(tid)), ctx)
@@ -172,8 +187,9 @@ def cc_submit_batch(ctx, txns: np.ndarray, ops: np.ndarray, scheme: int) -> int:
 
 
 def run_params(lanes_per_txn=0, waves_per_wg=0, grid=0, mode=CC_MODE_PLAIN, max_attempts=0, max_epochs=0,
-               flags=0, backoff_ns=0) -> cc_run_params:
-    return cc_run_params(lanes_per_txn, waves_per_wg, grid, mode, max_attempts, max_epochs, flags, backoff_ns, 0)
+               flags=0, backoff_ns=0, defer_after=0) -> cc_run_params:
+    return cc_run_params(lanes_per_txn, waves_per_wg, grid, mode, max_attempts, max_epochs, flags, backoff_ns,
+                         defer_after)
 
 
 def cc_run(ctx, batch_id: int, params: cc_run_params | None = None) -> None:

@@ -31,6 +31,7 @@ struct Batch {
   DevTxn *d_txns = nullptr;
   DevOutcome *d_out = nullptr;
   int64_t *d_reads = nullptr;
+  uint32_t *d_list = nullptr;  // pending transactions between passes
   bool ran = false;
   uint64_t stats[CC_N_STATS] = {};
 };
@@ -51,7 +52,7 @@ struct cc_ctx {
   Ctl *d_ctl = nullptr;
   std::map<uint64_t, Batch> batches;
   uint64_t next_batch = 1;
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::string err;
 };
 
@@ -104,6 +105,8 @@ void free_batch(Batch &b) {
   if (b.d_txns) (void)hipFree(b.d_txns);
   if (b.d_out) (void)hipFree(b.d_out);
   if (b.d_reads) (void)hipFree(b.d_reads);
+  if (b.d_list) (void)hipFree(b.d_list);
+  b.d_list = nullptr;
   b.d_ops = nullptr;
   b.d_txns = nullptr;
   b.d_out = nullptr;
@@ -222,6 +225,19 @@ cc_status cc_destroy(cc_ctx *c) {
   for (auto &e : c->ev)
     if (e) (void)hipEventDestroy(e);
   delete c;
+  return CC_OK;
+}
+
+cc_status cc_probe(cc_ctx *c, int kind, uint64_t footprint_bytes, uint64_t n_ops, int peer, double *ms) {
+  if (!c || !ms) return CC_E_INVAL;
+  if (kind < CC_PROBE_STREAM || kind > CC_PROBE_HANDOFF) return fail(c, CC_E_INVAL, "unknown probe");
+  if (footprint_bytes < 4096 || (kind == CC_PROBE_HANDOFF && (peer < 1 || peer > 64)))
+    return fail(c, CC_E_INVAL, "bad probe size or peer");
+  if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
+  uint64_t err = 0;
+  hipError_t e = run_probe(c->stream, kind, footprint_bytes, n_ops, peer, ms, &err, c->n_cu);
+  if (e != hipSuccess) return hip_fail(c, e, "probe");
+  if (err) return fail(c, CC_E_LIVELOCK, "hand-off turn exceeded its bounded wait");
   return CC_OK;
 }
 
@@ -399,7 +415,8 @@ cc_status cc_submit_batch(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, const 
   if ((e = alloc((void **)&b.d_ops, n_ops * sizeof(DevOp))) != hipSuccess ||
       (e = alloc((void **)&b.d_txns, n_txns * sizeof(DevTxn))) != hipSuccess ||
       (e = alloc((void **)&b.d_out, n_txns * sizeof(DevOutcome))) != hipSuccess ||
-      (e = alloc((void **)&b.d_reads, n_ops * sizeof(int64_t))) != hipSuccess) {
+      (e = alloc((void **)&b.d_reads, n_ops * sizeof(int64_t))) != hipSuccess ||
+      (e = alloc((void **)&b.d_list, n_txns * sizeof(uint32_t))) != hipSuccess) {
     free_batch(b);
     return hip_fail(c, e, "batch allocation");
   }
@@ -449,35 +466,68 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   a.ns_per_tick_q16 = (uint32_t)((1000000ull << 16) / c->wallclock_khz);
   a.has_slot = b.has_slot ? 1u : 0u;
 
+  const uint32_t defer = p.defer_after ? p.defer_after : 16;
+  a.pass = 0;
+  a.list = nullptr;
+
   HIP_OR(c, hipEventRecord(c->ev[0], c->stream));
   HIP_OR(c, launch_init(c->stream, c->d_words, c->total_rows, nullptr, 0, b.d_out, b.n_txns, c->d_ctl));
-  HIP_OR(c, hipEventRecord(c->ev[1], c->stream));
-  int grid_used = 0;
+  Ctl h{};
+  double kernel_ms = 0;
+  uint32_t passes = 0;
+  int first_grid = 0;
   if (b.n_txns) {
-    hipError_t e = launch_txn(c->stream, b.scheme, (int)lanes, (int)b.max_ops, (int)wpw, (int)p.grid,
-                              (p.flags & CC_RUN_STRICT_FENCES) != 0, a, c->n_cu, &grid_used);
-    if (e == hipErrorInvalidValue) return fail(c, CC_E_INVAL, "scheme or (lanes_per_txn, ops per txn) not supported");
-    if (e == hipErrorInvalidConfiguration)
-      return fail(c, CC_E_INVAL, "waves_per_wg too large for the register slots this lanes_per_txn needs");
-    if (e != hipSuccess) return hip_fail(c, e, "transaction kernel launch");
+    int grid = (int)p.grid;
+    uint32_t waves = wpw;
+    for (;;) {
+      const bool last = grid == 1 && waves == 1;
+      a.defer_after = last ? 0u : defer;
+      HIP_OR(c, hipEventRecord(c->ev[1], c->stream));
+      int grid_used = 0;
+      hipError_t e = launch_txn(c->stream, b.scheme, (int)lanes, (int)b.max_ops, (int)waves, grid,
+                                (p.flags & CC_RUN_STRICT_FENCES) != 0, a, c->n_cu, &grid_used);
+      if (e == hipErrorInvalidValue)
+        return fail(c, CC_E_INVAL, "scheme or (lanes_per_txn, ops per txn) not supported");
+      if (e == hipErrorInvalidConfiguration)
+        return fail(c, CC_E_INVAL, "waves_per_wg too large for the register slots this lanes_per_txn needs");
+      if (e != hipSuccess) return hip_fail(c, e, "transaction kernel launch");
+      HIP_OR(c, hipEventRecord(c->ev[2], c->stream));
+      HIP_OR(c, hipStreamSynchronize(c->stream));
+      float ms = 0;
+      HIP_OR(c, hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
+      kernel_ms += ms;
+      if (passes == 0) first_grid = grid_used;
+      ++passes;
+      HIP_OR(c, hipMemcpy(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+      if (h.stats[DS_COMMITTED] + h.stats[DS_GAVE_UP] >= b.n_txns || last) break;
+      // next pass: the pending transactions, 8x fewer workgroups, down to one wavefront
+      HIP_OR(c, launch_compact(c->stream, b.d_out, b.n_txns, a.max_attempts, b.d_list, c->d_ctl));
+      HIP_OR(c, hipMemcpyAsync(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+      HIP_OR(c, hipStreamSynchronize(c->stream));
+      a.list = b.d_list;
+      a.n_txns = h.pending_n;
+      a.pass = passes;
+      grid = std::max(1, grid_used / 8);
+      if (grid == 1) waves = 1;
+    }
   }
-  HIP_OR(c, hipEventRecord(c->ev[2], c->stream));
+  HIP_OR(c, hipEventRecord(c->ev[3], c->stream));
   HIP_OR(c, hipStreamSynchronize(c->stream));
-
-  Ctl h;
   HIP_OR(c, hipMemcpy(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
-  float ms_run = 0, ms_kern = 0;
-  HIP_OR(c, hipEventElapsedTime(&ms_run, c->ev[0], c->ev[2]));
-  HIP_OR(c, hipEventElapsedTime(&ms_kern, c->ev[1], c->ev[2]));
+  float ms_run = 0;
+  HIP_OR(c, hipEventElapsedTime(&ms_run, c->ev[0], c->ev[3]));
   std::memset(b.stats, 0, sizeof(b.stats));
   b.stats[CC_STAT_COMMITTED] = h.stats[DS_COMMITTED];
   b.stats[CC_STAT_ATTEMPTS] = h.stats[DS_ATTEMPTS];
   b.stats[CC_STAT_ABORT_LOCK] = h.stats[DS_ABORT_LOCK];
   b.stats[CC_STAT_ABORT_VALID] = h.stats[DS_ABORT_VALID];
-  b.stats[CC_STAT_KERNEL_NS] = (uint64_t)((double)ms_kern * 1e6);
+  b.stats[CC_STAT_KERNEL_NS] = (uint64_t)(kernel_ms * 1e6);
   b.stats[CC_STAT_RUN_NS] = (uint64_t)((double)ms_run * 1e6);
   b.stats[CC_STAT_TICKETS] = h.ticket;
   b.stats[CC_STAT_MAX_ATTEMPTS] = h.stats[DS_MAX_ATTEMPTS];
+  b.stats[CC_STAT_PASSES] = passes;
+  b.stats[CC_STAT_DEFERRED] = h.stats[DS_DEFERRED];
+  b.stats[CC_STAT_GRID] = (uint64_t)first_grid;
   b.ran = true;
   if (b.n_txns) {
     std::vector<cc_outcome> o(b.n_txns);

@@ -52,6 +52,7 @@ enum DevStat {
   DS_GAVE_UP = 4,
   DS_MAX_ATTEMPTS = 5,
   DS_TS_OVERFLOW = 6,
+  DS_DEFERRED = 7,
   DS_N = 8
 };
 
@@ -59,7 +60,7 @@ struct Ctl {
   uint64_t queue;        // next transaction index to hand out
   uint64_t ticket;       // serial ticket / timestamp counter (last value drawn)
   uint64_t start_clock;  // device wall clock at CC initialisation
-  uint64_t pad0;
+  uint64_t pending_n;    // length of the pending list built between passes
   uint64_t stats[DS_N];
 };
 
@@ -67,7 +68,8 @@ struct Ctl {
 struct RunArgs {
   const DevOp *ops;
   const DevTxn *txns;
-  uint64_t n_txns;
+  const uint32_t *list;  // transactions of this pass (nullptr: 0..n_txns-1)
+  uint64_t n_txns;       // transactions in this pass
   int64_t *data;    // value arena
   uint64_t *words;  // one control word per global row
   uint64_t *aux;    // second word per row (MVCC version pointer)
@@ -78,6 +80,8 @@ struct RunArgs {
   uint32_t backoff_ticks;  // wall-clock ticks
   uint32_t ns_per_tick_q16;  // wall-clock tick length in ns, 16.16 fixed point
   uint32_t has_slot;       // batch contains WRITE_SLOT ops
+  uint32_t defer_after;    // attempts in this pass before deferring (0: never)
+  uint32_t pass;           // 0 for the first pass
   uint32_t pad;
 };
 
@@ -85,9 +89,18 @@ struct RunArgs {
 hipError_t launch_init(hipStream_t s, uint64_t *words, uint64_t n_words, uint64_t *aux, uint64_t n_aux,
                        DevOutcome *out, uint64_t n_out, Ctl *ctl);
 
+// Between passes: list the transactions neither committed nor given up, and
+// reset the claim counter.  ctl->pending_n receives the count.
+hipError_t launch_compact(hipStream_t s, const DevOutcome *out, uint64_t n_txns, uint64_t max_attempts,
+                          uint32_t *list, Ctl *ctl);
+
 // Runs one plain batch: returns hipErrorInvalidValue for an unsupported
 // (lanes, ops-per-lane) combination.
 hipError_t launch_txn(hipStream_t s, int scheme, int lanes, int max_ops, int waves_per_wg, int grid,
                       bool strict, const RunArgs &a, int n_cu, int *grid_used);
+
+// Memory micro-benchmarks (roofline.hip); see cc_probe in cc.h.
+hipError_t run_probe(hipStream_t s, int kind, uint64_t footprint_bytes, uint64_t n_ops, int peer, double *ms_out,
+                     uint64_t *err_out, int n_cu);
 
 }  // namespace cce

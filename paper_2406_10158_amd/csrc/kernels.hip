@@ -288,21 +288,23 @@ struct MaxThreads {
 template <int L, int K, int SCHEME, bool STRICT>
 __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
   Team<L> t;
-  const uint64_t start_clock = a.ctl->start_clock;
   Slots<K> s;
+  const uint64_t start_clock = a.ctl->start_clock;
   int64_t txn = -1;         // current transaction (team-uniform)
-  uint32_t attempts = 0;
+  uint32_t attempts = 0;    // attempts of txn so far, all passes
+  uint32_t pass_att = 0;    // attempts of txn in this pass
   uint64_t ready_at = 0;    // wall-clock tick before which the team waits
   bool done = false;        // no transactions left for this team
-  uint64_t n_commit = 0, n_att = 0, n_lock = 0, n_valid = 0, n_gave = 0, max_att = 0;
+  uint64_t n_commit = 0, n_att = 0, n_lock = 0, n_valid = 0, n_gave = 0, n_defer = 0, max_att = 0;
 
   for (;;) {
     const bool need = txn < 0 && !done;
     const uint64_t q = t.claim(&a.ctl->queue, need, 1);
     if (need) {
       if (q < a.n_txns) {
-        txn = (int64_t)q;
-        attempts = 0;
+        txn = a.list ? (int64_t)a.list[q] : (int64_t)q;
+        attempts = a.pass ? a.out[txn].attempts : 0;
+        pass_att = 0;
         ready_at = 0;
       } else {
         done = true;
@@ -343,6 +345,7 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
     int r = occ_attempt<L, K, STRICT>(t, s, active, a, &key);
     if (active) {
       ++attempts;
+      ++pass_att;
       ++n_att;
       if (r == COMMIT) {
         if (t.tl == 0) {
@@ -365,15 +368,17 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
         if (t.tl == 0) {
           if (r == ABORT_LOCK) ++n_lock; else ++n_valid;
         }
-        if (attempts >= a.max_attempts) {
+        if (attempts >= a.max_attempts || (a.defer_after && pass_att >= a.defer_after)) {
+          // give up (attempt limit) or leave it to the next, less concurrent pass
           if (t.tl == 0) {
             a.out[txn].attempts = attempts;
-            ++n_gave;
+            if (attempts >= a.max_attempts) ++n_gave; else ++n_defer;
             max_att = attempts > max_att ? attempts : max_att;
           }
           txn = -1;
         } else {
-          const uint32_t sh = attempts < 8 ? attempts : 8;
+          // randomised exponential back-off
+          const uint32_t sh = pass_att < 12 ? pass_att : 12;
           const uint64_t span = (uint64_t)a.backoff_ticks << sh;
           ready_at = now + (mix64(((uint64_t)txn << 20) ^ attempts) % (span + 1));
         }
@@ -381,10 +386,10 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
     }
   }
   // one atomic per counter per wavefront (team leaders hold the counts; the
-  // attempts counter is kept per lane and divided back by L)
+  // attempts counter is kept per lane and counted in leaders only)
   n_att = t.tl == 0 ? n_att : 0;
   const uint64_t c0 = wave_sum(n_commit), c1 = wave_sum(n_att), c2 = wave_sum(n_lock), c3 = wave_sum(n_valid),
-                 c4 = wave_sum(n_gave), c5 = wave_max(max_att);
+                 c4 = wave_sum(n_gave), c5 = wave_max(max_att), c6 = wave_sum(n_defer);
   if (t.lane == 0) {
     if (c0) atomicAdd((unsigned long long *)&a.ctl->stats[DS_COMMITTED], (unsigned long long)c0);
     if (c1) atomicAdd((unsigned long long *)&a.ctl->stats[DS_ATTEMPTS], (unsigned long long)c1);
@@ -392,7 +397,46 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
     if (c3) atomicAdd((unsigned long long *)&a.ctl->stats[DS_ABORT_VALID], (unsigned long long)c3);
     if (c4) atomicAdd((unsigned long long *)&a.ctl->stats[DS_GAVE_UP], (unsigned long long)c4);
     if (c5) atomicMax((unsigned long long *)&a.ctl->stats[DS_MAX_ATTEMPTS], (unsigned long long)c5);
+    if (c6) atomicAdd((unsigned long long *)&a.ctl->stats[DS_DEFERRED], (unsigned long long)c6);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Between passes: the list of transactions still pending (not committed, not
+// given up), appended with one atomic per wavefront; order is irrelevant.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) pass_reset_kernel(Ctl *ctl) {
+  if (threadIdx.x == 0) {
+    ctl->queue = 0;
+    ctl->pending_n = 0;
+  }
+}
+
+__global__ void __launch_bounds__(256) compact_kernel(const DevOutcome *out, uint64_t n, uint64_t max_attempts,
+                                                      uint32_t *list, Ctl *ctl) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool p = false;
+  if (i < n) {
+    const DevOutcome o = out[i];
+    p = o.status != CC_COMMITTED && o.attempts < max_attempts;
+  }
+  const uint64_t m = ballot(p);
+  if (m == 0) return;
+  const int lane = __lane_id();
+  const int first = __ffsll((unsigned long long)m) - 1;
+  uint64_t base = 0;
+  if (lane == first) base = atomicAdd((unsigned long long *)&ctl->pending_n, (unsigned long long)__popcll(m));
+  base = readlane64(base, first);
+  if (p) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)i;
+}
+
+hipError_t launch_compact(hipStream_t s, const DevOutcome *out, uint64_t n_txns, uint64_t max_attempts,
+                          uint32_t *list, Ctl *ctl) {
+  hipLaunchKernelGGL(pass_reset_kernel, dim3(1), dim3(64), 0, s, ctl);
+  const uint64_t blocks = (n_txns + 255) / 256;
+  if (blocks) hipLaunchKernelGGL(compact_kernel, dim3((unsigned)blocks), dim3(256), 0, s, out, n_txns, max_attempts,
+                                 list, ctl);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -417,7 +461,7 @@ __global__ void __launch_bounds__(256) init_kernel(uint64_t *words, uint64_t n_w
   if (tid == 0) {
     ctl->queue = 0;
     ctl->ticket = 0;
-    ctl->pad0 = 0;
+    ctl->pending_n = 0;
     for (int i = 0; i < DS_N; ++i) ctl->stats[i] = 0;
     ctl->start_clock = wall_clock64();
   }

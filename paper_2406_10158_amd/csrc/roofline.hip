@@ -1,0 +1,143 @@
+// Memory micro-benchmarks that bound the transaction kernels: the engine's
+// hot path is random 8-byte accesses and 64-bit device atomics, so its
+// roofline is set by how many of those the memory system sustains, not by
+// streaming bandwidth or arithmetic.  Each probe times one kernel with HIP
+// events; addresses come from a hash of the op index (no index traffic).
+#include "engine.h"
+
+namespace cce {
+
+__device__ __forceinline__ uint64_t hash64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// 16-byte streaming copy src -> dst.
+__global__ void __launch_bounds__(256) probe_stream(const uint4 *src, uint4 *dst, uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+// Random 8-byte accesses over a power-of-two number of words.
+// mode 0: agent-scope loads   1: plain loads   2: agent-scope stores
+//      3: agent-scope fetch_or   4: agent-scope fetch_add on one word (every lane)
+//      5: agent-scope fetch_add on one word, one per wavefront
+template <int MODE>
+__global__ void __launch_bounds__(256) probe_random(uint64_t *words, uint64_t mask, uint64_t per_thread,
+                                                   uint64_t *sink) {
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t acc = 0;
+  for (uint64_t j = 0; j < per_thread; j += 4) {
+    uint64_t v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint64_t idx = hash64((tid << 24) ^ (j + u)) & mask;
+      if constexpr (MODE == 0) {
+        v[u] = __hip_atomic_load(words + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else if constexpr (MODE == 1) {
+        v[u] = words[idx];
+      } else if constexpr (MODE == 2) {
+        __hip_atomic_store(words + idx, j + u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v[u] = 0;
+      } else if constexpr (MODE == 3) {
+        v[u] = __hip_atomic_fetch_or(words + idx, 1ull << (u + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else if constexpr (MODE == 4) {
+        v[u] = __hip_atomic_fetch_add(words, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        v[u] = 0;
+        if (__lane_id() == 0) v[u] = __hip_atomic_fetch_add(words, 64ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    acc += v[0] ^ v[1] ^ v[2] ^ v[3];
+  }
+  if (acc == 0x5A5A5A5A5A5A5A5Aull) sink[tid & 1023] = acc;  // keeps the loads live
+}
+
+// Ping-pong on one word between lane 0 of block 0 and lane 0 of block `peer`
+// (blocks are dealt round-robin to the 8 XCDs, so peer 1 is another XCD and
+// peer 8 the same XCD).  Each side waits for its turn with agent-scope loads,
+// bounded by `spin_limit` polls per turn; on exhaustion it records an error.
+__global__ void __launch_bounds__(64) probe_handoff(uint64_t *flag, uint64_t rounds, int peer, uint64_t spin_limit,
+                                                    uint64_t *err) {
+  if (threadIdx.x != 0) return;
+  int side = -1;
+  if (blockIdx.x == 0) side = 0;
+  if ((int)blockIdx.x == peer) side = 1;
+  if (side < 0) return;
+  for (uint64_t r = 0; r < rounds; ++r) {
+    const uint64_t want = 2 * r + (uint64_t)side;
+    uint64_t spins = 0;
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != want) {
+      if (++spins > spin_limit) {
+        __hip_atomic_store(err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+      }
+    }
+    __hip_atomic_store(flag, want + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ void fill_kernel(uint64_t *p, uint64_t n, uint64_t v) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+hipError_t run_probe(hipStream_t s, int kind, uint64_t footprint_bytes, uint64_t n_ops, int peer, double *ms_out,
+                     uint64_t *err_out, int n_cu) {
+  *err_out = 0;
+  uint64_t words = 1;
+  while (words * 2 * sizeof(uint64_t) <= footprint_bytes) words *= 2;
+  uint64_t *buf = nullptr, *aux = nullptr;
+  hipError_t e = hipMalloc(&buf, words * sizeof(uint64_t));
+  if (e != hipSuccess) return e;
+  e = hipMalloc(&aux, 8192 * sizeof(uint64_t));
+  if (e != hipSuccess) {
+    (void)hipFree(buf);
+    return e;
+  }
+  hipEvent_t a, b;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  hipLaunchKernelGGL(fill_kernel, dim3(4096), dim3(256), 0, s, buf, words, 0ull);
+  hipLaunchKernelGGL(fill_kernel, dim3(32), dim3(256), 0, s, aux, 8192ull, 0ull);
+  const unsigned grid = (unsigned)(n_cu * 8), block = 256;
+  const uint64_t threads = (uint64_t)grid * block;
+  uint64_t per = (n_ops + threads - 1) / threads;
+  per = (per + 3) & ~3ull;
+  if (per == 0) per = 4;
+  (void)hipEventRecord(a, s);
+  switch (kind) {
+    case 0:
+      hipLaunchKernelGGL(probe_stream, dim3(grid * 4), dim3(256), 0, s, (const uint4 *)buf,
+                         (uint4 *)(buf + words / 2), (uint64_t)(words / 4));
+      break;
+    case 1: hipLaunchKernelGGL(probe_random<0>, dim3(grid), dim3(block), 0, s, buf, words - 1, per, aux); break;
+    case 2: hipLaunchKernelGGL(probe_random<1>, dim3(grid), dim3(block), 0, s, buf, words - 1, per, aux); break;
+    case 3: hipLaunchKernelGGL(probe_random<2>, dim3(grid), dim3(block), 0, s, buf, words - 1, per, aux); break;
+    case 4: hipLaunchKernelGGL(probe_random<3>, dim3(grid), dim3(block), 0, s, buf, words - 1, per, aux); break;
+    case 5: hipLaunchKernelGGL(probe_random<4>, dim3(grid), dim3(block), 0, s, buf, words - 1, per, aux); break;
+    case 6: hipLaunchKernelGGL(probe_random<5>, dim3(grid), dim3(block), 0, s, buf, words - 1, per, aux); break;
+    case 7:
+      hipLaunchKernelGGL(probe_handoff, dim3((unsigned)(peer + 1)), dim3(64), 0, s, buf, n_ops, peer,
+                         (uint64_t)1 << 20, aux + 4096);
+      break;
+    default:
+      break;
+  }
+  e = hipGetLastError();
+  (void)hipEventRecord(b, s);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float ms = 0;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+  if (e == hipSuccess && kind == 7) e = hipMemcpy(err_out, aux + 4096, sizeof(uint64_t), hipMemcpyDeviceToHost);
+  *ms_out = ms;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  (void)hipFree(buf);
+  (void)hipFree(aux);
+  return e;
+}
+
+}  // namespace cce
