@@ -53,6 +53,59 @@ def algorithmic_bytes(batch) -> int:
             + batch.n_txns * (8 + 32))
 
 
+def access_counts(batch) -> dict:
+    """Memory operations one committed pass of the OCC hot path must issue, from the batch itself."""
+    kind = batch.kind
+    n_ops = batch.total_ops
+    first = np.zeros(n_ops, bool)
+    first[batch.first_op[batch.n_ops > 0].astype(np.int64)] = True
+    same = np.zeros(n_ops, bool)
+    same[1:] = (batch.row[1:] == batch.row[:-1]) & (batch.table[1:] == batch.table[:-1])
+    leader = first | ~same
+    grp = np.cumsum(leader) - 1
+    written = np.zeros(int(leader.sum()), bool)
+    np.logical_or.at(written, grp, kind != 0)
+    n_groups, n_wgroups = len(written), int(written.sum())
+    n_writes = int((kind != 0).sum())
+    return {
+        # value reads + word reads of read-only rows + validation re-reads
+        "random_loads": n_ops + 2 * (n_groups - n_wgroups),
+        "random_atomics": n_wgroups,                 # write-row try-locks
+        "random_stores": n_writes + n_wgroups,       # new values + publishing words
+        "stream_bytes": n_ops * (16 + 8) + batch.n_txns * (8 + 32),
+    }
+
+
+def run_probes(ctx, binding, quick=False) -> dict:
+    """Self-measured rates of the memory operations the hot path is made of."""
+    n_cu, _ = binding.cc_device_info(ctx)
+    threads = n_cu * 8 * 256
+
+    def ops_of(n):
+        per = ((n + threads - 1) // threads + 3) // 4 * 4
+        return threads * per
+
+    out = {}
+    fp = 1 << 30
+    n = 1 << (26 if quick else 28)
+    words = 1
+    while words * 16 <= (2 << 30):
+        words *= 2
+    ms = binding.cc_probe(ctx, "stream", 2 << 30, 0)
+    out["stream_GBps"] = words * 8 / ms / 1e6
+    for name in ("gather", "scatter", "atomic"):
+        ms = binding.cc_probe(ctx, name, fp, n)
+        out[f"{name}_Gops"] = ops_of(n) / ms / 1e6
+    rounds = 4000 if quick else 20000
+    ms = binding.cc_probe(ctx, "handoff", 1 << 20, rounds, 1)
+    out["handoff_ns"] = ms * 1e6 / (2 * rounds)
+    ms = binding.cc_probe(ctx, "commit_handoff", 1 << 20, rounds, 1)
+    out["commit_handoff_ns"] = ms * 1e6 / rounds
+    ms = binding.cc_probe(ctx, "wave_counter", 1 << 20, 1 << 26)
+    out["one_word_atomic_ns"] = ms * 1e6 / (threads // 64 * (((1 << 26) + threads - 1) // threads + 3) // 4 * 4)
+    return {k: round(v, 3) for k, v in out.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +123,7 @@ def main():
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probes", action="store_true", help="only run the memory micro-benchmarks")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -79,6 +133,12 @@ def main():
 
     import torch
     from paper_2406_10158_amd import binding, workload
+
+    if args.probes:
+        ctx = binding.cc_init(0)
+        print(json.dumps({"probes": run_probes(ctx, binding)}))
+        binding.cc_destroy(ctx)
+        return
 
     t_gen = time.time()
     tables, batch = workload.kv_workload(n_rows=args.rows, n_fields=args.fields, n_txns=args.txns, ops=args.ops,
@@ -94,7 +154,7 @@ def main():
     for _ in range(args.warmup):
         eng.run(bid, **params)
     torch.cuda.synchronize()
-    kernel_ns, run_ns, attempts, p50, p99 = [], [], [], [], []
+    kernel_ns, run_ns, attempts, p50, p99, passes = [], [], [], [], [], []
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     t0 = time.perf_counter()
@@ -105,7 +165,9 @@ def main():
         attempts.append(st["attempts"])
         p50.append(st["lat_p50_ns"])
         p99.append(st["lat_p99_ns"])
-        print(f"[bench] step: {st['run_ns'] / 1e6:.2f} ms, attempts {st['attempts']}", file=sys.stderr, flush=True)
+        passes.append(st["passes"])
+        print(f"[bench] step: {st['run_ns'] / 1e6:.2f} ms, attempts {st['attempts']}, passes {st['passes']}",
+              file=sys.stderr, flush=True)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -113,19 +175,35 @@ def main():
     ms_per_step = ms_total / args.steps
     value = batch.n_txns / (ms_per_step / 1e3)
 
+    # HBM roofline of the transaction kernel (algorithmic bytes / its time)
     alg = algorithmic_bytes(batch)
-    k_s = float(np.mean(kernel_ns)) * 1e-9
-    achieved = alg / k_s / 1e9
+    k_step_s = float(np.mean(kernel_ns)) * 1e-9
+    launches = float(np.mean(passes))
+    achieved = alg / k_step_s / 1e9
     traffic = None
     if os.path.exists(args.traffic_json):
         with open(args.traffic_json) as f:
             tj = json.load(f)
-        key = f"{args.scheme}:{args.theta}:{args.rows}x{args.fields}:{args.txns}x{args.ops}"
-        traffic = tj.get(key)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": "txn_kernel", "algorithmic_bytes_per_launch": alg,
-                "kernel_ms": round(k_s * 1e3, 3)}
+        traffic = tj.get(f"{args.scheme}:{args.theta}:{args.rows}x{args.fields}:{args.txns}x{args.ops}")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
+                "kernel": "txn_kernel", "launches_per_step": launches,
+                "algorithmic_bytes_per_launch": int(alg / launches),
+                "avg_launch_ms": round(k_step_s * 1e3 / launches, 4)}
+
+    # measured random-access / atomic roofline and hot-row contention bound
+    probes = run_probes(eng.ctx, binding, quick=True)
+    acc = access_counts(batch)
+    t_roof = (acc["random_loads"] / (probes["gather_Gops"] * 1e9) + acc["random_atomics"] / (probes["atomic_Gops"] * 1e9)
+              + acc["random_stores"] / (probes["scatter_Gops"] * 1e9) + acc["stream_bytes"] / (probes["stream_GBps"] * 1e9))
+    x_roof = batch.n_txns / t_roof
+    hot_row, h = workload.hottest_row_writes(batch)
+    x_cont = batch.n_txns / (h * probes["commit_handoff_ns"] * 1e-9) if h else float("inf")
+    eff = min(x_roof, x_cont)
+    measured = {"random_access_roof_txn_per_s": round(x_roof, 1), "hot_row_writes_H": h,
+                "t_h_ns": probes["commit_handoff_ns"], "contention_bound_txn_per_s": round(x_cont, 1),
+                "effective_roof_txn_per_s": round(eff, 1), "active_bound": "contention" if x_cont < x_roof else "random-access",
+                "frac_of_effective": round(value / eff, 4), "probes": probes, "per_batch_accesses": acc}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -150,8 +228,9 @@ def main():
         "p50_commit_latency_ms": round(float(np.median(p50)) / 1e6, 4),
         "p99_commit_latency_ms": round(float(np.median(p99)) / 1e6, 4),
         "abort_rate": round((float(np.mean(attempts)) - batch.n_txns) / batch.n_txns, 4),
-        "kernel_only_txn_per_s": round(batch.n_txns / k_s, 1),
+        "kernel_only_txn_per_s": round(batch.n_txns / k_step_s, 1),
         "roofline": roofline,
+        "measured_roofline": measured,
         "cpu_baseline": cpu,
         "host_wall_s": round(wall, 3),
     }

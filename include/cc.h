@@ -143,7 +143,7 @@ enum cc_mode { CC_MODE_PLAIN = 0, CC_MODE_EPOCH = 1 };
 typedef struct {
   uint32_t lanes_per_txn; /* lanes cooperating on one transaction: 1, 4, 16, 64; 0 = smallest >= longest txn */
   uint32_t waves_per_wg;  /* 64-lane wavefronts per workgroup, 1..16; 0 = 4 */
-  uint32_t grid;          /* workgroups launched; 0 = enough to fill every compute unit */
+  uint32_t grid;          /* workgroups of the first pass; 0 = one per compute unit */
   uint32_t mode;          /* enum cc_mode */
   uint64_t max_attempts;  /* give up (CC_E_LIVELOCK) after this many attempts of one txn; 0 = 1<<24 */
   uint32_t max_epochs;    /* CC_MODE_EPOCH: epochs before CC_E_LIVELOCK; 0 = 1<<20 */
@@ -266,6 +266,11 @@ cc_status cc_release_batch(cc_ctx *ctx, uint64_t batch_id);
  *   CC_PROBE_WAVE_COUNTER  n_ops / 64 fetch_adds on one word, one per wavefront
  *   CC_PROBE_HANDOFF       n_ops ping-pong rounds on one word between two
  *                          workgroups `peer` apart (peer 1: another XCD; 8: same XCD)
+ *   CC_PROBE_COMMIT_HANDOFF n_ops rounds of the OCC commit critical section on
+ *                          one row (lock, value read + ticket, validation read,
+ *                          value store, publish), alternating between two
+ *                          workgroups `peer` apart: ms / n_ops is the hot-row
+ *                          hand-off time t_h
  * Random addresses are uniform over the largest power-of-two number of words
  * that fits footprint_bytes.  *ms receives the kernel time (HIP events).
  * Allocates and frees its own buffers.  CC_E_LIVELOCK if a hand-off turn
@@ -279,7 +284,8 @@ enum cc_probe_kind {
   CC_PROBE_ATOMIC = 4,
   CC_PROBE_SAME_WORD = 5,
   CC_PROBE_WAVE_COUNTER = 6,
-  CC_PROBE_HANDOFF = 7
+  CC_PROBE_HANDOFF = 7,
+  CC_PROBE_COMMIT_HANDOFF = 8
 };
 cc_status cc_probe(cc_ctx *ctx, int kind, uint64_t footprint_bytes, uint64_t n_ops, int peer, double *ms);
 

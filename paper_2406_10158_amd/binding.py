@@ -134,7 +134,7 @@ def cc_device_info(ctx):
 
 
 PROBES = {"stream": 0, "gather": 1, "gather_plain": 2, "scatter": 3, "atomic": 4, "same_word": 5,
-          "wave_counter": 6, "handoff": 7}
+          "wave_counter": 6, "handoff": 7, "commit_handoff": 8}
 
 
 def cc_probe(ctx, kind, footprint_bytes: int, n_ops: int, peer: int = 1) -> float:

@@ -230,8 +230,9 @@ cc_status cc_destroy(cc_ctx *c) {
 
 cc_status cc_probe(cc_ctx *c, int kind, uint64_t footprint_bytes, uint64_t n_ops, int peer, double *ms) {
   if (!c || !ms) return CC_E_INVAL;
-  if (kind < CC_PROBE_STREAM || kind > CC_PROBE_HANDOFF) return fail(c, CC_E_INVAL, "unknown probe");
-  if (footprint_bytes < 4096 || (kind == CC_PROBE_HANDOFF && (peer < 1 || peer > 64)))
+  if (kind < CC_PROBE_STREAM || kind > CC_PROBE_COMMIT_HANDOFF) return fail(c, CC_E_INVAL, "unknown probe");
+  const bool pair = kind == CC_PROBE_HANDOFF || kind == CC_PROBE_COMMIT_HANDOFF;
+  if (footprint_bytes < 4096 || (pair && (peer < 1 || peer > 64)))
     return fail(c, CC_E_INVAL, "bad probe size or peer");
   if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
   uint64_t err = 0;

@@ -79,6 +79,46 @@ __global__ void __launch_bounds__(64) probe_handoff(uint64_t *flag, uint64_t rou
   }
 }
 
+// The OCC commit critical section on one hot row, handed back and forth
+// between lane 0 of block 0 and lane 0 of block `peer`: wait until the row's
+// word carries the previous round's version (bounded), then lock it with
+// fetch_or, read the row's value and draw a ticket, re-read a second word
+// (the validation read), store the new value, wait for completion and
+// publish the word.  The time per round is the shortest interval between two
+// commits on one row that this lock / ticket / validate / install sequence
+// allows: the hot-row hand-off time t_h.
+__global__ void __launch_bounds__(64) probe_commit_handoff(uint64_t *buf, uint64_t rounds, int peer,
+                                                           uint64_t spin_limit, uint64_t *err) {
+  if (threadIdx.x != 0) return;
+  int side = -1;
+  if (blockIdx.x == 0) side = 0;
+  if ((int)blockIdx.x == peer) side = 1;
+  if (side < 0) return;
+  uint64_t *word = buf, *value = buf + 64, *ticket = buf + 128, *other = buf + 192 + 16 * side;
+  const uint64_t LOCKBIT = 1ull << 63;
+  for (uint64_t r = (uint64_t)side; r < rounds; r += 2) {
+    uint64_t spins = 0;
+    while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != r) {
+      if (++spins > spin_limit) {
+        __hip_atomic_store(err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+      }
+    }
+    const uint64_t old = __hip_atomic_fetch_or(word, LOCKBIT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    const uint64_t v = __hip_atomic_load(value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t t = __hip_atomic_fetch_add(ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    const uint64_t o = __hip_atomic_load(other, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(value, v + 1 + (o == 0x5A5Aull ? t + old : 0ull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    __hip_atomic_store(word, r + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 __global__ void fill_kernel(uint64_t *p, uint64_t n, uint64_t v) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
@@ -123,6 +163,10 @@ hipError_t run_probe(hipStream_t s, int kind, uint64_t footprint_bytes, uint64_t
       hipLaunchKernelGGL(probe_handoff, dim3((unsigned)(peer + 1)), dim3(64), 0, s, buf, n_ops, peer,
                          (uint64_t)1 << 20, aux + 4096);
       break;
+    case 8:
+      hipLaunchKernelGGL(probe_commit_handoff, dim3((unsigned)(peer + 1)), dim3(64), 0, s, buf, n_ops, peer,
+                         (uint64_t)1 << 20, aux + 4096);
+      break;
     default:
       break;
   }
@@ -131,7 +175,7 @@ hipError_t run_probe(hipStream_t s, int kind, uint64_t footprint_bytes, uint64_t
   if (e == hipSuccess) e = hipEventSynchronize(b);
   float ms = 0;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-  if (e == hipSuccess && kind == 7) e = hipMemcpy(err_out, aux + 4096, sizeof(uint64_t), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && (kind == 7 || kind == 8)) e = hipMemcpy(err_out, aux + 4096, sizeof(uint64_t), hipMemcpyDeviceToHost);
   *ms_out = ms;
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
