@@ -152,6 +152,8 @@ typedef struct {
   uint32_t defer_after;   /* CC_MODE_PLAIN: attempts of a transaction within one pass before it is deferred
                              to the next pass, which runs 8x fewer workgroups (the last pass runs one
                              wavefront and never defers); 0 = 16 */
+  uint64_t ts_start;      /* first value of the run's ticket / timestamp counter (0 for normal runs; a
+                             large value forces the 31-bit TO/MVCC timestamp-overflow path) */
 } cc_run_params;
 
 /* Counters reported by cc_stats (index: meaning). */

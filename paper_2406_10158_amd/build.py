@@ -4,6 +4,7 @@ Usage: python -m paper_2406_10158_amd.build
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -13,7 +14,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcc.so")
-SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "roofline.hip"), os.path.join(CSRC, "api.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in
+           ("txn_occ.hip", "txn_2pl.hip", "txn_to.hip", "txn_mvcc.hip", "txn_tictoc.hip", "kernels.hip",
+            "roofline.hip", "api.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else "hipcc")
 ARCH = "gfx950"
 # Packed FP32 instructions are disabled in all device code.
@@ -25,19 +28,27 @@ def build(verbose: bool = False) -> str:
     """Compile every source and link libcc.so in-tree; always rebuilds."""
     tmpdir = os.path.join(PKG, "_build")
     os.makedirs(tmpdir, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
         cmd = [HIPCC, f"--offload-arch={ARCH}", *COMMON, "-c", src, "-o", obj]
         if src.endswith(".hip"):
             cmd[1:1] = DEVICE_FLAGS
+        cmds.append((src, cmd))
+        objs.append(obj)
+
+    def compile_one(item):
+        src, cmd = item
         if verbose:
             print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            sys.stderr.write(r.stdout + r.stderr)
-            raise RuntimeError(f"hipcc failed on {src}")
-        objs.append(obj)
+        return src, subprocess.run(cmd, capture_output=True, text=True)
+
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as pool:
+        for src, r in pool.map(compile_one, cmds):
+            if r.returncode != 0:
+                sys.stderr.write(r.stdout + r.stderr)
+                raise RuntimeError(f"hipcc failed on {src}")
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -32,6 +32,7 @@ struct Batch {
   DevOutcome *d_out = nullptr;
   int64_t *d_reads = nullptr;
   uint32_t *d_list = nullptr;  // pending transactions between passes
+  uint64_t *d_nodes = nullptr; // MVCC history nodes (3 words per op)
   bool ran = false;
   uint64_t stats[CC_N_STATS] = {};
 };
@@ -106,7 +107,9 @@ void free_batch(Batch &b) {
   if (b.d_out) (void)hipFree(b.d_out);
   if (b.d_reads) (void)hipFree(b.d_reads);
   if (b.d_list) (void)hipFree(b.d_list);
+  if (b.d_nodes) (void)hipFree(b.d_nodes);
   b.d_list = nullptr;
+  b.d_nodes = nullptr;
   b.d_ops = nullptr;
   b.d_txns = nullptr;
   b.d_out = nullptr;
@@ -417,7 +420,8 @@ cc_status cc_submit_batch(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, const 
       (e = alloc((void **)&b.d_txns, n_txns * sizeof(DevTxn))) != hipSuccess ||
       (e = alloc((void **)&b.d_out, n_txns * sizeof(DevOutcome))) != hipSuccess ||
       (e = alloc((void **)&b.d_reads, n_ops * sizeof(int64_t))) != hipSuccess ||
-      (e = alloc((void **)&b.d_list, n_txns * sizeof(uint32_t))) != hipSuccess) {
+      (e = alloc((void **)&b.d_list, n_txns * sizeof(uint32_t))) != hipSuccess ||
+      (scheme == CC_MVCC && (e = alloc((void **)&b.d_nodes, n_ops * 3 * sizeof(uint64_t))) != hipSuccess)) {
     free_batch(b);
     return hip_fail(c, e, "batch allocation");
   }
@@ -457,7 +461,12 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   a.n_txns = b.n_txns;
   a.data = c->d_data;
   a.words = c->d_words;
+  if (b.scheme == CC_MVCC && !c->d_aux) {
+    HIP_OR(c, hipMalloc(&c->d_aux, std::max<uint64_t>(c->total_rows, 1) * sizeof(uint64_t)));
+  }
   a.aux = c->d_aux;
+  a.nodes = b.d_nodes;
+  a.n_nodes = b.scheme == CC_MVCC ? b.n_ops : 0;
   a.out = b.d_out;
   a.reads = b.d_reads;
   a.ctl = c->d_ctl;
@@ -472,7 +481,8 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   a.list = nullptr;
 
   HIP_OR(c, hipEventRecord(c->ev[0], c->stream));
-  HIP_OR(c, launch_init(c->stream, c->d_words, c->total_rows, nullptr, 0, b.d_out, b.n_txns, c->d_ctl));
+  HIP_OR(c, launch_init(c->stream, c->d_words, c->total_rows, c->d_aux, b.scheme == CC_MVCC ? c->total_rows : 0,
+                        b.d_out, b.n_txns, c->d_ctl, p.ts_start));
   Ctl h{};
   double kernel_ms = 0;
   uint32_t passes = 0;
@@ -524,7 +534,7 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   b.stats[CC_STAT_ABORT_VALID] = h.stats[DS_ABORT_VALID];
   b.stats[CC_STAT_KERNEL_NS] = (uint64_t)(kernel_ms * 1e6);
   b.stats[CC_STAT_RUN_NS] = (uint64_t)((double)ms_run * 1e6);
-  b.stats[CC_STAT_TICKETS] = h.ticket;
+  b.stats[CC_STAT_TICKETS] = h.ticket - p.ts_start;
   b.stats[CC_STAT_MAX_ATTEMPTS] = h.stats[DS_MAX_ATTEMPTS];
   b.stats[CC_STAT_PASSES] = passes;
   b.stats[CC_STAT_DEFERRED] = h.stats[DS_DEFERRED];

@@ -73,6 +73,8 @@ struct RunArgs {
   int64_t *data;    // value arena
   uint64_t *words;  // one control word per global row
   uint64_t *aux;    // second word per row (MVCC version pointer)
+  uint64_t *nodes;  // MVCC history nodes, 3 words per op of the batch
+  uint64_t n_nodes;
   DevOutcome *out;
   int64_t *reads;   // per op read value
   Ctl *ctl;
@@ -87,7 +89,7 @@ struct RunArgs {
 
 // Host-side launchers (kernels.hip).
 hipError_t launch_init(hipStream_t s, uint64_t *words, uint64_t n_words, uint64_t *aux, uint64_t n_aux,
-                       DevOutcome *out, uint64_t n_out, Ctl *ctl);
+                       DevOutcome *out, uint64_t n_out, Ctl *ctl, uint64_t ticket_start);
 
 // Between passes: list the transactions neither committed nor given up, and
 // reset the claim counter.  ctl->pending_n receives the count.
@@ -98,6 +100,17 @@ hipError_t launch_compact(hipStream_t s, const DevOutcome *out, uint64_t n_txns,
 // (lanes, ops-per-lane) combination.
 hipError_t launch_txn(hipStream_t s, int scheme, int lanes, int max_ops, int waves_per_wg, int grid,
                       bool strict, const RunArgs &a, int n_cu, int *grid_used);
+
+// Per-scheme launchers (txn_<scheme>.hip).
+#define CCE_DECLARE_LAUNCH(NAME)                                                                           \
+  hipError_t NAME(hipStream_t s, int lanes, int max_ops, int waves_per_wg, int grid, bool strict, const RunArgs &a, \
+                  int n_cu, int *grid_used);
+CCE_DECLARE_LAUNCH(launch_txn_occ)
+CCE_DECLARE_LAUNCH(launch_txn_2pl)
+CCE_DECLARE_LAUNCH(launch_txn_to)
+CCE_DECLARE_LAUNCH(launch_txn_mvcc)
+CCE_DECLARE_LAUNCH(launch_txn_tictoc)
+#undef CCE_DECLARE_LAUNCH
 
 // Memory micro-benchmarks (roofline.hip); see cc_probe in cc.h.
 hipError_t run_probe(hipStream_t s, int kind, uint64_t footprint_bytes, uint64_t n_ops, int peer, double *ms_out,

@@ -1,0 +1,442 @@
+// One execution attempt of a transaction under each concurrency-control
+// scheme.  Every function is called by all 64 lanes of a wavefront; `active`
+// says whether this lane's team runs an attempt now.  Rounds are
+// wavefront-synchronous and separated by ordering points; a team votes on
+// abort with a ballot over its lanes.  All schemes are no-wait: a conflict
+// aborts the attempt (waiting is unsafe when the holder may be a lane of the
+// same wavefront, which cannot make progress while this one spins -- paper
+// Section 3.4, "Spin Lock").  Returned through hi/lo: the serial key.
+#pragma once
+
+#include "device.h"
+
+namespace cce {
+
+// ===========================================================================
+// OCC, Silo-style (paper Section 2 "Optimistic Concurrency Control";
+// Section 3.5 "OCC"; control word per row = lock bit + 63-bit TID, Table 2).
+//
+//   R1  write rows: try-lock with fetch_or(LOCK); the returned word is the
+//       row's committed TID, a set lock bit means it is held -> abort.
+//       read-only rows: load the TID word; locked -> abort.
+//   R2  read every operation's value (write rows under our lock) and draw the
+//       serial ticket, which is also the TID our writes will carry.
+//   R3  validate: each read-only row still has the observed word, and every
+//       observed TID is older than our ticket; else abort (release locks).
+//   R4  store new values, wait, then store word = ticket on each write row:
+//       publishes the values and releases the lock in one store.
+// The paper's Silo locks the write set at validation time, after its read
+// phase.  Read/write sets here are known before execution (Section 4.1,
+// "Constraints"), so write rows are locked first and read under the lock,
+// which shortens the time a hot row is held or exposed to invalidation.
+// Serial key (0, ticket): tickets are drawn while every write lock is held
+// and before validation, so conflicting transactions are ordered by ticket.
+// ===========================================================================
+constexpr uint64_t OCC_LOCK = 1ull << 63;
+
+template <int L, int K, bool STRICT>
+__device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a,
+                                           uint64_t *hi, uint64_t *lo) {
+  bool fail = false;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    s.got[k] = false;
+    if (active && s.valid[k] && op_leader(s.rowk[k])) {
+      uint64_t *w = a.words + op_row(s.rowk[k]);
+      if (op_written(s.rowk[k])) {
+        const uint64_t old = or_word(w, OCC_LOCK);
+        s.v[k] = old;
+        s.got[k] = !(old & OCC_LOCK);
+        fail |= !s.got[k];
+      } else {
+        const uint64_t o = ld_word(w);
+        s.v[k] = o;
+        fail |= (o & OCC_LOCK) != 0;
+      }
+    }
+  }
+  order_point<STRICT>();
+  const bool lock_fail = t.any(fail);
+  const bool alive = active && !lock_fail;
+  if (active && lock_fail) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (s.got[k]) st_word(a.words + op_row(s.rowk[k]), s.v[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (alive && s.valid[k]) s.x[k] = ld_val(a.data + s.elem[k]);
+  const uint64_t ticket = t.claim(&a.ctl->ticket, alive, 1) + 1;
+  order_point<STRICT>();
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (alive && s.valid[k] && op_leader(s.rowk[k])) {
+      if (!op_written(s.rowk[k])) bad |= ld_word(a.words + op_row(s.rowk[k])) != s.v[k];
+      bad |= (s.v[k] & ~OCC_LOCK) >= ticket;
+    }
+  }
+  const bool valid_fail = t.any(bad);
+  const bool commit = alive && !valid_fail;
+  if (alive && valid_fail) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (s.got[k]) st_word(a.words + op_row(s.rowk[k]), s.v[k]);
+  }
+  install_values<L, K>(t, s, commit, a);
+  order_point<STRICT>();
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (commit && s.got[k]) st_word(a.words + op_row(s.rowk[k]), ticket);
+  *hi = 0;
+  *lo = ticket;
+  if (!active) return COMMIT;
+  return lock_fail ? ABORT_LOCK : (valid_fail ? ABORT_VALID : COMMIT);
+}
+
+// ===========================================================================
+// Two-phase locking, no-wait (paper Section 2 "Two-Phase Locking"; Section
+// 3.5 "Two-Phase Locking"; lock word = shared-mode bit, 31-bit holder
+// count, 31-bit holder, Table 2).  Layout here: bit 63 exclusive, bits 62-32
+// holder (transaction id), bits 30-0 shared-holder count.
+//   R1  exclusive rows: CAS 0 -> EXCL|holder; shared rows: fetch_add(1) and
+//       abort if the exclusive bit was set (the increment is undone).
+//   R2  read values under the locks; draw the ticket at the lock point.
+//   R3  store new values, wait, release (clear exclusive bits with fetch_and,
+//       so concurrent failed shared increments are not lost; fetch_add(-1)).
+// Serial key (0, ticket): strict 2PL, ticket drawn while all locks are held.
+// ===========================================================================
+constexpr uint64_t TPL_EXCL = 1ull << 63;
+constexpr uint64_t TPL_COUNT = (1ull << 31) - 1ull;
+
+template <int L, int K, bool STRICT>
+__device__ __forceinline__ int tpl_attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a,
+                                           uint32_t txn, uint64_t *hi, uint64_t *lo) {
+  bool fail = false;
+  bool shared[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    s.got[k] = false;
+    shared[k] = false;
+    if (active && s.valid[k] && op_leader(s.rowk[k])) {
+      uint64_t *w = a.words + op_row(s.rowk[k]);
+      if (op_written(s.rowk[k])) {
+        uint64_t expected = 0;
+        s.got[k] = cas_word(w, &expected, TPL_EXCL | ((uint64_t)(txn & 0x7FFFFFFFu) << 32));
+        fail |= !s.got[k];
+      } else {
+        const uint64_t old = add_word(w, 1ull);
+        shared[k] = true;  // our increment is in the word until we take it out
+        s.got[k] = !(old & TPL_EXCL);
+        fail |= !s.got[k];
+      }
+    }
+  }
+  order_point<STRICT>();
+  const bool lock_fail = t.any(fail);
+  const bool alive = active && !lock_fail;
+  if (active && lock_fail) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      uint64_t *w = a.words + op_row(s.rowk[k]);
+      if (shared[k]) add_word(w, ~0ull);
+      else if (s.got[k]) and_word(w, TPL_COUNT);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (alive && s.valid[k]) s.x[k] = ld_val(a.data + s.elem[k]);
+  const uint64_t ticket = t.claim(&a.ctl->ticket, alive, 1) + 1;
+  order_point<STRICT>();
+  install_values<L, K>(t, s, alive, a);
+  order_point<STRICT>();
+  if (alive) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      uint64_t *w = a.words + op_row(s.rowk[k]);
+      if (shared[k]) add_word(w, ~0ull);
+      else if (s.got[k]) and_word(w, TPL_COUNT);
+    }
+  }
+  *hi = 0;
+  *lo = ticket;
+  if (!active) return COMMIT;
+  return lock_fail ? ABORT_LOCK : COMMIT;
+}
+
+// ===========================================================================
+// Basic timestamp ordering, and its multi-version form (paper Section 2
+// "Timestamp Ordering" and "MVCC"; Section 3.5 "Basic TO" and "MVCC";
+// word = commit/dirty bit, 31-bit RTS, 31-bit WTS, Table 2; MVCC adds a
+// 64-bit version pointer per row).  Layout: bit 63 dirty (an uncommitted
+// write holds the row), bits 61-31 RTS, bits 30-0 WTS.
+//   R0  draw a timestamp ts for this attempt (one global counter).
+//   R1  write rows: CAS loop -- abort if dirty or ts < RTS or ts < WTS, else
+//       set dirty.  read rows: CAS loop -- abort if dirty (no waiting for the
+//       writer) or ts < WTS (TO; MVCC instead reads an older version); else
+//       raise RTS to ts.
+//   R2  read values (MVCC, older version: also the version pointer).
+//   R3  re-check read rows: not dirty and the same WTS, so the value read
+//       belongs to the version checked in R1.  MVCC old-version reads walk
+//       the version chain back to the newest writer with timestamp <= ts.
+//   R4  (MVCC: record each write's pre-image in its history node and link
+//       it) store new values, wait, publish word = {RTS=ts, WTS=ts}.
+// Serial key (0, ts).  Timestamps are relative to the run and must stay
+// below 2^31; reaching it stops the run with CC_E_TS_OVERFLOW.
+// History nodes (MVCC): one per write operation, 3 words {prev node,
+// writer ts | cell << 32, pre-image}; node i+1 belongs to op i (0 = none).
+// A chain lists a row's writers newest first; a reader at ts starts from the
+// current value and undoes, field by field, every writer newer than ts.
+// ===========================================================================
+constexpr uint64_t TO_DIRTY = 1ull << 63;
+constexpr uint64_t TO_MASK31 = (1ull << 31) - 1ull;
+__device__ __forceinline__ uint64_t to_rts(uint64_t w) { return (w >> 31) & TO_MASK31; }
+__device__ __forceinline__ uint64_t to_wts(uint64_t w) { return w & TO_MASK31; }
+__device__ __forceinline__ uint64_t to_word(uint64_t rts, uint64_t wts) { return (rts << 31) | wts; }
+constexpr int MVCC_MAX_WALK = 1 << 16;
+
+template <int L, int K, bool STRICT, bool MV>
+__device__ __forceinline__ int to_attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a,
+                                          uint64_t *hi, uint64_t *lo) {
+  const uint64_t ts = t.claim(&a.ctl->ticket, active, 1) + 1;
+  const bool overflow = active && ts > TO_MASK31;
+  bool fail = overflow;
+  bool old_ver[K];  // MVCC: this op reads a version older than the current one
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    s.got[k] = false;
+    old_ver[k] = false;
+    const bool lead = op_leader(s.rowk[k]);
+    // MVCC followers of read rows also look at the word, to pick the version
+    const bool look = lead || (MV && !op_written(s.rowk[k]));
+    if (active && !overflow && s.valid[k] && look) {
+      uint64_t *wp = a.words + op_row(s.rowk[k]);
+      uint64_t w = ld_word(wp);
+      bool done = false, bad = false;
+      for (int it = 0; it < CAS_RETRIES && !done && !bad; ++it) {
+        if (w & TO_DIRTY) {
+          bad = true;
+        } else if (op_written(s.rowk[k])) {
+          if (ts < to_rts(w) || ts < to_wts(w)) {
+            bad = true;
+          } else if (cas_word(wp, &w, w | TO_DIRTY)) {
+            done = true;
+            s.got[k] = true;
+          }
+        } else if (ts < to_wts(w)) {
+          if (MV) {
+            old_ver[k] = true;
+            done = true;
+          } else {
+            bad = true;
+          }
+        } else if (!lead || to_rts(w) >= ts) {
+          done = true;
+        } else if (cas_word(wp, &w, to_word(ts, to_wts(w)))) {
+          done = true;
+        }
+      }
+      s.v[k] = w;
+      fail |= bad || !done;
+    }
+  }
+  order_point<STRICT>();
+  const bool lock_fail = t.any(fail);
+  const bool alive = active && !lock_fail;
+  if (active && lock_fail) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (s.got[k]) st_word(a.words + op_row(s.rowk[k]), s.v[k]);
+  }
+  uint64_t ptr[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    ptr[k] = 0;
+    if (alive && s.valid[k]) {
+      s.x[k] = ld_val(a.data + s.elem[k]);
+      if (MV && old_ver[k]) ptr[k] = ld_word(a.aux + op_row(s.rowk[k]));
+    }
+  }
+  order_point<STRICT>();
+  bool bad = false;
+  bool same[K];  // the row's word did not change between R1 and R3
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    same[k] = true;
+    const bool look = op_leader(s.rowk[k]) || (MV && !op_written(s.rowk[k]));
+    if (alive && s.valid[k] && look && !op_written(s.rowk[k])) {
+      const uint64_t w2 = ld_word(a.words + op_row(s.rowk[k]));
+      same[k] = !(w2 & TO_DIRTY) && to_wts(w2) == to_wts(s.v[k]);
+      bad |= !same[k];
+    }
+  }
+  if (MV) {
+    // Old-version reads walk the chain from the pointer read in R2.  Only
+    // when the word did not change: then no writer linked nodes before our
+    // R3 load, and writers after it link above that pointer, so the nodes
+    // walked are complete.  Indices and length are still bounded.
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (alive && old_ver[k] && same[k]) {
+        const uint32_t cell = s.elem[k];
+        int64_t val = s.x[k];
+        uint64_t p = ptr[k];
+        int steps = 0;
+        while (p != 0 && p <= a.n_nodes && steps < MVCC_MAX_WALK) {
+          const uint64_t *node = a.nodes + 3 * (p - 1);
+          const uint64_t tf = ld_word(node + 1);
+          if ((tf & 0xFFFFFFFFull) <= ts) break;
+          if ((uint32_t)(tf >> 32) == cell) val = (int64_t)ld_word(node + 2);
+          p = ld_word(node);
+          ++steps;
+        }
+        if (p > a.n_nodes || steps >= MVCC_MAX_WALK) bad = true;
+        s.x[k] = val;
+      }
+    }
+  }
+  const bool valid_fail = t.any(bad);
+  const bool commit = alive && !valid_fail;
+  if (alive && valid_fail) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (s.got[k]) st_word(a.words + op_row(s.rowk[k]), s.v[k]);
+  }
+  if (MV) {
+    // history nodes for every write op: pre-image, writer ts, cell; link with
+    // an exchange on the row's version pointer (we hold the row, so only our
+    // own lanes link concurrently)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (commit && s.valid[k] && op_kind(s.rowk[k]) != CC_READ) {
+        uint64_t *node = a.nodes + 3 * (uint64_t)s.oi[k];
+        st_word(node + 1, ts | ((uint64_t)s.elem[k] << 32));
+        st_word(node + 2, (uint64_t)s.x[k]);
+        const uint64_t prev = xchg_word(a.aux + op_row(s.rowk[k]), (uint64_t)s.oi[k] + 1);
+        st_word(node, prev);
+      }
+    }
+  }
+  install_values<L, K>(t, s, commit, a);
+  order_point<STRICT>();
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (commit && s.got[k]) st_word(a.words + op_row(s.rowk[k]), to_word(ts, ts));
+  *hi = 0;
+  *lo = ts;
+  if (!active) return COMMIT;
+  if (overflow) return TS_OVERFLOW;
+  return lock_fail ? ABORT_LOCK : (valid_fail ? ABORT_VALID : COMMIT);
+}
+
+// ===========================================================================
+// TicToc (paper Section 2 "Optimistic Concurrency Control"; Section 3.5
+// "OCC"; word = lock bit, 15-bit delta, 48-bit WTS with RTS = WTS + delta,
+// Table 2).  Layout: bit 63 lock, bits 62-48 delta, bits 47-0 WTS.
+//   R1  write rows: try-lock with fetch_or (abort if held); read rows: load
+//       the word (abort if locked).
+//   R2  read values; draw a ticket (tie-breaker for equal commit
+//       timestamps); commit_ts = max over write rows of RTS+1 and over read
+//       rows of WTS (team maximum).
+//   R3  for each read row with RTS < commit_ts: the row must still carry the
+//       observed WTS and be unlocked; extend its RTS to commit_ts by CAS (if
+//       the delta would not fit in 15 bits, WTS is raised instead -- only
+//       other readers of the old WTS are affected, and they abort).
+//   R4  store values, wait, publish word = {WTS = commit_ts, delta = 0}.
+// Serial key (commit_ts, ticket).
+// ===========================================================================
+constexpr uint64_t TT_LOCK = 1ull << 63;
+constexpr uint64_t TT_WTS_MASK = (1ull << 48) - 1ull;
+constexpr uint64_t TT_DELTA_MAX = (1ull << 15) - 1ull;
+__device__ __forceinline__ uint64_t tt_wts(uint64_t w) { return w & TT_WTS_MASK; }
+__device__ __forceinline__ uint64_t tt_rts(uint64_t w) { return tt_wts(w) + ((w >> 48) & TT_DELTA_MAX); }
+
+template <int L, int K, bool STRICT>
+__device__ __forceinline__ int tictoc_attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a,
+                                              uint64_t *hi, uint64_t *lo) {
+  bool fail = false;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    s.got[k] = false;
+    if (active && s.valid[k] && op_leader(s.rowk[k])) {
+      uint64_t *w = a.words + op_row(s.rowk[k]);
+      if (op_written(s.rowk[k])) {
+        const uint64_t old = or_word(w, TT_LOCK);
+        s.v[k] = old;
+        s.got[k] = !(old & TT_LOCK);
+        fail |= !s.got[k];
+      } else {
+        const uint64_t o = ld_word(w);
+        s.v[k] = o;
+        fail |= (o & TT_LOCK) != 0;
+      }
+    }
+  }
+  order_point<STRICT>();
+  const bool lock_fail = t.any(fail);
+  const bool alive = active && !lock_fail;
+  if (active && lock_fail) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (s.got[k]) st_word(a.words + op_row(s.rowk[k]), s.v[k]);
+  }
+  uint64_t cts = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (alive && s.valid[k]) {
+      s.x[k] = ld_val(a.data + s.elem[k]);
+      if (op_leader(s.rowk[k])) {
+        const uint64_t c = op_written(s.rowk[k]) ? tt_rts(s.v[k]) + 1 : tt_wts(s.v[k]);
+        cts = c > cts ? c : cts;
+      }
+    }
+  }
+  const uint64_t ticket = t.claim(&a.ctl->ticket, alive, 1) + 1;
+  cts = t.max(cts);
+  const bool overflow = alive && cts > TT_WTS_MASK - TT_DELTA_MAX;
+  order_point<STRICT>();
+  bool bad = overflow;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (alive && !overflow && s.valid[k] && op_leader(s.rowk[k]) && !op_written(s.rowk[k]) &&
+        tt_rts(s.v[k]) < cts) {
+      uint64_t *wp = a.words + op_row(s.rowk[k]);
+      uint64_t w = ld_word(wp);
+      bool done = false, b = false;
+      for (int it = 0; it < CAS_RETRIES && !done && !b; ++it) {
+        if (tt_wts(w) != tt_wts(s.v[k]) || (w & TT_LOCK)) {
+          b = true;
+        } else if (tt_rts(w) >= cts) {
+          done = true;
+        } else {
+          uint64_t wts = tt_wts(w), delta = cts - wts;
+          if (delta > TT_DELTA_MAX) {
+            wts = cts - TT_DELTA_MAX;
+            delta = TT_DELTA_MAX;
+          }
+          if (cas_word(wp, &w, wts | (delta << 48))) done = true;
+        }
+      }
+      bad |= b || !done;
+    }
+  }
+  const bool valid_fail = t.any(bad);
+  const bool commit = alive && !valid_fail;
+  if (alive && valid_fail) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (s.got[k]) st_word(a.words + op_row(s.rowk[k]), s.v[k]);
+  }
+  install_values<L, K>(t, s, commit, a);
+  order_point<STRICT>();
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (commit && s.got[k]) st_word(a.words + op_row(s.rowk[k]), cts);
+  *hi = cts;
+  *lo = ticket;
+  if (!active) return COMMIT;
+  if (overflow && !lock_fail) return TS_OVERFLOW;
+  return lock_fail ? ABORT_LOCK : (valid_fail ? ABORT_VALID : COMMIT);
+}
+
+}  // namespace cce

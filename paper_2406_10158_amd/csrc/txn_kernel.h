@@ -1,0 +1,197 @@
+// The plain-batch transaction kernel, templated on lanes per transaction,
+// register slots per lane, scheme and fence strength, and its launcher.
+// Each scheme instantiates it in its own translation unit (txn_<scheme>.hip).
+#pragma once
+
+#include "schemes.h"
+
+namespace cce {
+
+// Largest workgroup a (lanes, ops-per-lane) variant is compiled for: more
+// register slots per lane leave room for fewer wavefronts.
+template <int K>
+struct MaxThreads {
+  static constexpr int value = K <= 1 ? 1024 : (K <= 4 ? 512 : 256);
+};
+
+template <int L, int K, int SCHEME, bool STRICT>
+__device__ __forceinline__ int attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a, uint32_t txn,
+                                       uint64_t *hi, uint64_t *lo) {
+  if constexpr (SCHEME == CC_OCC) return occ_attempt<L, K, STRICT>(t, s, active, a, hi, lo);
+  else if constexpr (SCHEME == CC_2PL_NW) return tpl_attempt<L, K, STRICT>(t, s, active, a, txn, hi, lo);
+  else if constexpr (SCHEME == CC_TO) return to_attempt<L, K, STRICT, false>(t, s, active, a, hi, lo);
+  else if constexpr (SCHEME == CC_MVCC) return to_attempt<L, K, STRICT, true>(t, s, active, a, hi, lo);
+  else return tictoc_attempt<L, K, STRICT>(t, s, active, a, hi, lo);
+}
+
+// ---------------------------------------------------------------------------
+// Plain batch kernel: persistent teams, in-kernel retry until commit (or
+// deferral to the next, less concurrent pass).
+// ---------------------------------------------------------------------------
+template <int L, int K, int SCHEME, bool STRICT>
+__global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
+  Team<L> t;
+  Slots<K> s;
+  const uint64_t start_clock = a.ctl->start_clock;
+  int64_t txn = -1;         // current transaction (team-uniform)
+  uint32_t attempts = 0;    // attempts of txn so far, all passes
+  uint32_t pass_att = 0;    // attempts of txn in this pass
+  uint64_t ready_at = 0;    // wall-clock tick before which the team waits
+  bool done = false;        // no transactions left for this team
+  uint64_t n_commit = 0, n_att = 0, n_lock = 0, n_valid = 0, n_gave = 0, n_defer = 0, n_ovf = 0, max_att = 0;
+
+  for (;;) {
+    const bool need = txn < 0 && !done;
+    const uint64_t q = t.claim(&a.ctl->queue, need, 1);
+    if (need) {
+      if (q < a.n_txns) {
+        txn = a.list ? (int64_t)a.list[q] : (int64_t)q;
+        attempts = a.pass ? a.out[txn].attempts : 0;
+        pass_att = 0;
+        ready_at = 0;
+      } else {
+        done = true;
+      }
+    }
+    if (ballot(txn >= 0) == 0) break;
+    const uint64_t now = wall_clock64();
+    const bool active = txn >= 0 && now >= ready_at;
+    if (ballot(active) == 0) {
+      __builtin_amdgcn_s_sleep(2);
+      continue;
+    }
+    // stage the transaction's ops in registers (coalesced 16 B loads per team)
+    uint32_t first = 0, n = 0;
+    if (active) {
+      const DevTxn d = a.txns[txn];
+      first = d.first;
+      n = d.n;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint32_t idx = (uint32_t)t.tl + (uint32_t)(k * L);
+      s.valid[k] = active && idx < n;
+      s.oi[k] = first + idx;
+      if (s.valid[k]) {
+        const DevOp op = a.ops[first + idx];
+        s.rowk[k] = op.rowk;
+        s.elem[k] = op.elem;
+        s.arg[k] = op.arg;
+      } else {
+        s.rowk[k] = FOLLOWER_BIT;
+        s.elem[k] = 0;
+        s.arg[k] = 0;
+      }
+      s.x[k] = 0;
+      s.v[k] = 0;
+    }
+    uint64_t key_hi = 0, key_lo = 0;
+    const int r = attempt<L, K, SCHEME, STRICT>(t, s, active, a, (uint32_t)(txn < 0 ? 0 : txn), &key_hi, &key_lo);
+    if (active) {
+      ++attempts;
+      ++pass_att;
+      ++n_att;
+      if (r == COMMIT) {
+        if (t.tl == 0) {
+          DevOutcome o;
+          o.status = CC_COMMITTED;
+          o.attempts = attempts;
+          o.serial_hi = key_hi;
+          o.serial_lo = key_lo;
+          const uint64_t dt = wall_clock64() - start_clock;
+          o.commit_ns = (int64_t)((dt * a.ns_per_tick_q16) >> 16);
+          a.out[txn] = o;
+          ++n_commit;
+          max_att = attempts > max_att ? attempts : max_att;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+          if (s.valid[k]) __builtin_nontemporal_store(s.x[k], a.reads + first + t.tl + k * L);
+        txn = -1;
+      } else {
+        if (t.tl == 0) {
+          if (r == ABORT_LOCK) ++n_lock;
+          else if (r == ABORT_VALID) ++n_valid;
+          else ++n_ovf;
+        }
+        if (r == TS_OVERFLOW || attempts >= a.max_attempts || (a.defer_after && pass_att >= a.defer_after)) {
+          // give up (timestamp overflow, attempt limit) or leave the
+          // transaction to the next, less concurrent pass
+          if (t.tl == 0) {
+            a.out[txn].attempts = attempts;
+            if (r == TS_OVERFLOW || attempts >= a.max_attempts) ++n_gave; else ++n_defer;
+            max_att = attempts > max_att ? attempts : max_att;
+          }
+          txn = -1;
+        } else {
+          // randomised exponential back-off
+          const uint32_t sh = pass_att < 12 ? pass_att : 12;
+          const uint64_t span = (uint64_t)a.backoff_ticks << sh;
+          ready_at = now + (mix64(((uint64_t)txn << 20) ^ attempts) % (span + 1));
+        }
+      }
+    }
+  }
+  // one atomic per counter per wavefront (team leaders hold the counts)
+  n_att = t.tl == 0 ? n_att : 0;
+  const uint64_t c0 = wave_sum(n_commit), c1 = wave_sum(n_att), c2 = wave_sum(n_lock), c3 = wave_sum(n_valid),
+                 c4 = wave_sum(n_gave), c5 = wave_max(max_att), c6 = wave_sum(n_defer), c7 = wave_sum(n_ovf);
+  if (t.lane == 0) {
+    if (c0) atomicAdd((unsigned long long *)&a.ctl->stats[DS_COMMITTED], (unsigned long long)c0);
+    if (c1) atomicAdd((unsigned long long *)&a.ctl->stats[DS_ATTEMPTS], (unsigned long long)c1);
+    if (c2) atomicAdd((unsigned long long *)&a.ctl->stats[DS_ABORT_LOCK], (unsigned long long)c2);
+    if (c3) atomicAdd((unsigned long long *)&a.ctl->stats[DS_ABORT_VALID], (unsigned long long)c3);
+    if (c4) atomicAdd((unsigned long long *)&a.ctl->stats[DS_GAVE_UP], (unsigned long long)c4);
+    if (c5) atomicMax((unsigned long long *)&a.ctl->stats[DS_MAX_ATTEMPTS], (unsigned long long)c5);
+    if (c6) atomicAdd((unsigned long long *)&a.ctl->stats[DS_DEFERRED], (unsigned long long)c6);
+    if (c7) atomicAdd((unsigned long long *)&a.ctl->stats[DS_TS_OVERFLOW], (unsigned long long)c7);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch over (lanes per txn, ops per lane, strict)
+// ---------------------------------------------------------------------------
+template <int L, int K, int SCHEME, bool STRICT>
+static hipError_t launch_one(hipStream_t s, int waves_per_wg, int grid, const RunArgs &a, int n_cu, int *grid_used) {
+  auto kern = txn_kernel<L, K, SCHEME, STRICT>;
+  const int block = 64 * waves_per_wg;
+  if (block > MaxThreads<K>::value) return hipErrorInvalidConfiguration;
+  if (grid <= 0) {
+    // default: one workgroup per compute unit.  Measured on the key-value
+    // workload, fuller occupancy only adds conflicting transactions in flight
+    // (more aborts) without adding throughput, at every contention level.
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, 0);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    grid = n_cu;
+  }
+  // never more teams than transactions
+  const uint64_t teams_per_wg = (uint64_t)waves_per_wg * (64 / L);
+  const uint64_t need = (a.n_txns + teams_per_wg - 1) / teams_per_wg;
+  if ((uint64_t)grid > need) grid = (int)(need > 0 ? need : 1);
+  *grid_used = grid;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int SCHEME, bool STRICT>
+static hipError_t dispatch(hipStream_t s, int lanes, int max_ops, int waves_per_wg, int grid, const RunArgs &a,
+                           int n_cu, int *grid_used) {
+  const int need_k = (max_ops + lanes - 1) / lanes;
+#define CCE_TRY(LL, KK)                                                                      \
+  if (lanes == LL && need_k <= KK)                                                           \
+    return launch_one<LL, KK, SCHEME, STRICT>(s, waves_per_wg, grid, a, n_cu, grid_used);
+  CCE_TRY(1, 4)
+  CCE_TRY(1, 16)
+  CCE_TRY(4, 4)
+  CCE_TRY(4, 16)
+  CCE_TRY(16, 1)
+  CCE_TRY(16, 4)
+  CCE_TRY(64, 1)
+  CCE_TRY(64, 4)
+#undef CCE_TRY
+  return hipErrorInvalidValue;
+}
+
+}  // namespace cce
