@@ -338,10 +338,11 @@ __device__ __forceinline__ int to_attempt(const Team<L> &t, Slots<K> &s, bool ac
 //   R2  read values; draw a ticket (tie-breaker for equal commit
 //       timestamps); commit_ts = max over write rows of RTS+1 and over read
 //       rows of WTS (team maximum).
-//   R3  for each read row with RTS < commit_ts: the row must still carry the
-//       observed WTS and be unlocked; extend its RTS to commit_ts by CAS (if
-//       the delta would not fit in 15 bits, WTS is raised instead -- only
-//       other readers of the old WTS are affected, and they abort).
+//   R3  every read row must still carry the observed WTS and be unlocked (so
+//       the value read in R2 is that version's); if its RTS < commit_ts,
+//       extend RTS to commit_ts by CAS (if the delta would not fit in 15
+//       bits, WTS is raised instead -- only other readers of the old WTS are
+//       affected, and they abort).
 //   R4  store values, wait, publish word = {WTS = commit_ts, delta = 0}.
 // Serial key (commit_ts, ticket).
 // ===========================================================================
@@ -398,8 +399,10 @@ __device__ __forceinline__ int tictoc_attempt(const Team<L> &t, Slots<K> &s, boo
   bool bad = overflow;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    if (alive && !overflow && s.valid[k] && op_leader(s.rowk[k]) && !op_written(s.rowk[k]) &&
-        tt_rts(s.v[k]) < cts) {
+    if (alive && !overflow && s.valid[k] && op_leader(s.rowk[k]) && !op_written(s.rowk[k])) {
+      // the value read in R2 belongs to the observed version only if the row
+      // is still unlocked with the same WTS now (a writer installs values
+      // while holding the lock, then publishes a new WTS)
       uint64_t *wp = a.words + op_row(s.rowk[k]);
       uint64_t w = ld_word(wp);
       bool done = false, b = false;
