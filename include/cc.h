@@ -25,8 +25,8 @@
  *     array it passes; the engine copies inputs before the call returns and
  *     never keeps a caller pointer.
  *   - A context is used by one host thread at a time.  Work is issued on the
- *     stream given at cc_init (the default stream if NULL); calls that return
- *     results synchronise that stream.
+ *     stream given at cc_init (if NULL, a stream the context creates with the
+ *     default priority); calls that return results synchronise that stream.
  *   - All table values are int64; arithmetic wraps in two's complement.
  */
 #ifndef CC_H_
@@ -134,7 +134,28 @@ typedef struct {
   void *stream;    /* hipStream_t to issue work on (NULL: the null stream) */
 } cc_config;
 
-enum cc_mode { CC_MODE_PLAIN = 0, CC_MODE_EPOCH = 1 };
+/*
+ * Run modes.
+ *   CC_MODE_PLAIN  the paper's procedure (Section 4.1, "Experimental
+ *                  Procedure"): each transaction is retried in-kernel until it
+ *                  commits; after defer_after failed attempts it moves to a
+ *                  later pass with 8x fewer workgroups.
+ *   CC_MODE_EPOCH  batching: in each epoch every pending transaction gets
+ *                  defer_after (default 1) attempts on a persistent grid; the
+ *                  aborted ones wait for the next epoch.  Four epochs are
+ *                  captured as one hipGraph and replayed until nothing is
+ *                  pending (max_epochs bounds the total: CC_E_LIVELOCK).
+ *   CC_MODE_SERVE  continuous batching over a stream: transactions are taken
+ *                  in arrival order (cc_set_arrivals) by a persistent grid,
+ *                  each starts no earlier than its arrival time on the device
+ *                  clock and only once CC_SERVE_BYTES_PER_OP x its op count
+ *                  fits in the hbm_cap_bytes budget of uncommitted work; it
+ *                  releases the bytes when it commits; aborts retry after
+ *                  back-off while later arrivals proceed.  Latency statistics
+ *                  are commit time minus arrival time.
+ */
+enum cc_mode { CC_MODE_PLAIN = 0, CC_MODE_EPOCH = 1, CC_MODE_SERVE = 2 };
+#define CC_SERVE_BYTES_PER_OP 32 /* read value + new value + undo / version record, 8 B each + 8 B index */
 
 /* Run flags. */
 #define CC_RUN_STRICT_FENCES 0x1u /* agent-scope acquire/release fences (cache invalidate/write-back) at
@@ -151,9 +172,11 @@ typedef struct {
   uint32_t backoff_ns;    /* base of the randomised exponential back-off after an abort; 0 = 200 ns */
   uint32_t defer_after;   /* CC_MODE_PLAIN: attempts of a transaction within one pass before it is deferred
                              to the next pass, which runs 8x fewer workgroups (the last pass runs one
-                             wavefront and never defers); 0 = 16 */
+                             wavefront and never defers); 0 = 16.  CC_MODE_EPOCH: attempts per epoch;
+                             0 = 1 */
   uint64_t ts_start;      /* first value of the run's ticket / timestamp counter (0 for normal runs; a
                              large value forces the 31-bit TO/MVCC timestamp-overflow path) */
+  uint64_t hbm_cap_bytes; /* CC_MODE_SERVE: admission budget for uncommitted work; 0 = no cap */
 } cc_run_params;
 
 /* Counters reported by cc_stats (index: meaning). */
@@ -172,7 +195,12 @@ enum cc_stat {
   CC_STAT_PASSES = 11,     /* kernel passes run (CC_MODE_PLAIN) */
   CC_STAT_DEFERRED = 12,   /* transactions deferred to a later pass */
   CC_STAT_GRID = 13,       /* workgroups of the first pass */
-  CC_N_STATS = 16
+  CC_STAT_T_USEFUL_NS = 14,/* summed over transactions: time in attempts that committed */
+  CC_STAT_T_ABORT_NS = 15, /* summed over transactions: time in attempts that aborted */
+  CC_STAT_T_WAIT_NS = 16,  /* summed over transactions: back-off time between attempts */
+  CC_STAT_GAVE_UP = 17,    /* transactions left pending (attempt limit or timestamp overflow) */
+  CC_STAT_ADMIT_WAITS = 18,/* CC_MODE_SERVE: admissions postponed because the byte budget was full */
+  CC_N_STATS = 24
 };
 
 /* Library version and self-description. */
@@ -248,6 +276,14 @@ cc_status cc_run(cc_ctx *ctx, uint64_t batch_id, const cc_run_params *params);
  */
 cc_status cc_fetch_outcomes(cc_ctx *ctx, uint64_t batch_id, cc_outcome *per_txn, int64_t *per_op_read,
                             int dst_on_device);
+
+/*
+ * Set the arrival time of every transaction of a batch, for CC_MODE_SERVE:
+ * arrival_ns[t] is nanoseconds after the start of the run (CC
+ * initialisation), non-decreasing in t, n == the batch's transaction count.
+ * Host array; copied.  CC_E_INVAL on a decreasing or negative time.
+ */
+cc_status cc_set_arrivals(cc_ctx *ctx, uint64_t batch_id, const int64_t *arrival_ns, uint64_t n);
 
 /* Copy up to n counters (enum cc_stat order) of the batch's last run. */
 cc_status cc_stats(cc_ctx *ctx, uint64_t batch_id, uint64_t *counters, uint32_t n);

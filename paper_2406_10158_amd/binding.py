@@ -28,11 +28,13 @@ CC_OCC, CC_2PL_NW, CC_TO, CC_MVCC, CC_TICTOC = 0, 1, 2, 3, 4
 SCHEMES = {"occ": CC_OCC, "2pl_nw": CC_2PL_NW, "to": CC_TO, "mvcc": CC_MVCC, "tictoc": CC_TICTOC}
 CC_READ, CC_ADD, CC_COND_ADD, CC_WRITE_SLOT = 0, 1, 2, 3
 CC_PENDING, CC_COMMITTED = 0, 1
-CC_MODE_PLAIN, CC_MODE_EPOCH = 0, 1
+CC_MODE_PLAIN, CC_MODE_EPOCH, CC_MODE_SERVE = 0, 1, 2
+CC_SERVE_BYTES_PER_OP = 32
 CC_RUN_STRICT_FENCES = 0x1
 STAT_NAMES = ["committed", "attempts", "abort_lock", "abort_valid", "kernel_ns", "run_ns", "tickets",
-              "max_attempts", "lat_p50_ns", "lat_p99_ns", "epochs", "passes", "deferred", "grid"]
-CC_N_STATS = 16
+              "max_attempts", "lat_p50_ns", "lat_p99_ns", "epochs", "passes", "deferred", "grid",
+              "t_useful_ns", "t_abort_ns", "t_wait_ns", "gave_up", "admit_waits"]
+CC_N_STATS = 24
 
 OP_DTYPE = np.dtype([("row", "<u4"), ("table", "<u2"), ("field", "u1"), ("kind", "u1"), ("arg", "<i8")])
 TXN_DTYPE = np.dtype([("first_op", "<u8"), ("n_ops", "<u4"), ("reserved", "<u4")])
@@ -49,7 +51,7 @@ class cc_run_params(ctypes.Structure):
     _fields_ = [("lanes_per_txn", ctypes.c_uint32), ("waves_per_wg", ctypes.c_uint32), ("grid", ctypes.c_uint32),
                 ("mode", ctypes.c_uint32), ("max_attempts", ctypes.c_uint64), ("max_epochs", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("backoff_ns", ctypes.c_uint32), ("defer_after", ctypes.c_uint32),
-                ("ts_start", ctypes.c_uint64)]
+                ("ts_start", ctypes.c_uint64), ("hbm_cap_bytes", ctypes.c_uint64)]
 
 
 _P = ctypes.c_void_p
@@ -69,6 +71,7 @@ _SIGS = {
     "cc_run": (_S, [_P, ctypes.c_uint64, ctypes.POINTER(cc_run_params)]),
     "cc_fetch_outcomes": (_S, [_P, ctypes.c_uint64, _P, _P, ctypes.c_int]),
     "cc_stats": (_S, [_P, ctypes.c_uint64, _P, ctypes.c_uint32]),
+    "cc_set_arrivals": (_S, [_P, ctypes.c_uint64, _P, ctypes.c_uint64]),
     "cc_release_batch": (_S, [_P, ctypes.c_uint64]),
     "cc_device_info": (_S, [_P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]),
     "cc_probe": (_S, [_P, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
@@ -188,9 +191,9 @@ def cc_submit_batch(ctx, txns: np.ndarray, ops: np.ndarray, scheme: int) -> int:
 
 
 def run_params(lanes_per_txn=0, waves_per_wg=0, grid=0, mode=CC_MODE_PLAIN, max_attempts=0, max_epochs=0,
-               flags=0, backoff_ns=0, defer_after=0, ts_start=0) -> cc_run_params:
+               flags=0, backoff_ns=0, defer_after=0, ts_start=0, hbm_cap_bytes=0) -> cc_run_params:
     return cc_run_params(lanes_per_txn, waves_per_wg, grid, mode, max_attempts, max_epochs, flags, backoff_ns,
-                         defer_after, ts_start)
+                         defer_after, ts_start, hbm_cap_bytes)
 
 
 def cc_run(ctx, batch_id: int, params: cc_run_params | None = None) -> None:
@@ -204,6 +207,11 @@ def cc_fetch_outcomes(ctx, batch_id: int, per_txn=None, per_op_read=None) -> Non
     p1 = _ptr(per_txn) if per_txn is not None else None
     p2 = _ptr(per_op_read) if per_op_read is not None else None
     _check(lib.cc_fetch_outcomes(ctx, batch_id, p1, p2, on_dev), ctx)
+
+
+def cc_set_arrivals(ctx, batch_id: int, arrival_ns: np.ndarray) -> None:
+    a = _host(arrival_ns, np.int64)
+    _check(lib.cc_set_arrivals(ctx, batch_id, _ptr(a), len(a)), ctx)
 
 
 def cc_stats(ctx, batch_id: int) -> dict:

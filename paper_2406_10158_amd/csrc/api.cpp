@@ -33,6 +33,11 @@ struct Batch {
   int64_t *d_reads = nullptr;
   uint32_t *d_list = nullptr;  // pending transactions between passes
   uint64_t *d_nodes = nullptr; // MVCC history nodes (3 words per op)
+  int64_t *d_arrival = nullptr;           // serving: arrival ticks per transaction
+  std::vector<int64_t> arrival_ns;        // host copy, for latency statistics
+  hipGraphExec_t epoch_graph = nullptr;  // captured epochs for the last epoch-mode parameters
+  uint64_t epoch_key[4] = {0, 0, 0, 0};
+  int epoch_grid = 0;
   bool ran = false;
   uint64_t stats[CC_N_STATS] = {};
 };
@@ -42,6 +47,7 @@ struct Batch {
 struct cc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  bool own_stream = false;
   int n_cu = 0;
   uint32_t wallclock_khz = 0;
   std::vector<Table> tables;
@@ -101,6 +107,13 @@ cc_status freeze(cc_ctx *c) {
   return CC_OK;
 }
 
+cc_status launch_error(cc_ctx *c, hipError_t e) {
+  if (e == hipErrorInvalidValue) return fail(c, CC_E_INVAL, "scheme or (lanes_per_txn, ops per txn) not supported");
+  if (e == hipErrorInvalidConfiguration)
+    return fail(c, CC_E_INVAL, "waves_per_wg too large for the register slots this lanes_per_txn needs");
+  return hip_fail(c, e, "transaction kernel launch");
+}
+
 void free_batch(Batch &b) {
   if (b.d_ops) (void)hipFree(b.d_ops);
   if (b.d_txns) (void)hipFree(b.d_txns);
@@ -108,6 +121,10 @@ void free_batch(Batch &b) {
   if (b.d_reads) (void)hipFree(b.d_reads);
   if (b.d_list) (void)hipFree(b.d_list);
   if (b.d_nodes) (void)hipFree(b.d_nodes);
+  if (b.epoch_graph) (void)hipGraphExecDestroy(b.epoch_graph);
+  if (b.d_arrival) (void)hipFree(b.d_arrival);
+  b.d_arrival = nullptr;
+  b.epoch_graph = nullptr;
   b.d_list = nullptr;
   b.d_nodes = nullptr;
   b.d_ops = nullptr;
@@ -192,6 +209,15 @@ cc_status cc_init(cc_ctx **out, const cc_config *cfg) {
   c->device = dev;
   c->stream = cfg ? (hipStream_t)cfg->stream : nullptr;
   c->n_cu = p.multiProcessorCount;
+  if (!c->stream) {
+    // a stream of our own (default priority), so that runs can be captured
+    if (hipSetDevice(dev) != hipSuccess || hipStreamCreate(&c->stream) != hipSuccess) {
+      delete c;
+      g_init_err = "hipStreamCreate failed";
+      return CC_E_HIP;
+    }
+    c->own_stream = true;
+  }
   int khz = 0;
   if (hipSetDevice(dev) != hipSuccess ||
       hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) {
@@ -227,6 +253,7 @@ cc_status cc_destroy(cc_ctx *c) {
   if (c->d_ctl) (void)hipFree(c->d_ctl);
   for (auto &e : c->ev)
     if (e) (void)hipEventDestroy(e);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return CC_OK;
 }
@@ -443,7 +470,10 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   Batch &b = it->second;
   cc_run_params p{};
   if (pp) p = *pp;
-  if (p.mode != CC_MODE_PLAIN) return fail(c, CC_E_INVAL, "unsupported mode");
+  if (p.mode != CC_MODE_PLAIN && p.mode != CC_MODE_EPOCH && p.mode != CC_MODE_SERVE)
+    return fail(c, CC_E_INVAL, "unknown mode");
+  if (p.mode == CC_MODE_SERVE && b.n_txns && !b.d_arrival)
+    return fail(c, CC_E_STATE, "CC_MODE_SERVE needs cc_set_arrivals first");
   uint32_t lanes = p.lanes_per_txn;
   if (lanes == 0) {
     lanes = 1;
@@ -476,18 +506,87 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   a.ns_per_tick_q16 = (uint32_t)((1000000ull << 16) / c->wallclock_khz);
   a.has_slot = b.has_slot ? 1u : 0u;
 
-  const uint32_t defer = p.defer_after ? p.defer_after : 16;
+  const uint32_t defer = p.defer_after ? p.defer_after : (p.mode == CC_MODE_SERVE ? 256 : 16);
   a.pass = 0;
   a.list = nullptr;
+  if (p.mode == CC_MODE_SERVE) {
+    a.arrival = b.d_arrival;
+    a.budget_cap = p.hbm_cap_bytes;
+    a.bytes_per_op = CC_SERVE_BYTES_PER_OP;
+  }
 
   HIP_OR(c, hipEventRecord(c->ev[0], c->stream));
   HIP_OR(c, launch_init(c->stream, c->d_words, c->total_rows, c->d_aux, b.scheme == CC_MVCC ? c->total_rows : 0,
                         b.d_out, b.n_txns, c->d_ctl, p.ts_start));
   Ctl h{};
   double kernel_ms = 0;
-  uint32_t passes = 0;
+  uint32_t passes = 0, epochs = 0;
   int first_grid = 0;
-  if (b.n_txns) {
+  bool epoch_limit = false;
+  const bool strict = (p.flags & CC_RUN_STRICT_FENCES) != 0;
+  if (b.n_txns && p.mode == CC_MODE_EPOCH) {
+    // Epochs: every pending transaction gets defer_after (default 1) attempts,
+    // aborted ones wait for the next epoch.  One epoch = [reset claim counter,
+    // list the pending transactions, persistent transaction kernel over that
+    // list]; EPOCHS_PER_GRAPH epochs are captured once as a hipGraph and the
+    // graph is replayed until nothing is pending.  The kernel reads the
+    // pending count from the control block, so the graph's arguments are fixed.
+    constexpr uint32_t EPOCHS_PER_GRAPH = 4;
+    const uint32_t max_epochs = p.max_epochs ? p.max_epochs : (1u << 20);
+    a.defer_after = p.defer_after ? p.defer_after : 1;
+    a.pass = 1;
+    a.list = b.d_list;
+    a.n_from_ctl = 1;
+    const uint64_t key[4] = {(uint64_t)lanes | ((uint64_t)wpw << 8) | ((uint64_t)p.grid << 16),
+                             (uint64_t)p.flags | ((uint64_t)a.defer_after << 32), a.max_attempts,
+                             (uint64_t)a.backoff_ticks | ((uint64_t)p.ts_start << 32)};
+    if (!b.epoch_graph || std::memcmp(key, b.epoch_key, sizeof key) != 0) {
+      if (b.epoch_graph) (void)hipGraphExecDestroy(b.epoch_graph);
+      b.epoch_graph = nullptr;
+      hipGraph_t g = nullptr;
+      HIP_OR(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e = hipSuccess;
+      int grid_used = 0;
+      for (uint32_t i = 0; i < EPOCHS_PER_GRAPH && e == hipSuccess; ++i) {
+        e = launch_compact(c->stream, b.d_out, b.n_txns, a.max_attempts, b.d_list, c->d_ctl);
+        if (e == hipSuccess)
+          e = launch_txn(c->stream, b.scheme, (int)lanes, (int)b.max_ops, (int)wpw, (int)p.grid, strict, a, c->n_cu,
+                         &grid_used);
+      }
+      const hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+      if (e != hipSuccess) {
+        if (e2 == hipSuccess && g) (void)hipGraphDestroy(g);
+        return launch_error(c, e);
+      }
+      if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&b.epoch_graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        b.epoch_graph = nullptr;
+        return hip_fail(c, e, "hipGraphInstantiate");
+      }
+      std::memcpy(b.epoch_key, key, sizeof key);
+      b.epoch_grid = grid_used;
+    }
+    first_grid = b.epoch_grid;
+    for (;;) {
+      HIP_OR(c, hipEventRecord(c->ev[1], c->stream));
+      HIP_OR(c, hipGraphLaunch(b.epoch_graph, c->stream));
+      HIP_OR(c, hipEventRecord(c->ev[2], c->stream));
+      HIP_OR(c, hipStreamSynchronize(c->stream));
+      float ms = 0;
+      HIP_OR(c, hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
+      kernel_ms += ms;
+      epochs += EPOCHS_PER_GRAPH;
+      ++passes;
+      HIP_OR(c, hipMemcpy(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+      if (h.stats[DS_COMMITTED] + h.stats[DS_GAVE_UP] >= b.n_txns) break;
+      if (epochs >= max_epochs) {
+        epoch_limit = true;
+        break;
+      }
+    }
+  } else if (b.n_txns) {
     int grid = (int)p.grid;
     uint32_t waves = wpw;
     for (;;) {
@@ -495,13 +594,9 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
       a.defer_after = last ? 0u : defer;
       HIP_OR(c, hipEventRecord(c->ev[1], c->stream));
       int grid_used = 0;
-      hipError_t e = launch_txn(c->stream, b.scheme, (int)lanes, (int)b.max_ops, (int)waves, grid,
-                                (p.flags & CC_RUN_STRICT_FENCES) != 0, a, c->n_cu, &grid_used);
-      if (e == hipErrorInvalidValue)
-        return fail(c, CC_E_INVAL, "scheme or (lanes_per_txn, ops per txn) not supported");
-      if (e == hipErrorInvalidConfiguration)
-        return fail(c, CC_E_INVAL, "waves_per_wg too large for the register slots this lanes_per_txn needs");
-      if (e != hipSuccess) return hip_fail(c, e, "transaction kernel launch");
+      hipError_t e = launch_txn(c->stream, b.scheme, (int)lanes, (int)b.max_ops, (int)waves, grid, strict, a, c->n_cu,
+                                &grid_used);
+      if (e != hipSuccess) return launch_error(c, e);
       HIP_OR(c, hipEventRecord(c->ev[2], c->stream));
       HIP_OR(c, hipStreamSynchronize(c->stream));
       float ms = 0;
@@ -518,6 +613,8 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
       a.list = b.d_list;
       a.n_txns = h.pending_n;
       a.pass = passes;
+      a.arrival = nullptr;  // deferred transactions have all arrived
+      a.budget_cap = 0;
       grid = std::max(1, grid_used / 8);
       if (grid == 1) waves = 1;
     }
@@ -539,13 +636,23 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   b.stats[CC_STAT_PASSES] = passes;
   b.stats[CC_STAT_DEFERRED] = h.stats[DS_DEFERRED];
   b.stats[CC_STAT_GRID] = (uint64_t)first_grid;
+  b.stats[CC_STAT_EPOCHS] = epochs;
+  const double ns_per_tick = 1e6 / (double)c->wallclock_khz;
+  b.stats[CC_STAT_T_USEFUL_NS] = (uint64_t)((double)h.stats[DS_T_USEFUL] * ns_per_tick);
+  b.stats[CC_STAT_T_ABORT_NS] = (uint64_t)((double)h.stats[DS_T_ABORT] * ns_per_tick);
+  b.stats[CC_STAT_T_WAIT_NS] = (uint64_t)((double)h.stats[DS_T_WAIT] * ns_per_tick);
+  b.stats[CC_STAT_GAVE_UP] = h.stats[DS_GAVE_UP];
+  b.stats[CC_STAT_ADMIT_WAITS] = h.stats[DS_ADMIT_WAITS];
   b.ran = true;
   if (b.n_txns) {
     std::vector<cc_outcome> o(b.n_txns);
     HIP_OR(c, hipMemcpy(o.data(), b.d_out, b.n_txns * sizeof(cc_outcome), hipMemcpyDeviceToHost));
+    if (p.mode == CC_MODE_SERVE)
+      for (uint64_t t = 0; t < b.n_txns; ++t) o[t].commit_ns -= b.arrival_ns[t];
     latency_percentiles(o, &b.stats[CC_STAT_LAT_P50_NS], &b.stats[CC_STAT_LAT_P99_NS]);
   }
   if (h.stats[DS_TS_OVERFLOW]) return fail(c, CC_E_TS_OVERFLOW, "timestamp overflow during the run");
+  if (epoch_limit) return fail(c, CC_E_LIVELOCK, "max_epochs reached with transactions pending");
   if (h.stats[DS_COMMITTED] != b.n_txns) {
     char msg[160];
     std::snprintf(msg, sizeof msg, "%llu of %llu transactions committed (attempt limit reached)",
@@ -566,6 +673,26 @@ cc_status cc_fetch_outcomes(cc_ctx *c, uint64_t batch_id, cc_outcome *per_txn, i
   if (per_txn && b.n_txns) HIP_OR(c, hipMemcpyAsync(per_txn, b.d_out, b.n_txns * sizeof(cc_outcome), k, c->stream));
   if (per_op && b.n_ops) HIP_OR(c, hipMemcpyAsync(per_op, b.d_reads, b.n_ops * sizeof(int64_t), k, c->stream));
   HIP_OR(c, hipStreamSynchronize(c->stream));
+  return CC_OK;
+}
+
+cc_status cc_set_arrivals(cc_ctx *c, uint64_t batch_id, const int64_t *arrival_ns, uint64_t n) {
+  if (!c || (n && !arrival_ns)) return CC_E_INVAL;
+  auto it = c->batches.find(batch_id);
+  if (it == c->batches.end()) return fail(c, CC_E_NOBATCH, "unknown batch");
+  Batch &b = it->second;
+  if (n != b.n_txns) return fail(c, CC_E_INVAL, "one arrival time per transaction");
+  std::vector<int64_t> ticks(std::max<uint64_t>(n, 1), 0);
+  for (uint64_t t = 0; t < n; ++t) {
+    if (arrival_ns[t] < 0 || (t && arrival_ns[t] < arrival_ns[t - 1]))
+      return fail(c, CC_E_INVAL, "arrival times must be non-negative and non-decreasing");
+    ticks[t] = (int64_t)((double)arrival_ns[t] * (double)c->wallclock_khz / 1e6);
+  }
+  if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
+  if (!b.d_arrival) HIP_OR(c, hipMalloc(&b.d_arrival, ticks.size() * sizeof(int64_t)));
+  HIP_OR(c, hipMemcpyAsync(b.d_arrival, ticks.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  HIP_OR(c, hipStreamSynchronize(c->stream));
+  b.arrival_ns.assign(arrival_ns, arrival_ns + n);
   return CC_OK;
 }
 

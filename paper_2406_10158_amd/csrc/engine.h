@@ -53,7 +53,11 @@ enum DevStat {
   DS_MAX_ATTEMPTS = 5,
   DS_TS_OVERFLOW = 6,
   DS_DEFERRED = 7,
-  DS_N = 8
+  DS_T_USEFUL = 8,  // wall-clock ticks, summed over teams
+  DS_T_ABORT = 9,
+  DS_T_WAIT = 10,
+  DS_ADMIT_WAITS = 11,  // serving: admissions deferred because the byte budget was full
+  DS_N = 16
 };
 
 struct Ctl {
@@ -61,6 +65,7 @@ struct Ctl {
   uint64_t ticket;       // serial ticket / timestamp counter (last value drawn)
   uint64_t start_clock;  // device wall clock at CC initialisation
   uint64_t pending_n;    // length of the pending list built between passes
+  uint64_t budget_used;  // serving: bytes reserved by admitted, uncommitted transactions
   uint64_t stats[DS_N];
 };
 
@@ -83,8 +88,12 @@ struct RunArgs {
   uint32_t ns_per_tick_q16;  // wall-clock tick length in ns, 16.16 fixed point
   uint32_t has_slot;       // batch contains WRITE_SLOT ops
   uint32_t defer_after;    // attempts in this pass before deferring (0: never)
-  uint32_t pass;           // 0 for the first pass
-  uint32_t pad;
+  uint32_t pass;           // 0 for the first pass (attempt counts start at 0)
+  uint32_t n_from_ctl;     // take the pass's transaction count from ctl->pending_n
+  const int64_t *arrival;  // serving: arrival time of each transaction, wall-clock ticks after start
+  uint64_t budget_cap;     // serving: admission cap on reserved bytes (0: no cap)
+  uint32_t bytes_per_op;   // serving: log / version bytes one operation reserves
+  uint32_t pad2;
 };
 
 // Host-side launchers (kernels.hip).

@@ -33,31 +33,57 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
   Team<L> t;
   Slots<K> s;
   const uint64_t start_clock = a.ctl->start_clock;
+  // epoch mode replays a captured graph, so the pending count is read here
+  const uint64_t n_txns = a.n_from_ctl ? ld_word(&a.ctl->pending_n) : a.n_txns;
   int64_t txn = -1;         // current transaction (team-uniform)
   uint32_t attempts = 0;    // attempts of txn so far, all passes
   uint32_t pass_att = 0;    // attempts of txn in this pass
   uint64_t ready_at = 0;    // wall-clock tick before which the team waits
   bool done = false;        // no transactions left for this team
   uint64_t n_commit = 0, n_att = 0, n_lock = 0, n_valid = 0, n_gave = 0, n_defer = 0, n_ovf = 0, max_att = 0;
+  uint64_t t_useful = 0, t_abort = 0, t_wait = 0;  // per team, in leader lanes
+  uint64_t reserved = 0;    // serving: bytes this team's transaction holds in the budget
+  uint64_t n_admit_wait = 0;
 
   for (;;) {
     const bool need = txn < 0 && !done;
     const uint64_t q = t.claim(&a.ctl->queue, need, 1);
     if (need) {
-      if (q < a.n_txns) {
+      if (q < n_txns) {
         txn = a.list ? (int64_t)a.list[q] : (int64_t)q;
         attempts = a.pass ? a.out[txn].attempts : 0;
         pass_att = 0;
-        ready_at = 0;
+        // serving: not before the transaction's arrival
+        ready_at = a.arrival ? start_clock + (uint64_t)a.arrival[txn] : 0;
+        reserved = 0;
       } else {
         done = true;
       }
     }
     if (ballot(txn >= 0) == 0) break;
-    const uint64_t now = wall_clock64();
+    uint64_t now = wall_clock64();
+    if (a.budget_cap && txn >= 0 && now >= ready_at && reserved == 0) {
+      // serving admission: reserve the transaction's log / version bytes, or
+      // wait a little and try again
+      uint64_t need = 0;
+      if (t.tl == 0) {
+        need = (uint64_t)a.txns[txn].n * a.bytes_per_op + 1;
+        const uint64_t before = add_word(&a.ctl->budget_used, need);
+        // over the cap: back out, unless nothing else is admitted (a
+        // transaction larger than the cap still runs, alone)
+        if (before + need > a.budget_cap && before != 0) {
+          add_word(&a.ctl->budget_used, (uint64_t)0 - need);
+          need = 0;
+          ++n_admit_wait;
+        }
+      }
+      reserved = (uint64_t)__shfl((long long)need, t.tb, 64);
+      if (reserved == 0) ready_at = now + a.backoff_ticks;
+    }
     const bool active = txn >= 0 && now >= ready_at;
     if (ballot(active) == 0) {
       __builtin_amdgcn_s_sleep(2);
+      if (txn >= 0 && t.tl == 0) t_wait += wall_clock64() - now;
       continue;
     }
     // stage the transaction's ops in registers (coalesced 16 B loads per team)
@@ -87,6 +113,12 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
     }
     uint64_t key_hi = 0, key_lo = 0;
     const int r = attempt<L, K, SCHEME, STRICT>(t, s, active, a, (uint32_t)(txn < 0 ? 0 : txn), &key_hi, &key_lo);
+    if (t.tl == 0 && txn >= 0) {
+      const uint64_t dt = wall_clock64() - now;
+      if (!active) t_wait += dt;
+      else if (r == COMMIT) t_useful += dt;
+      else t_abort += dt;
+    }
     if (active) {
       ++attempts;
       ++pass_att;
@@ -107,6 +139,8 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
 #pragma unroll
         for (int k = 0; k < K; ++k)
           if (s.valid[k]) __builtin_nontemporal_store(s.x[k], a.reads + first + t.tl + k * L);
+        if (reserved && t.tl == 0) add_word(&a.ctl->budget_used, (uint64_t)0 - reserved);
+        reserved = 0;
         txn = -1;
       } else {
         if (t.tl == 0) {
@@ -121,7 +155,9 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
             a.out[txn].attempts = attempts;
             if (r == TS_OVERFLOW || attempts >= a.max_attempts) ++n_gave; else ++n_defer;
             max_att = attempts > max_att ? attempts : max_att;
+            if (reserved) add_word(&a.ctl->budget_used, (uint64_t)0 - reserved);
           }
+          reserved = 0;
           txn = -1;
         } else {
           // randomised exponential back-off
@@ -136,6 +172,8 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
   n_att = t.tl == 0 ? n_att : 0;
   const uint64_t c0 = wave_sum(n_commit), c1 = wave_sum(n_att), c2 = wave_sum(n_lock), c3 = wave_sum(n_valid),
                  c4 = wave_sum(n_gave), c5 = wave_max(max_att), c6 = wave_sum(n_defer), c7 = wave_sum(n_ovf);
+  const uint64_t c8 = wave_sum(t_useful), c9 = wave_sum(t_abort), c10 = wave_sum(t_wait),
+                 c11 = wave_sum(n_admit_wait);
   if (t.lane == 0) {
     if (c0) atomicAdd((unsigned long long *)&a.ctl->stats[DS_COMMITTED], (unsigned long long)c0);
     if (c1) atomicAdd((unsigned long long *)&a.ctl->stats[DS_ATTEMPTS], (unsigned long long)c1);
@@ -145,6 +183,10 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
     if (c5) atomicMax((unsigned long long *)&a.ctl->stats[DS_MAX_ATTEMPTS], (unsigned long long)c5);
     if (c6) atomicAdd((unsigned long long *)&a.ctl->stats[DS_DEFERRED], (unsigned long long)c6);
     if (c7) atomicAdd((unsigned long long *)&a.ctl->stats[DS_TS_OVERFLOW], (unsigned long long)c7);
+    if (c8) atomicAdd((unsigned long long *)&a.ctl->stats[DS_T_USEFUL], (unsigned long long)c8);
+    if (c9) atomicAdd((unsigned long long *)&a.ctl->stats[DS_T_ABORT], (unsigned long long)c9);
+    if (c10) atomicAdd((unsigned long long *)&a.ctl->stats[DS_T_WAIT], (unsigned long long)c10);
+    if (c11) atomicAdd((unsigned long long *)&a.ctl->stats[DS_ADMIT_WAITS], (unsigned long long)c11);
   }
 }
 

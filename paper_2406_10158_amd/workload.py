@@ -399,3 +399,77 @@ def order_entry_workload(n_warehouses: int, n_txns: int, seed: int = 0, new_orde
     b = _pack(lengths, np.array(row, np.int64), np.array(table, np.int64), np.array(field, np.int64),
               np.array(kind, np.int64), np.array(arg, np.int64), meta)
     return tables, b
+
+
+# ----------------------------------------------------------------------------
+# Serving streams: Poisson arrivals over a key-value / order-entry mix
+# ----------------------------------------------------------------------------
+
+def concat_batches(parts):
+    """One batch holding the given batches' transactions, in the given (batch, txn ids) order."""
+    lengths, row, table, field, kind, arg = [], [], [], [], [], []
+    for bt, ids in parts:
+        for t in ids:
+            sl = bt.txn_slice(int(t))
+            lengths.append(int(bt.n_ops[t]))
+            row.append(bt.row[sl]); table.append(bt.table[sl]); field.append(bt.field[sl])
+            kind.append(bt.kind[sl]); arg.append(bt.arg[sl])
+    cat = (lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.zeros(0, dt))
+    return _pack(lengths, cat(row, np.uint32), cat(table, np.uint16), cat(field, np.uint8), cat(kind, np.uint8),
+                 cat(arg, np.int64), {})
+
+
+def serve_stream(n_arrivals: int, rate_per_s: float, kv_rows=10_000_000, kv_fields=10, kv_ops=(8, 32),
+                 kv_theta=0.9, oe_warehouses=8, kv_frac=0.5, isolated_frac=0.0, seed=0, with_kv=True,
+                 with_oe=True, arrivals_ns=None, kinds=None):
+    """A serving stream: tables, one batch in arrival order, arrival times (ns), and masks.
+
+    Arrivals are a Poisson process of ``rate_per_s`` (exponential gaps).  Each
+    arrival is a key-value transaction (table 0: ``kv_ops`` ops, Zipf
+    ``kv_theta``) with probability ``kv_frac``, else an order-entry
+    transaction (tables 1-7, ``oe_warehouses`` warehouses).  A fraction
+    ``isolated_frac`` of the key-value transactions use private rows of a
+    reserved range at the top of the key-value table that nothing else
+    touches.  ``with_kv`` / ``with_oe`` drop one kind (keeping the others'
+    arrival times), which gives the "alone" runs of a mixed stream.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed + 7_000_001))
+    if arrivals_ns is None:
+        gaps = rng.exponential(1e9 / rate_per_s, size=n_arrivals)
+        arrivals_ns = np.floor(np.cumsum(gaps)).astype(np.int64)
+    if kinds is None:
+        kinds = rng.random(n_arrivals) < kv_frac          # True: key-value
+    n_kv = int(kinds.sum())
+    n_oe = n_arrivals - n_kv
+    n_iso = int(round(isolated_frac * n_kv))
+    iso_rows_per = kv_ops[1] if isinstance(kv_ops, (tuple, list)) else int(kv_ops)
+    reserved = n_iso * iso_rows_per
+    shared_rows = kv_rows - reserved
+    kvb = kv_batch(shared_rows, kv_fields, n_kv, ops=kv_ops, theta=kv_theta, seed=seed)
+    iso = np.zeros(n_kv, bool)
+    if n_iso:
+        iso_ids = rng.choice(n_kv, size=n_iso, replace=False)
+        iso[iso_ids] = True
+        for j, t in enumerate(np.sort(iso_ids)):
+            sl = kvb.txn_slice(int(t))
+            kvb.row[sl] = shared_rows + j * iso_rows_per + np.arange(sl.stop - sl.start, dtype=np.uint32)
+    oe_tables, oeb = order_entry_workload(oe_warehouses, max(n_oe, 1), seed=seed + 1)
+    oeb.table = (oeb.table + 1).astype(np.uint16)
+    tables = [kv_table(kv_rows, kv_fields)] + oe_tables
+    parts, is_kv, is_iso, keep = [], [], [], []
+    ik = io = 0
+    for a in range(n_arrivals):
+        if kinds[a]:
+            if with_kv:
+                parts.append((kvb, [ik])); is_kv.append(True); is_iso.append(bool(iso[ik])); keep.append(a)
+            ik += 1
+        else:
+            if with_oe:
+                parts.append((oeb, [io])); is_kv.append(False); is_iso.append(False); keep.append(a)
+            io += 1
+    batch = concat_batches(parts)
+    batch.meta = dict(workload="serve", rate_per_s=rate_per_s, seed=seed, oe_warehouses=oe_warehouses,
+                      is_new_order=np.array([False] * len(is_kv)))
+    keep = np.array(keep, np.int64)
+    return tables, batch, arrivals_ns[keep] if len(keep) else np.zeros(0, np.int64), dict(
+        is_kv=np.array(is_kv, bool), is_isolated=np.array(is_iso, bool), arrivals_all=arrivals_ns, kinds=kinds)

@@ -50,7 +50,7 @@ def test_strerror_and_version(b):
 
 def test_struct_layouts_match_header(b):
     assert b.OP_DTYPE.itemsize == 16 and b.TXN_DTYPE.itemsize == 16 and b.OUTCOME_DTYPE.itemsize == 32
-    assert ctypes.sizeof(b.cc_run_params) == 48
+    assert ctypes.sizeof(b.cc_run_params) == 56
 
 
 def _batch(rows, tables=None, fields=None, kinds=None, args=None, txn_lens=None):

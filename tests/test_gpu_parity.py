@@ -206,3 +206,67 @@ def test_timestamp_overflow_is_reported(scheme):
 def test_large_ticket_start_is_harmless(scheme):
     tabs, b = wl.kv_workload(n_rows=1_000, n_fields=2, n_txns=5_000, ops=4, theta=0.9, seed=10)
     run_and_check(tabs, b, scheme, ts_start=(1 << 40))
+
+
+# ---------------------------------------------------------------------------
+# epoch mode (batching): graph-replayed epochs, aborted transactions retried in
+# the next epoch
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("scheme", IMPLEMENTED)
+def test_epoch_mode(scheme):
+    bb = binding()
+    tabs, b = wl.kv_workload(n_rows=100_000, n_fields=4, n_txns=20_000, ops=(2, 64), theta=0.8, seed=21)
+    out, reads, final, st = run_and_check(tabs, b, scheme, mode=bb.CC_MODE_EPOCH)
+    assert st["epochs"] >= 4 and st["epochs"] % 4 == 0
+
+
+@pytest.mark.parametrize("scheme", ["occ", "tictoc"])
+def test_epoch_graph_replays(scheme):
+    # the captured graph is reused by later runs of the batch; every replay must
+    # be valid and end in the order-free closed form
+    bb = binding()
+    tabs, b = wl.kv_workload(n_rows=50_000, n_fields=4, n_txns=12_000, ops=(2, 32), theta=0.9, seed=22)
+    cf = oracle.final_add_only(tabs, b)
+    with bb.Engine(tabs) as eng:
+        bid = eng.submit(b, scheme)
+        for rep in range(4):
+            eng.load(tabs)
+            st = eng.run(bid, mode=bb.CC_MODE_EPOCH, lanes_per_txn=16)
+            out, reads = eng.outcomes(bid, b.n_txns, b.total_ops)
+            final = eng.tables()
+            r = check(tabs, b, out, reads, final)
+            assert r.ok, (rep, r)
+            assert np.array_equal(final[0], cf[0])
+            # a plain run in between must not disturb the cached graph
+            if rep == 1:
+                eng.load(tabs)
+                eng.run(bid)
+
+
+@pytest.mark.parametrize("scheme", ["occ", "2pl_nw"])
+def test_epoch_limit_reports_livelock(scheme):
+    bb = binding()
+    b = wl.kv_batch(2, 1, 3_000, ops=2, read_ratio=0.0, seed=23)
+    tabs = [wl.kv_table(2, 1)]
+    out, reads, final, st = run_batch(tabs, b, scheme, mode=bb.CC_MODE_EPOCH, max_epochs=4)
+    assert isinstance(st.get("error"), bb.CCError) and st["error"].status == bb.CC_E_LIVELOCK
+    assert check(tabs, b, out, reads, final, require_all_committed=False).ok
+
+
+def test_autotuner_picks_a_feasible_point():
+    bb = binding()
+    from paper_2406_10158_amd import autotune
+    tabs, b = wl.kv_workload(n_rows=100_000, n_fields=4, n_txns=16_384, ops=(2, 64), theta=0.8, seed=24)
+    with bb.Engine(tabs) as eng:
+        bid = eng.submit(b, "occ")
+        best, res = autotune.tune(eng, bid, b.n_txns, reset=lambda: eng.load(tabs))
+        assert best is not None and best["feasible"]
+        infeasible = [r for r in res if not r["feasible"]]
+        assert any(r["lanes_per_txn"] == 1 for r in infeasible)  # 64-op transactions do not fit one lane
+        # the chosen point still produces a correct run
+        eng.load(tabs)
+        params = {k: best[k] for k in ("mode", "lanes_per_txn", "waves_per_wg", "grid")}
+        eng.run(bid, **params)
+        out, reads = eng.outcomes(bid, b.n_txns, b.total_ops)
+        assert check(tabs, b, out, reads, eng.tables()).ok

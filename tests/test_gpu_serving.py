@@ -1,0 +1,91 @@
+"""GPU serving mode: continuous admission of a Poisson stream, checked against the oracle.
+
+The alone-versus-mix test runs a key-value stream by itself and interleaved
+with an order-entry stream on disjoint tables (same arrival times): every run
+must replay exactly in its serial order, the key-value table must end in the
+same state (add-only, so it is order-free), and transactions on a reserved
+key range nothing else touches must read bit-identical values in both runs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import SCHEMES, binding, check, run_batch
+from paper_2406_10158_amd import workload as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def serve(tables, batch, arrivals, scheme="occ", **params):
+    bb = binding()
+    with bb.Engine(tables) as eng:
+        bid = eng.submit(batch, scheme)
+        bb.cc_set_arrivals(eng.ctx, bid, arrivals)
+        err = None
+        try:
+            st = eng.run(bid, mode=bb.CC_MODE_SERVE, **params)
+        except bb.CCError as e:
+            err, st = e, bb.cc_stats(eng.ctx, bid)
+        out, reads = eng.outcomes(bid, batch.n_txns, batch.total_ops)
+        final = eng.tables()
+    assert err is None, err
+    return out, reads, final, st
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_serve_stream_parity(scheme):
+    tabs, b, arr, m = wl.serve_stream(6_000, 2e6, kv_rows=200_000, isolated_frac=0.05, seed=31)
+    out, reads, final, st = serve(tabs, b, arr, scheme)
+    rep = check(tabs, b, out, reads, final)
+    assert rep.ok, rep
+    # nothing commits before it arrives (device clock ticks are 10 ns)
+    assert np.all(out["commit_ns"] + 10 >= arr)
+    assert st["lat_p99_ns"] >= st["lat_p50_ns"] > 0
+
+
+def test_serve_alone_vs_mix():
+    kw = dict(kv_rows=200_000, isolated_frac=0.1, seed=32)
+    tabs, mix, arr, m = wl.serve_stream(8_000, 4e6, **kw)
+    _, alone, arr_a, ma = wl.serve_stream(8_000, 4e6, with_oe=False, **kw)
+    out_m, reads_m, fin_m, _ = serve(tabs, mix, arr)
+    out_a, reads_a, fin_a, _ = serve(tabs, alone, arr_a)
+    assert check(tabs, mix, out_m, reads_m, fin_m).ok
+    assert check(tabs, alone, out_a, reads_a, fin_a).ok
+    # the key-value table is order-free: same final state alone and in the mix
+    cf = oracle.final_add_only([tabs[0]], alone)[0]
+    assert np.array_equal(fin_a[0], cf)
+    assert np.array_equal(fin_m[0], cf)
+    # isolated transactions read the same bytes alone and mixed (their initial values)
+    kv_ids_mix = np.nonzero(m["is_kv"])[0]
+    iso_a = np.nonzero(ma["is_isolated"])[0]
+    assert len(iso_a) > 0
+    for t_a in iso_a:
+        t_m = kv_ids_mix[t_a]
+        ra = reads_a[alone.txn_slice(int(t_a))]
+        rm = reads_m[mix.txn_slice(int(t_m))]
+        assert np.array_equal(ra, rm)
+        sl = alone.txn_slice(int(t_a))
+        assert np.array_equal(ra, 16 * alone.row[sl].astype(np.int64) + alone.field[sl].astype(np.int64))
+
+
+@pytest.mark.parametrize("scheme", ["occ", "mvcc"])
+def test_serve_small_budget_throttles_but_loses_nothing(scheme):
+    bb = binding()
+    tabs, b, arr, m = wl.serve_stream(3_000, 20e6, kv_rows=100_000, seed=33)
+    cap = 3 * 32 * bb.CC_SERVE_BYTES_PER_OP
+    out, reads, final, st = serve(tabs, b, arr, scheme, hbm_cap_bytes=cap)
+    assert st["admit_waits"] > 0
+    assert st["committed"] == b.n_txns
+    assert check(tabs, b, out, reads, final).ok
+
+
+def test_serve_needs_arrivals():
+    bb = binding()
+    tabs, b, arr, m = wl.serve_stream(100, 1e6, kv_rows=10_000, seed=34)
+    with bb.Engine(tabs) as eng:
+        bid = eng.submit(b, "occ")
+        with pytest.raises(bb.CCError) as e:
+            eng.run(bid, mode=bb.CC_MODE_SERVE)
+        assert e.value.status == bb.CC_E_STATE
+        with pytest.raises(bb.CCError):
+            bb.cc_set_arrivals(eng.ctx, bid, arr[::-1].copy() if len(arr) > 1 else np.array([-1]))
