@@ -106,6 +106,135 @@ def run_probes(ctx, binding, quick=False) -> dict:
     return {k: round(v, 3) for k, v in out.items()}
 
 
+def _emit(rec):
+    print(json.dumps(rec), flush=True)
+
+
+def _run_stats(eng, bid, n_txns, steps=2, warmup=1, reset=None, **params):
+    for _ in range(warmup):
+        if reset:
+            reset()
+        eng.run(bid, **params)
+    sts = []
+    for _ in range(steps):
+        if reset:
+            reset()
+        sts.append(eng.run(bid, **params))
+    run_ns = float(np.median([s["run_ns"] for s in sts]))
+    st = sts[-1]
+    att = float(np.mean([s["attempts"] for s in sts]))
+    busy = st["t_useful_ns"] + st["t_abort_ns"] + st["t_wait_ns"]
+    return {"txn_per_s": round(n_txns / (run_ns * 1e-9), 1), "run_ms": round(run_ns / 1e6, 3),
+            "kernel_ms": round(st["kernel_ns"] / 1e6, 3), "abort_rate": round((att - n_txns) / max(n_txns, 1), 3),
+            "p50_ms": round(st["lat_p50_ns"] / 1e6, 4), "p99_ms": round(st["lat_p99_ns"] / 1e6, 4),
+            "passes": st["passes"], "epochs": st["epochs"],
+            "breakdown": {k: round(st[f"t_{k}_ns"] / busy, 3) if busy else 0 for k in ("useful", "abort", "wait")}}
+
+
+def suite_schemes(args, binding, workload):
+    """Every scheme on the key-value config at each contention level."""
+    for theta in (0.0, 0.6, 0.9, 0.99):
+        tables, batch = workload.kv_workload(n_rows=args.rows, n_fields=args.fields, n_txns=args.txns,
+                                             ops=args.ops, theta=theta, seed=args.seed)
+        h = workload.hottest_row_writes(batch)[1]
+        eng = binding.Engine(tables)
+        for scheme in ("occ", "2pl_nw", "to", "mvcc", "tictoc"):
+            bid = eng.submit(batch, scheme)
+            rec = {"suite": "schemes", "theta": theta, "scheme": scheme, "hot_row_writes": h}
+            try:
+                rec.update(_run_stats(eng, bid, batch.n_txns))
+            except binding.CCError as e:
+                rec["error"] = str(e)
+            _emit(rec)
+            eng.release(bid)
+        eng.close()
+
+
+def suite_order_entry(args, binding, workload):
+    """Order-entry (NewOrder + Payment) at 1, 8 and 64 warehouses under every scheme."""
+    import oracle
+    for w in (1, 8, 64):
+        tables, batch = workload.order_entry_workload(w, args.oe_txns, seed=args.seed)
+        eng = binding.Engine(tables)
+        for scheme in ("occ", "2pl_nw", "to", "mvcc", "tictoc"):
+            bid = eng.submit(batch, scheme)
+            rec = {"suite": "order_entry", "warehouses": w, "txns": batch.n_txns, "scheme": scheme}
+            try:
+                eng.load(tables)
+                rec.update(_run_stats(eng, bid, batch.n_txns, steps=1, warmup=0))
+                out, reads = eng.outcomes(bid, batch.n_txns, batch.total_ops)
+                fin = eng.tables()
+                rep = oracle.check_run(tables, batch, out["status"], out["serial_hi"], out["serial_lo"], reads, fin)
+                rec["oracle_ok"] = bool(rep.ok)
+                rec["invariants"] = oracle.order_entry_invariants(tables, fin, batch, out["status"] == 1)
+            except binding.CCError as e:
+                rec["error"] = str(e)
+            _emit(rec)
+            eng.release(bid)
+        eng.close()
+
+
+def suite_batching(args, binding, workload):
+    """Uneven transactions (2-64 ops), Zipf 0.8: autotuned plain and epoch launches per batch size."""
+    from paper_2406_10158_amd import autotune
+    cache = autotune.TuneCache(os.path.join(ROOT, "paper_2406_10158_amd", "tuned.json"))
+    tables, full = workload.kv_workload(n_rows=args.rows, n_fields=args.fields, n_txns=1 << 20, ops=(2, 64),
+                                        theta=0.8, seed=args.seed)
+    eng = binding.Engine(tables)
+    for lg in range(14, 21):
+        batch = full if lg == 20 else full.subset(np.arange(1 << lg))
+        bid = eng.submit(batch, "occ")
+        default = _run_stats(eng, bid, batch.n_txns, steps=1, warmup=1)
+        best, res = autotune.tune(eng, bid, batch.n_txns,
+                                  log=lambda r: print(f"[tune] {batch.n_txns} {r.get('mode_name')} "
+                                                      f"L={r['lanes_per_txn']} W={r['waves_per_wg']} "
+                                                      f"{r.get('txn_per_s', 'infeasible')}", file=sys.stderr,
+                                                      flush=True))
+        key = autotune.TuneCache.key("kv-uneven-2-64", 0.8, batch.n_txns, "occ")
+        cache.put(key, best)
+        by_mode = {}
+        for r in res:
+            if r["feasible"]:
+                m = r["mode_name"]
+                if m not in by_mode or r["txn_per_s"] > by_mode[m]["txn_per_s"]:
+                    by_mode[m] = r
+        _emit({"suite": "batching", "batch": batch.n_txns, "default_plain": default,
+               "best": {m: {k: r[k] for k in ("lanes_per_txn", "waves_per_wg", "txn_per_s", "run_ms", "attempts",
+                                              "epochs", "p99_ms")} for m, r in by_mode.items()},
+               "infeasible": sum(1 for r in res if not r["feasible"]), "points": len(res)})
+        eng.release(bid)
+    cache.save()
+    eng.close()
+
+
+def suite_serving(args, binding, workload):
+    """Poisson streams of key-value (8-32 ops, Zipf 0.9) + order-entry (W=8) at increasing offered load."""
+    # one stream of transactions; each offered load rescales its arrival times
+    tables, batch, arr1, m = workload.serve_stream(args.serve_arrivals, 1e6, kv_rows=args.rows,
+                                                   kv_fields=args.fields, seed=args.seed)
+    eng = binding.Engine(tables)
+    bid = eng.submit(batch, "occ")
+    for rate in (1e6, 2e6, 5e6, 10e6, 20e6, 50e6):
+        arr = (arr1 * (1e6 / rate)).astype(np.int64)
+        binding.cc_set_arrivals(eng.ctx, bid, arr)
+        rec = {"suite": "serving", "offered_txn_per_s": rate, "arrivals": batch.n_txns,
+               "hbm_cap_bytes": args.serve_cap}
+        try:
+            eng.load(tables)
+            st = eng.run(bid, mode=binding.CC_MODE_SERVE, hbm_cap_bytes=args.serve_cap)
+            out, _ = eng.outcomes(bid, batch.n_txns, 0)
+            span_ns = float(out["commit_ns"].max())
+            rec.update(committed=st["committed"], committed_txn_per_s=round(st["committed"] / (span_ns * 1e-9), 1),
+                       p50_latency_ms=round(st["lat_p50_ns"] / 1e6, 4), p99_latency_ms=round(st["lat_p99_ns"] / 1e6, 4),
+                       abort_rate=round((st["attempts"] - st["committed"]) / max(st["committed"], 1), 3),
+                       admit_waits=st["admit_waits"], passes=st["passes"],
+                       stream_span_ms=round(float(arr[-1]) / 1e6, 3))
+        except binding.CCError as e:
+            rec["error"] = str(e)
+        _emit(rec)
+    eng.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +253,11 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probes", action="store_true", help="only run the memory micro-benchmarks")
+    ap.add_argument("--suite", choices=["schemes", "order_entry", "batching", "serving"],
+                    help="run a measurement suite instead of the headline step (JSON line per point)")
+    ap.add_argument("--oe-txns", type=int, default=100_000)
+    ap.add_argument("--serve-arrivals", type=int, default=100_000)
+    ap.add_argument("--serve-cap", type=int, default=4 << 30)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -139,6 +273,10 @@ def main():
         print(json.dumps({"probes": run_probes(ctx, binding)}))
         binding.cc_destroy(ctx)
         return
+    if args.suite:
+        {"schemes": suite_schemes, "order_entry": suite_order_entry, "batching": suite_batching,
+         "serving": suite_serving}[args.suite](args, binding, workload)
+        return
 
     t_gen = time.time()
     tables, batch = workload.kv_workload(n_rows=args.rows, n_fields=args.fields, n_txns=args.txns, ops=args.ops,
@@ -147,7 +285,7 @@ def main():
     print(f"[bench] generated {batch.n_txns} txns / {batch.total_ops} ops in {t_gen:.1f}s", file=sys.stderr,
           flush=True)
     torch.cuda.init()
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()  # default priority; the engine issues all its work on it
     eng = binding.Engine(tables, device=0, stream=stream.cuda_stream)
     bid = eng.submit(batch, args.scheme)
     params = dict(lanes_per_txn=args.lanes, waves_per_wg=args.waves, grid=args.grid, flags=args.flags)

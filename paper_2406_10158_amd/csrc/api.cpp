@@ -524,6 +524,46 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   int first_grid = 0;
   bool epoch_limit = false;
   const bool strict = (p.flags & CC_RUN_STRICT_FENCES) != 0;
+
+  // Plain passes over the pending transactions: each pass runs 8x fewer
+  // workgroups than the last, down to a single wavefront that never defers,
+  // so every transaction eventually runs without concurrency.
+  auto plain_passes = [&](int grid, uint32_t waves, bool first_is_all) -> cc_status {
+    bool all = first_is_all;
+    for (;;) {
+      if (!all) {
+        HIP_OR(c, launch_compact(c->stream, b.d_out, b.n_txns, a.max_attempts, b.d_list, c->d_ctl));
+        HIP_OR(c, hipMemcpyAsync(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+        HIP_OR(c, hipStreamSynchronize(c->stream));
+        a.list = b.d_list;
+        a.n_txns = h.pending_n;
+        a.pass = 1;  // attempt counts continue from the outcome records
+        a.n_from_ctl = 0;
+        a.arrival = nullptr;  // deferred transactions have all arrived
+        a.budget_cap = 0;
+      }
+      const bool last = grid == 1 && waves == 1;
+      a.defer_after = last ? 0u : defer;
+      HIP_OR(c, hipEventRecord(c->ev[1], c->stream));
+      int grid_used = 0;
+      hipError_t e = launch_txn(c->stream, b.scheme, (int)lanes, (int)b.max_ops, (int)waves, grid, strict, a, c->n_cu,
+                                &grid_used);
+      if (e != hipSuccess) return launch_error(c, e);
+      HIP_OR(c, hipEventRecord(c->ev[2], c->stream));
+      HIP_OR(c, hipStreamSynchronize(c->stream));
+      float ms = 0;
+      HIP_OR(c, hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
+      kernel_ms += ms;
+      if (first_grid == 0) first_grid = grid_used;
+      ++passes;
+      all = false;
+      HIP_OR(c, hipMemcpy(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+      if (h.stats[DS_COMMITTED] + h.stats[DS_GAVE_UP] >= b.n_txns || last) return CC_OK;
+      grid = std::max(1, grid_used / 8);
+      if (grid == 1) waves = 1;
+    }
+  };
+
   if (b.n_txns && p.mode == CC_MODE_EPOCH) {
     // Epochs: every pending transaction gets defer_after (default 1) attempts,
     // aborted ones wait for the next epoch.  One epoch = [reset claim counter,
@@ -531,6 +571,9 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
     // list]; EPOCHS_PER_GRAPH epochs are captured once as a hipGraph and the
     // graph is replayed until nothing is pending.  The kernel reads the
     // pending count from the control block, so the graph's arguments are fixed.
+    // A replay that commits almost nothing (symmetric conflicts repeating
+    // epoch after epoch) hands the rest to the plain passes, which always
+    // finish.
     constexpr uint32_t EPOCHS_PER_GRAPH = 4;
     const uint32_t max_epochs = p.max_epochs ? p.max_epochs : (1u << 20);
     a.defer_after = p.defer_after ? p.defer_after : 1;
@@ -569,6 +612,7 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
       b.epoch_grid = grid_used;
     }
     first_grid = b.epoch_grid;
+    uint64_t done_before = 0;
     for (;;) {
       HIP_OR(c, hipEventRecord(c->ev[1], c->stream));
       HIP_OR(c, hipGraphLaunch(b.epoch_graph, c->stream));
@@ -578,46 +622,26 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
       HIP_OR(c, hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
       kernel_ms += ms;
       epochs += EPOCHS_PER_GRAPH;
-      ++passes;
       HIP_OR(c, hipMemcpy(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
-      if (h.stats[DS_COMMITTED] + h.stats[DS_GAVE_UP] >= b.n_txns) break;
+      const uint64_t done = h.stats[DS_COMMITTED] + h.stats[DS_GAVE_UP];
+      if (done >= b.n_txns) break;
       if (epochs >= max_epochs) {
         epoch_limit = true;
         break;
       }
+      // fewer than 1/256 of the pending transactions committed in four epochs:
+      // the epochs are stalled on conflicts; finish with the plain passes
+      const uint64_t pending = b.n_txns - done;
+      if ((done - done_before) * 256 < pending || done == done_before) {
+        cc_status st = plain_passes(std::max(1, b.epoch_grid / 8), b.epoch_grid / 8 > 1 ? wpw : 1u, false);
+        if (st) return st;
+        break;
+      }
+      done_before = done;
     }
   } else if (b.n_txns) {
-    int grid = (int)p.grid;
-    uint32_t waves = wpw;
-    for (;;) {
-      const bool last = grid == 1 && waves == 1;
-      a.defer_after = last ? 0u : defer;
-      HIP_OR(c, hipEventRecord(c->ev[1], c->stream));
-      int grid_used = 0;
-      hipError_t e = launch_txn(c->stream, b.scheme, (int)lanes, (int)b.max_ops, (int)waves, grid, strict, a, c->n_cu,
-                                &grid_used);
-      if (e != hipSuccess) return launch_error(c, e);
-      HIP_OR(c, hipEventRecord(c->ev[2], c->stream));
-      HIP_OR(c, hipStreamSynchronize(c->stream));
-      float ms = 0;
-      HIP_OR(c, hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
-      kernel_ms += ms;
-      if (passes == 0) first_grid = grid_used;
-      ++passes;
-      HIP_OR(c, hipMemcpy(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
-      if (h.stats[DS_COMMITTED] + h.stats[DS_GAVE_UP] >= b.n_txns || last) break;
-      // next pass: the pending transactions, 8x fewer workgroups, down to one wavefront
-      HIP_OR(c, launch_compact(c->stream, b.d_out, b.n_txns, a.max_attempts, b.d_list, c->d_ctl));
-      HIP_OR(c, hipMemcpyAsync(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
-      HIP_OR(c, hipStreamSynchronize(c->stream));
-      a.list = b.d_list;
-      a.n_txns = h.pending_n;
-      a.pass = passes;
-      a.arrival = nullptr;  // deferred transactions have all arrived
-      a.budget_cap = 0;
-      grid = std::max(1, grid_used / 8);
-      if (grid == 1) waves = 1;
-    }
+    cc_status st = plain_passes((int)p.grid, wpw, true);
+    if (st) return st;
   }
   HIP_OR(c, hipEventRecord(c->ev[3], c->stream));
   HIP_OR(c, hipStreamSynchronize(c->stream));

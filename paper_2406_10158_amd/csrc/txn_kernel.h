@@ -63,22 +63,25 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
     if (ballot(txn >= 0) == 0) break;
     uint64_t now = wall_clock64();
     if (a.budget_cap && txn >= 0 && now >= ready_at && reserved == 0) {
-      // serving admission: reserve the transaction's log / version bytes, or
-      // wait a little and try again
+      // serving admission: reserve the transaction's log / version bytes by
+      // CAS, only if they fit (or nothing else is admitted: a transaction
+      // larger than the cap still runs, alone); failed tries leave the
+      // counter untouched, so they cannot crowd out each other
       uint64_t need = 0;
       if (t.tl == 0) {
-        need = (uint64_t)a.txns[txn].n * a.bytes_per_op + 1;
-        const uint64_t before = add_word(&a.ctl->budget_used, need);
-        // over the cap: back out, unless nothing else is admitted (a
-        // transaction larger than the cap still runs, alone)
-        if (before + need > a.budget_cap && before != 0) {
-          add_word(&a.ctl->budget_used, (uint64_t)0 - need);
-          need = 0;
-          ++n_admit_wait;
+        const uint64_t want = (uint64_t)a.txns[txn].n * a.bytes_per_op + 1;
+        uint64_t used = ld_word(&a.ctl->budget_used);
+        for (int it = 0; it < CAS_RETRIES; ++it) {
+          if (used != 0 && used + want > a.budget_cap) break;
+          if (cas_word(&a.ctl->budget_used, &used, used + want)) {
+            need = want;
+            break;
+          }
         }
+        if (need == 0) ++n_admit_wait;
       }
       reserved = (uint64_t)__shfl((long long)need, t.tb, 64);
-      if (reserved == 0) ready_at = now + a.backoff_ticks;
+      if (reserved == 0) ready_at = now + 1 + (mix64(((uint64_t)txn << 20) ^ now) % (8ull * a.backoff_ticks));
     }
     const bool active = txn >= 0 && now >= ready_at;
     if (ballot(active) == 0) {
