@@ -199,8 +199,8 @@ def suite_batching(args, binding, workload):
                 if m not in by_mode or r["txn_per_s"] > by_mode[m]["txn_per_s"]:
                     by_mode[m] = r
         _emit({"suite": "batching", "batch": batch.n_txns, "default_plain": default,
-               "best": {m: {k: r[k] for k in ("lanes_per_txn", "waves_per_wg", "txn_per_s", "run_ms", "attempts",
-                                              "epochs", "p99_ms")} for m, r in by_mode.items()},
+               "best": {m: {k: r[k] for k in ("lanes_per_txn", "waves_per_wg", "defer_after", "txn_per_s", "run_ms",
+                                              "attempts", "epochs", "p99_ms")} for m, r in by_mode.items()},
                "infeasible": sum(1 for r in res if not r["feasible"]), "points": len(res)})
         eng.release(bid)
     cache.save()

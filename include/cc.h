@@ -160,10 +160,13 @@ enum cc_mode { CC_MODE_PLAIN = 0, CC_MODE_EPOCH = 1, CC_MODE_SERVE = 2 };
 /* Run flags. */
 #define CC_RUN_STRICT_FENCES 0x1u /* agent-scope acquire/release fences (cache invalidate/write-back) at
                                      every ordering point instead of wait-for-completion only */
+#define CC_RUN_EAGER_INSTALL 0x2u /* OCC: store new values in the validation round (undo on abort) instead
+                                     of after validation succeeds; measured ~3% slower on the key-value
+                                     workload, kept for comparison */
 
 typedef struct {
   uint32_t lanes_per_txn; /* lanes cooperating on one transaction: 1, 4, 16, 64; 0 = smallest >= longest txn */
-  uint32_t waves_per_wg;  /* 64-lane wavefronts per workgroup, 1..16; 0 = 4 */
+  uint32_t waves_per_wg;  /* 64-lane wavefronts per workgroup, 1..16; 0 = 1 */
   uint32_t grid;          /* workgroups of the first pass; 0 = one per compute unit */
   uint32_t mode;          /* enum cc_mode */
   uint64_t max_attempts;  /* give up (CC_E_LIVELOCK) after this many attempts of one txn; 0 = 1<<24 */

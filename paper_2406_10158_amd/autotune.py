@@ -22,12 +22,15 @@ WAVES = (1, 2, 4, 8, 16)
 MODES = (("plain", b.CC_MODE_PLAIN), ("epoch", b.CC_MODE_EPOCH))
 
 
-def candidates(lanes=LANES, waves=WAVES, modes=MODES, grids=(0,)):
+def candidates(lanes=LANES, waves=WAVES, modes=MODES, grids=(0,), epoch_attempts=(1, 8)):
+    """Launch points to try; epoch mode also varies the attempts each transaction gets per epoch."""
     for mname, mode in modes:
         for L in lanes:
             for W in waves:
                 for G in grids:
-                    yield {"mode_name": mname, "mode": mode, "lanes_per_txn": L, "waves_per_wg": W, "grid": G}
+                    for d in (epoch_attempts if mode == b.CC_MODE_EPOCH else (0,)):
+                        yield {"mode_name": mname, "mode": mode, "lanes_per_txn": L, "waves_per_wg": W, "grid": G,
+                               "defer_after": d}
 
 
 def tune(engine, batch_id: int, n_txns: int, points=None, repeats: int = 1, reset=None, log=None):

@@ -93,7 +93,7 @@ struct RunArgs {
   const int64_t *arrival;  // serving: arrival time of each transaction, wall-clock ticks after start
   uint64_t budget_cap;     // serving: admission cap on reserved bytes (0: no cap)
   uint32_t bytes_per_op;   // serving: log / version bytes one operation reserves
-  uint32_t pad2;
+  uint32_t eager_install;  // OCC: store values in the validation round (undo on abort)
 };
 
 // Host-side launchers (kernels.hip).

@@ -22,13 +22,13 @@ namespace cce {
 //   R2  read every operation's value (write rows under our lock) and draw the
 //       serial ticket, which is also the TID our writes will carry.
 //   R3  validate: each read-only row still has the observed word, and every
-//       observed TID is older than our ticket.  In the same round the new
-//       values are stored under the write locks (eager install).  On a
-//       failed validation the pre-images are stored back before release.
+//       observed TID is older than our ticket; then store the new values
+//       and wait.  (CC_RUN_EAGER_INSTALL stores them in the validation round
+//       instead, and stores the pre-images back on a failed validation.)
 //   R4  store word = ticket on each write row: publishes the values and
-//       releases the lock in one store.  An aborted attempt releases with its
-//       ticket too (never the old word), so anyone who read a value it
-//       stored fails validation.
+//       releases the lock in one store.  A failed attempt restores the old
+//       word -- or, after an eager install, also publishes its ticket, so
+//       that anyone who read a value it stored fails validation.
 // The paper's Silo locks the write set at validation time, after its read
 // phase.  Read/write sets here are known before execution (Section 4.1,
 // "Constraints"), so write rows are locked first and read under the lock,
@@ -83,25 +83,27 @@ __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool a
       bad |= (s.v[k] & ~OCC_LOCK) >= ticket;
     }
   }
-  install_values<L, K>(t, s, alive, a);
+  const bool eager = a.eager_install != 0;
+  if (eager) install_values<L, K>(t, s, alive, a);
   const bool valid_fail = t.any(bad);
   const bool commit = alive && !valid_fail;
+  if (!eager) install_values<L, K>(t, s, commit, a);
   order_point<STRICT>();
-  if (alive && valid_fail) {
+  if (eager && alive && valid_fail) {
     // undo: put the pre-images back, and wait for them before the words
     // are released
 #pragma unroll
     for (int k = 0; k < K; ++k)
       if (s.valid[k] && op_kind(s.rowk[k]) != CC_READ) st_val(a.data + s.elem[k], s.x[k]);
   }
-  if (ballot(alive && valid_fail)) order_point<STRICT>();
+  if (eager && ballot(alive && valid_fail)) order_point<STRICT>();
   // R4: one store per write row publishes the values and releases the lock.
   // An aborted attempt also publishes its ticket as the row's TID: its values
   // were visible under the lock, so a reader that saw them must fail
   // validation, which a restored old TID would not guarantee.
 #pragma unroll
   for (int k = 0; k < K; ++k)
-    if (alive && s.got[k]) st_word(a.words + op_row(s.rowk[k]), ticket);
+    if (alive && s.got[k]) st_word(a.words + op_row(s.rowk[k]), (commit || eager) ? ticket : s.v[k]);
   *hi = 0;
   *lo = ticket;
   if (!active) return COMMIT;

@@ -63,19 +63,27 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
     if (ballot(txn >= 0) == 0) break;
     uint64_t now = wall_clock64();
     if (a.budget_cap && txn >= 0 && now >= ready_at && reserved == 0) {
-      // serving admission: reserve the transaction's log / version bytes by
-      // CAS, only if they fit (or nothing else is admitted: a transaction
-      // larger than the cap still runs, alone); failed tries leave the
-      // counter untouched, so they cannot crowd out each other
+      // serving admission: reserve the transaction's log / version bytes if
+      // they fit in the budget (or nothing else is admitted: a transaction
+      // larger than the cap still runs, alone)
       uint64_t need = 0;
       if (t.tl == 0) {
         const uint64_t want = (uint64_t)a.txns[txn].n * a.bytes_per_op + 1;
-        uint64_t used = ld_word(&a.ctl->budget_used);
-        for (int it = 0; it < CAS_RETRIES; ++it) {
-          if (used != 0 && used + want > a.budget_cap) break;
-          if (cas_word(&a.ctl->budget_used, &used, used + want)) {
-            need = want;
-            break;
+        // fast path: one fetch_add, kept if the total stays within the cap
+        const uint64_t before = add_word(&a.ctl->budget_used, want);
+        if (before + want <= a.budget_cap || before == 0) {
+          need = want;
+        } else {
+          add_word(&a.ctl->budget_used, (uint64_t)0 - want);
+          // the cap binds: reserve by CAS only if the bytes fit, so that
+          // tries which fail do not hold bytes others could use
+          uint64_t used = ld_word(&a.ctl->budget_used);
+          for (int it = 0; it < 4; ++it) {
+            if (used != 0 && used + want > a.budget_cap) break;
+            if (cas_word(&a.ctl->budget_used, &used, used + want)) {
+              need = want;
+              break;
+            }
           }
         }
         if (need == 0) ++n_admit_wait;

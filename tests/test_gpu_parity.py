@@ -140,6 +140,17 @@ def test_strict_fences(scheme):
     run_and_check(tabs, b, scheme, flags=b_.CC_RUN_STRICT_FENCES)
 
 
+@pytest.mark.parametrize("theta", [0.6, 0.99])
+def test_occ_eager_install(theta):
+    # values stored in the validation round and undone on abort; aborted
+    # attempts release with a fresh TID
+    b_ = binding()
+    tabs, b = wl.kv_workload(n_rows=20_000, n_fields=4, n_txns=20_000, ops=16, theta=theta, seed=17)
+    run_and_check(tabs, b, "occ", flags=b_.CC_RUN_EAGER_INSTALL)
+    tabs, b = wl.order_entry_workload(1, 1_000, seed=18)
+    run_and_check(tabs, b, "occ", flags=b_.CC_RUN_EAGER_INSTALL)
+
+
 @pytest.mark.parametrize("scheme", IMPLEMENTED)
 def test_repeated_runs_accumulate(scheme):
     tabs, b = wl.kv_workload(n_rows=10_000, n_fields=2, n_txns=8_000, ops=8, theta=0.9, seed=8)
@@ -266,7 +277,7 @@ def test_autotuner_picks_a_feasible_point():
         assert any(r["lanes_per_txn"] == 1 for r in infeasible)  # 64-op transactions do not fit one lane
         # the chosen point still produces a correct run
         eng.load(tabs)
-        params = {k: best[k] for k in ("mode", "lanes_per_txn", "waves_per_wg", "grid")}
+        params = {k: best[k] for k in ("mode", "lanes_per_txn", "waves_per_wg", "grid", "defer_after")}
         eng.run(bid, **params)
         out, reads = eng.outcomes(bid, b.n_txns, b.total_ops)
         assert check(tabs, b, out, reads, eng.tables()).ok
