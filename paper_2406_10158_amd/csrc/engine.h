@@ -65,7 +65,8 @@ struct Ctl {
   uint64_t ticket;       // serial ticket / timestamp counter (last value drawn)
   uint64_t start_clock;  // device wall clock at CC initialisation
   uint64_t pending_n;    // length of the pending list built between passes
-  uint64_t budget_used;  // serving: bytes reserved by admitted, uncommitted transactions
+  uint64_t budget_reserved;  // serving: bytes ever reserved (a FIFO position counter)
+  uint64_t budget_released;  // serving: bytes ever released
   uint64_t stats[DS_N];
 };
 

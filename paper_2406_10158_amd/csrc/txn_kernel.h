@@ -42,7 +42,9 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
   bool done = false;        // no transactions left for this team
   uint64_t n_commit = 0, n_att = 0, n_lock = 0, n_valid = 0, n_gave = 0, n_defer = 0, n_ovf = 0, max_att = 0;
   uint64_t t_useful = 0, t_abort = 0, t_wait = 0;  // per team, in leader lanes
-  uint64_t reserved = 0;    // serving: bytes this team's transaction holds in the budget
+  uint64_t reserved = 0;    // serving: bytes this team's transaction reserved (0: none)
+  uint64_t res_pos = 0;     // serving: the reservation's position in the byte queue
+  bool admitted = false;    // serving: the reservation has been granted
   uint64_t n_admit_wait = 0;
 
   for (;;) {
@@ -56,40 +58,36 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
         // serving: not before the transaction's arrival
         ready_at = a.arrival ? start_clock + (uint64_t)a.arrival[txn] : 0;
         reserved = 0;
+        admitted = false;
       } else {
         done = true;
       }
     }
     if (ballot(txn >= 0) == 0) break;
     uint64_t now = wall_clock64();
-    if (a.budget_cap && txn >= 0 && now >= ready_at && reserved == 0) {
-      // serving admission: reserve the transaction's log / version bytes if
-      // they fit in the budget (or nothing else is admitted: a transaction
-      // larger than the cap still runs, alone)
-      uint64_t need = 0;
+    if (a.budget_cap && txn >= 0 && now >= ready_at && !admitted) {
+      // serving admission, first come first served on bytes: an arrived
+      // transaction takes a position in a byte queue with one fetch_add on
+      // the reserved counter, and runs once the released counter shows that
+      // all but `cap` of the bytes queued before it (and its own) have been
+      // given back.  Waiting is a load; nothing is undone, so concurrent
+      // admissions cannot crowd each other out.  A transaction larger than
+      // the cap waits for everything before it, then runs alone.
+      uint64_t rs = reserved, pos = res_pos;
+      bool ok = false;
       if (t.tl == 0) {
-        const uint64_t want = (uint64_t)a.txns[txn].n * a.bytes_per_op + 1;
-        // fast path: one fetch_add, kept if the total stays within the cap
-        const uint64_t before = add_word(&a.ctl->budget_used, want);
-        if (before + want <= a.budget_cap || before == 0) {
-          need = want;
-        } else {
-          add_word(&a.ctl->budget_used, (uint64_t)0 - want);
-          // the cap binds: reserve by CAS only if the bytes fit, so that
-          // tries which fail do not hold bytes others could use
-          uint64_t used = ld_word(&a.ctl->budget_used);
-          for (int it = 0; it < 4; ++it) {
-            if (used != 0 && used + want > a.budget_cap) break;
-            if (cas_word(&a.ctl->budget_used, &used, used + want)) {
-              need = want;
-              break;
-            }
-          }
+        if (rs == 0) {
+          rs = (uint64_t)a.txns[txn].n * a.bytes_per_op + 1;
+          pos = add_word(&a.ctl->budget_reserved, rs);
         }
-        if (need == 0) ++n_admit_wait;
+        const uint64_t need = rs < a.budget_cap ? rs : a.budget_cap;
+        ok = ld_word(&a.ctl->budget_released) + a.budget_cap >= pos + need;
+        if (!ok) ++n_admit_wait;
       }
-      reserved = (uint64_t)__shfl((long long)need, t.tb, 64);
-      if (reserved == 0) ready_at = now + 1 + (mix64(((uint64_t)txn << 20) ^ now) % (8ull * a.backoff_ticks));
+      reserved = (uint64_t)__shfl((long long)rs, t.tb, 64);
+      res_pos = (uint64_t)__shfl((long long)pos, t.tb, 64);
+      admitted = __shfl((int)ok, t.tb, 64) != 0;
+      if (!admitted) ready_at = now + 1 + (mix64(((uint64_t)txn << 20) ^ now) % (4ull * a.backoff_ticks));
     }
     const bool active = txn >= 0 && now >= ready_at;
     if (ballot(active) == 0) {
@@ -150,7 +148,7 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
 #pragma unroll
         for (int k = 0; k < K; ++k)
           if (s.valid[k]) __builtin_nontemporal_store(s.x[k], a.reads + first + t.tl + k * L);
-        if (reserved && t.tl == 0) add_word(&a.ctl->budget_used, (uint64_t)0 - reserved);
+        if (reserved && t.tl == 0) add_word(&a.ctl->budget_released, reserved);
         reserved = 0;
         txn = -1;
       } else {
@@ -166,7 +164,7 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
             a.out[txn].attempts = attempts;
             if (r == TS_OVERFLOW || attempts >= a.max_attempts) ++n_gave; else ++n_defer;
             max_att = attempts > max_att ? attempts : max_att;
-            if (reserved) add_word(&a.ctl->budget_used, (uint64_t)0 - reserved);
+            if (reserved) add_word(&a.ctl->budget_released, reserved);
           }
           reserved = 0;
           txn = -1;
