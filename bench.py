@@ -324,10 +324,11 @@ def main():
         with open(args.traffic_json) as f:
             tj = json.load(f)
         t = tj.get(f"{args.scheme}:{args.theta}:{args.rows}x{args.fields}:{args.txns}x{args.ops}")
-        src = os.path.join(ROOT, "paper_2406_10158_amd", "csrc", "kernels.hip")
-        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        csrc = os.path.join(ROOT, "paper_2406_10158_amd", "csrc")
+        cur = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                      for f in ("kernels.hip", "schemes.h", "txn_kernel.h", "device.h"))).hexdigest()[:16]
         # counters taken on another version of the kernel do not describe this one
-        if t and t.get("kernels_hip_sha256_16") == cur:
+        if t and t.get("kernel_src_sha256_16") == cur:
             traffic = t["total_bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
