@@ -160,6 +160,10 @@ enum cc_mode { CC_MODE_PLAIN = 0, CC_MODE_EPOCH = 1, CC_MODE_SERVE = 2 };
 /* Run flags. */
 #define CC_RUN_STRICT_FENCES 0x1u /* agent-scope acquire/release fences (cache invalidate/write-back) at
                                      every ordering point instead of wait-for-completion only */
+#define CC_RUN_WAIT_UNLOCK 0x4u   /* (currently rejected with CC_E_INVAL) after failing on a row another
+                                     transaction holds, look at that row's word between attempts and
+                                     retry once it is free.  Disabled: teams of one wavefront that block
+                                     each other retry in lockstep and can livelock in the final pass. */
 #define CC_RUN_EAGER_INSTALL 0x2u /* OCC: store new values in the validation round (undo on abort) instead
                                      of after validation succeeds; measured ~3% slower on the key-value
                                      workload, kept for comparison */

@@ -32,6 +32,7 @@ CC_MODE_PLAIN, CC_MODE_EPOCH, CC_MODE_SERVE = 0, 1, 2
 CC_SERVE_BYTES_PER_OP = 32
 CC_RUN_STRICT_FENCES = 0x1
 CC_RUN_EAGER_INSTALL = 0x2
+CC_RUN_WAIT_UNLOCK = 0x4
 STAT_NAMES = ["committed", "attempts", "abort_lock", "abort_valid", "kernel_ns", "run_ns", "tickets",
               "max_attempts", "lat_p50_ns", "lat_p99_ns", "epochs", "passes", "deferred", "grid",
               "t_useful_ns", "t_abort_ns", "t_wait_ns", "gave_up", "admit_waits"]

@@ -482,7 +482,14 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   if (lanes != 1 && lanes != 4 && lanes != 16 && lanes != 64) return fail(c, CC_E_INVAL, "lanes_per_txn must be 1, 4, 16 or 64");
   const uint32_t wpw = p.waves_per_wg ? p.waves_per_wg : 1;
   if (wpw < 1 || wpw > 16) return fail(c, CC_E_INVAL, "waves_per_wg must be 1..16");
-  if (p.flags & ~(CC_RUN_STRICT_FENCES | CC_RUN_EAGER_INSTALL)) return fail(c, CC_E_INVAL, "unknown run flag");
+  if (p.flags & ~(CC_RUN_STRICT_FENCES | CC_RUN_EAGER_INSTALL | CC_RUN_WAIT_UNLOCK))
+    return fail(c, CC_E_INVAL, "unknown run flag");
+  if (p.flags & CC_RUN_WAIT_UNLOCK)
+    // Switched off: two teams of one wavefront that block each other both see
+    // the row free on their next loop iteration (each attempt releases its
+    // locks before returning) and retry together, so in the final
+    // single-wavefront pass, which never defers, they can conflict forever.
+    return fail(c, CC_E_INVAL, "CC_RUN_WAIT_UNLOCK is disabled (same-wavefront retries can livelock)");
   if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
 
   RunArgs a{};
@@ -506,6 +513,7 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   a.ns_per_tick_q16 = (uint32_t)((1000000ull << 16) / c->wallclock_khz);
   a.has_slot = b.has_slot ? 1u : 0u;
   a.eager_install = (p.flags & CC_RUN_EAGER_INSTALL) ? 1u : 0u;
+  a.wait_unlock = (p.flags & CC_RUN_WAIT_UNLOCK) ? 1u : 0u;
 
   const uint32_t defer = p.defer_after ? p.defer_after : (p.mode == CC_MODE_SERVE ? 256 : 16);
   a.pass = 0;

@@ -168,7 +168,18 @@ struct Slots {
   uint32_t oi[K]; // op index in the batch
   bool got[K];    // this slot holds its row's lock
   bool valid[K];
+  uint32_t block; // a row another transaction held when this attempt failed to lock (~0u: none)
 };
+
+// The first row (in lane order) that a lane of my team found held by another
+// transaction, or ~0u.  Team-uniform; every lane of the wavefront must call it.
+template <int L>
+__device__ __forceinline__ uint32_t blocking_row(const Team<L> &t, uint32_t my_row) {
+  const uint64_t m = ballot(my_row != ~0u) & t.tmask;
+  if (m == 0) return ~0u;
+  const int src = __ffsll((unsigned long long)m) - 1;
+  return (uint32_t)__shfl((int)my_row, src, 64);
+}
 
 // Value read by op `src` of the team's transaction (lane src%L, slot src/L).
 template <int L, int K>

@@ -95,6 +95,8 @@ struct RunArgs {
   uint64_t budget_cap;     // serving: admission cap on reserved bytes (0: no cap)
   uint32_t bytes_per_op;   // serving: log / version bytes one operation reserves
   uint32_t eager_install;  // OCC: store values in the validation round (undo on abort)
+  uint32_t wait_unlock;    // after a lock failure, poll the held row until it is free
+  uint32_t pad3;
 };
 
 // Host-side launchers (kernels.hip).

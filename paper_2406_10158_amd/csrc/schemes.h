@@ -42,6 +42,7 @@ template <int L, int K, bool STRICT>
 __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a,
                                            uint64_t *hi, uint64_t *lo) {
   bool fail = false;
+  uint32_t blk = ~0u;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     s.got[k] = false;
@@ -51,15 +52,18 @@ __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool a
         const uint64_t old = or_word(w, OCC_LOCK);
         s.v[k] = old;
         s.got[k] = !(old & OCC_LOCK);
+        if (!s.got[k] && blk == ~0u) blk = op_row(s.rowk[k]);
         fail |= !s.got[k];
       } else {
         const uint64_t o = ld_word(w);
         s.v[k] = o;
+        if ((o & OCC_LOCK) && blk == ~0u) blk = op_row(s.rowk[k]);
         fail |= (o & OCC_LOCK) != 0;
       }
     }
   }
   order_point<STRICT>();
+  s.block = blocking_row(t, blk);
   const bool lock_fail = t.any(fail);
   const bool alive = active && !lock_fail;
   if (active && lock_fail) {
@@ -129,6 +133,7 @@ template <int L, int K, bool STRICT>
 __device__ __forceinline__ int tpl_attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a,
                                            uint32_t txn, uint64_t *hi, uint64_t *lo) {
   bool fail = false;
+  uint32_t blk = ~0u;
   bool shared[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -139,16 +144,19 @@ __device__ __forceinline__ int tpl_attempt(const Team<L> &t, Slots<K> &s, bool a
       if (op_written(s.rowk[k])) {
         uint64_t expected = 0;
         s.got[k] = cas_word(w, &expected, TPL_EXCL | ((uint64_t)(txn & 0x7FFFFFFFu) << 32));
+        if (!s.got[k] && (expected & TPL_EXCL) && blk == ~0u) blk = op_row(s.rowk[k]);
         fail |= !s.got[k];
       } else {
         const uint64_t old = add_word(w, 1ull);
         shared[k] = true;  // our increment is in the word until we take it out
         s.got[k] = !(old & TPL_EXCL);
+        if (!s.got[k] && blk == ~0u) blk = op_row(s.rowk[k]);
         fail |= !s.got[k];
       }
     }
   }
   order_point<STRICT>();
+  s.block = blocking_row(t, blk);
   const bool lock_fail = t.any(fail);
   const bool alive = active && !lock_fail;
   if (active && lock_fail) {
@@ -217,6 +225,7 @@ __device__ __forceinline__ int to_attempt(const Team<L> &t, Slots<K> &s, bool ac
   const uint64_t ts = t.claim(&a.ctl->ticket, active, 1) + 1;
   const bool overflow = active && ts > TO_MASK31;
   bool fail = overflow;
+  uint32_t blk = ~0u;
   bool old_ver[K];  // MVCC: this op reads a version older than the current one
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -253,10 +262,12 @@ __device__ __forceinline__ int to_attempt(const Team<L> &t, Slots<K> &s, bool ac
         }
       }
       s.v[k] = w;
+      if ((w & TO_DIRTY) && bad && blk == ~0u) blk = op_row(s.rowk[k]);
       fail |= bad || !done;
     }
   }
   order_point<STRICT>();
+  s.block = blocking_row(t, blk);
   const bool lock_fail = t.any(fail);
   const bool alive = active && !lock_fail;
   if (active && lock_fail) {
@@ -372,6 +383,7 @@ template <int L, int K, bool STRICT>
 __device__ __forceinline__ int tictoc_attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a,
                                               uint64_t *hi, uint64_t *lo) {
   bool fail = false;
+  uint32_t blk = ~0u;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     s.got[k] = false;
@@ -381,15 +393,18 @@ __device__ __forceinline__ int tictoc_attempt(const Team<L> &t, Slots<K> &s, boo
         const uint64_t old = or_word(w, TT_LOCK);
         s.v[k] = old;
         s.got[k] = !(old & TT_LOCK);
+        if (!s.got[k] && blk == ~0u) blk = op_row(s.rowk[k]);
         fail |= !s.got[k];
       } else {
         const uint64_t o = ld_word(w);
         s.v[k] = o;
+        if ((o & TT_LOCK) && blk == ~0u) blk = op_row(s.rowk[k]);
         fail |= (o & TT_LOCK) != 0;
       }
     }
   }
   order_point<STRICT>();
+  s.block = blocking_row(t, blk);
   const bool lock_fail = t.any(fail);
   const bool alive = active && !lock_fail;
   if (active && lock_fail) {

@@ -45,6 +45,8 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
   uint64_t reserved = 0;    // serving: bytes this team's transaction reserved (0: none)
   uint64_t res_pos = 0;     // serving: the reservation's position in the byte queue
   bool admitted = false;    // serving: the reservation has been granted
+  uint32_t wait_row = ~0u;  // row whose release the team waits for (~0u: none)
+  uint32_t polls = 0;
   uint64_t n_admit_wait = 0;
 
   for (;;) {
@@ -59,6 +61,7 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
         ready_at = a.arrival ? start_clock + (uint64_t)a.arrival[txn] : 0;
         reserved = 0;
         admitted = false;
+        wait_row = ~0u;
       } else {
         done = true;
       }
@@ -88,6 +91,26 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
       res_pos = (uint64_t)__shfl((long long)pos, t.tb, 64);
       admitted = __shfl((int)ok, t.tb, 64) != 0;
       if (!admitted) ready_at = now + 1 + (mix64(((uint64_t)txn << 20) ^ now) % (4ull * a.backoff_ticks));
+    }
+    if (wait_row != ~0u && txn >= 0 && now >= ready_at) {
+      // waiting for a row another transaction holds: look at its word (a
+      // load, not an atomic) and retry once it is free.  The gaps between
+      // looks grow exponentially (randomised), so that however many teams
+      // wait on one hot row, their loads cannot queue up on that address
+      // ahead of the holder's own release.  After a bounded number of looks
+      // the team falls back to the ordinary back-off.
+      bool free_now = false;
+      if (t.tl == 0) free_now = (ld_word(a.words + wait_row) >> 63) == 0;
+      free_now = __shfl((int)free_now, t.tb, 64) != 0;
+      if (free_now) {
+        wait_row = ~0u;
+      } else {
+        ++polls;
+        const uint32_t sh = polls < 10 ? polls : 10;
+        ready_at = now + 1 + (mix64(((uint64_t)txn << 24) ^ ((uint64_t)polls << 8) ^ attempts) %
+                              ((uint64_t)a.backoff_ticks << sh));
+        if (polls >= 16) wait_row = ~0u;
+      }
     }
     const bool active = txn >= 0 && now >= ready_at;
     if (ballot(active) == 0) {
@@ -121,6 +144,7 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
       s.v[k] = 0;
     }
     uint64_t key_hi = 0, key_lo = 0;
+    s.block = ~0u;
     const int r = attempt<L, K, SCHEME, STRICT>(t, s, active, a, (uint32_t)(txn < 0 ? 0 : txn), &key_hi, &key_lo);
     if (t.tl == 0 && txn >= 0) {
       const uint64_t dt = wall_clock64() - now;
@@ -168,6 +192,11 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
           }
           reserved = 0;
           txn = -1;
+        } else if (a.wait_unlock && r == ABORT_LOCK && s.block != ~0u) {
+          // retry when the row that stopped us is released
+          wait_row = s.block;
+          polls = 0;
+          ready_at = now + 1 + (mix64(((uint64_t)txn << 20) ^ attempts) % a.backoff_ticks);
         } else {
           // randomised exponential back-off
           const uint32_t sh = pass_att < 12 ? pass_att : 12;

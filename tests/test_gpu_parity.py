@@ -140,6 +140,29 @@ def test_strict_fences(scheme):
     run_and_check(tabs, b, scheme, flags=b_.CC_RUN_STRICT_FENCES)
 
 
+@pytest.mark.skip(reason="CC_RUN_WAIT_UNLOCK is switched off: two teams of one wavefront that block each other "
+                         "see the row free on the next loop iteration and retry in lockstep, which livelocked "
+                         "the final single-wavefront pass (a GPU run went silent); cc_run rejects the flag")
+@pytest.mark.parametrize("scheme", IMPLEMENTED)
+def test_wait_unlock_retry_policy(scheme):
+    b_ = binding()
+    tabs, b = wl.kv_workload(n_rows=20_000, n_fields=4, n_txns=20_000, ops=16, theta=0.99, seed=27)
+    run_and_check(tabs, b, scheme, flags=b_.CC_RUN_WAIT_UNLOCK)
+    tabs, b = wl.order_entry_workload(1, 1_000, seed=28)
+    run_and_check(tabs, b, scheme, flags=b_.CC_RUN_WAIT_UNLOCK)
+
+
+def test_wait_unlock_flag_is_rejected():
+    b_ = binding()
+    tabs, b = wl.kv_workload(n_rows=1_000, n_fields=2, n_txns=100, ops=4, seed=29)
+    with b_.Engine(tabs) as eng:
+        bid = eng.submit(b, "occ")
+        with pytest.raises(b_.CCError) as e:
+            eng.run(bid, flags=b_.CC_RUN_WAIT_UNLOCK)
+        assert e.value.status == b_.CC_E_INVAL
+        assert np.array_equal(eng.tables()[0], tabs[0])
+
+
 @pytest.mark.parametrize("theta", [0.6, 0.99])
 def test_occ_eager_install(theta):
     # values stored in the validation round and undone on abort; aborted
