@@ -164,6 +164,11 @@ enum cc_mode { CC_MODE_PLAIN = 0, CC_MODE_EPOCH = 1, CC_MODE_SERVE = 2 };
                                      transaction holds, look at that row's word between attempts and
                                      retry once it is free.  Disabled: teams of one wavefront that block
                                      each other retry in lockstep and can livelock in the final pass. */
+#define CC_RUN_PRECHECK 0x8u      /* OCC: an extra first round loads every row's word and aborts before
+                                     taking any lock if one is held -- on every attempt.  By default it
+                                     runs from a transaction's third attempt on (repeated failures are
+                                     the sign of contention) */
+#define CC_RUN_NO_PRECHECK 0x10u  /* OCC: never run the pre-check round */
 #define CC_RUN_EAGER_INSTALL 0x2u /* OCC: store new values in the validation round (undo on abort) instead
                                      of after validation succeeds; measured ~3% slower on the key-value
                                      workload, kept for comparison */
@@ -207,6 +212,10 @@ enum cc_stat {
   CC_STAT_T_WAIT_NS = 16,  /* summed over transactions: back-off time between attempts */
   CC_STAT_GAVE_UP = 17,    /* transactions left pending (attempt limit or timestamp overflow) */
   CC_STAT_ADMIT_WAITS = 18,/* CC_MODE_SERVE: admissions postponed because the byte budget was full */
+  CC_STAT_OCC_R1_NS = 19,  /* OCC, summed over committed attempts: time in round 1 (locks, read words), */
+  CC_STAT_OCC_R2_NS = 20,  /*   round 2 (values + ticket), round 3 (validation + install) and round 4 */
+  CC_STAT_OCC_R3_NS = 21,  /*   (release) */
+  CC_STAT_OCC_R4_NS = 22,
   CC_N_STATS = 24
 };
 

@@ -169,6 +169,7 @@ struct Slots {
   bool got[K];    // this slot holds its row's lock
   bool valid[K];
   uint32_t block; // a row another transaction held when this attempt failed to lock (~0u: none)
+  uint64_t tr[4]; // wall clock at the end of each round (OCC; for the per-round time breakdown)
 };
 
 // The first row (in lane order) that a lane of my team found held by another

@@ -57,6 +57,10 @@ enum DevStat {
   DS_T_ABORT = 9,
   DS_T_WAIT = 10,
   DS_ADMIT_WAITS = 11,  // serving: admissions deferred because the byte budget was full
+  DS_R1 = 12,           // OCC, committed attempts: ticks in each round (lock / read+ticket /
+  DS_R2 = 13,           //   validate+install / release)
+  DS_R3 = 14,
+  DS_R4 = 15,
   DS_N = 16
 };
 
@@ -96,7 +100,7 @@ struct RunArgs {
   uint32_t bytes_per_op;   // serving: log / version bytes one operation reserves
   uint32_t eager_install;  // OCC: store values in the validation round (undo on abort)
   uint32_t wait_unlock;    // after a lock failure, poll the held row until it is free
-  uint32_t pad3;
+  uint32_t precheck;       // OCC load-only round before any lock: 0 never, 1 on retries, 2 always
 };
 
 // Host-side launchers (kernels.hip).

@@ -40,13 +40,36 @@ constexpr uint64_t OCC_LOCK = 1ull << 63;
 
 template <int L, int K, bool STRICT>
 __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a,
-                                           uint64_t *hi, uint64_t *lo) {
+                                           bool precheck, uint64_t *hi, uint64_t *lo) {
   bool fail = false;
   uint32_t blk = ~0u;
+  bool pre_fail = false;
+  if (ballot(active && precheck)) {
+    // R0, by default from a transaction's third attempt on: load every row's
+    // word and give up before taking any lock if one is held, so that
+    // failing attempts never hold rows (or write their lines) while they
+    // fail elsewhere.  Read-only rows keep the word loaded here, exactly as
+    // R1 would load it.  Early attempts skip it: until a transaction has
+    // failed repeatedly there is little sign of contention, and at low
+    // contention the extra round (which its whole wavefront waits for) costs
+    // more than it saves.
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (active && precheck && s.valid[k] && op_leader(s.rowk[k])) {
+        const uint64_t o = ld_word(a.words + op_row(s.rowk[k]));
+        s.v[k] = o;
+        if ((o & OCC_LOCK) && blk == ~0u) blk = op_row(s.rowk[k]);
+        fail |= (o & OCC_LOCK) != 0;
+      }
+    }
+    order_point<STRICT>();
+    pre_fail = t.any(fail);
+  }
+  const bool go = active && !pre_fail;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     s.got[k] = false;
-    if (active && s.valid[k] && op_leader(s.rowk[k])) {
+    if (go && s.valid[k] && op_leader(s.rowk[k]) && (!precheck || op_written(s.rowk[k]))) {
       uint64_t *w = a.words + op_row(s.rowk[k]);
       if (op_written(s.rowk[k])) {
         const uint64_t old = or_word(w, OCC_LOCK);
@@ -63,6 +86,7 @@ __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool a
     }
   }
   order_point<STRICT>();
+  s.tr[0] = wall_clock64();
   s.block = blocking_row(t, blk);
   const bool lock_fail = t.any(fail);
   const bool alive = active && !lock_fail;
@@ -77,6 +101,7 @@ __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool a
     if (alive && s.valid[k]) s.x[k] = ld_val(a.data + s.elem[k]);
   const uint64_t ticket = t.claim(&a.ctl->ticket, alive, 1) + 1;
   order_point<STRICT>();
+  s.tr[1] = wall_clock64();
   // R3: validation loads, and -- in the same round -- the new values stored
   // under the write locks (eager install)
   bool bad = false;
@@ -93,6 +118,7 @@ __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool a
   const bool commit = alive && !valid_fail;
   if (!eager) install_values<L, K>(t, s, commit, a);
   order_point<STRICT>();
+  s.tr[2] = wall_clock64();
   if (eager && alive && valid_fail) {
     // undo: put the pre-images back, and wait for them before the words
     // are released
@@ -108,6 +134,7 @@ __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool a
 #pragma unroll
   for (int k = 0; k < K; ++k)
     if (alive && s.got[k]) st_word(a.words + op_row(s.rowk[k]), (commit || eager) ? ticket : s.v[k]);
+  s.tr[3] = wall_clock64();
   *hi = 0;
   *lo = ticket;
   if (!active) return COMMIT;

@@ -16,8 +16,11 @@ struct MaxThreads {
 
 template <int L, int K, int SCHEME, bool STRICT>
 __device__ __forceinline__ int attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a, uint32_t txn,
-                                       uint64_t *hi, uint64_t *lo) {
-  if constexpr (SCHEME == CC_OCC) return occ_attempt<L, K, STRICT>(t, s, active, a, hi, lo);
+                                       bool retry, uint64_t *hi, uint64_t *lo) {
+  if constexpr (SCHEME == CC_OCC) {
+    const bool precheck = a.precheck == 2 || (a.precheck == 1 && retry);
+    return occ_attempt<L, K, STRICT>(t, s, active, a, precheck, hi, lo);
+  }
   else if constexpr (SCHEME == CC_2PL_NW) return tpl_attempt<L, K, STRICT>(t, s, active, a, txn, hi, lo);
   else if constexpr (SCHEME == CC_TO) return to_attempt<L, K, STRICT, false>(t, s, active, a, hi, lo);
   else if constexpr (SCHEME == CC_MVCC) return to_attempt<L, K, STRICT, true>(t, s, active, a, hi, lo);
@@ -45,6 +48,7 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
   uint64_t reserved = 0;    // serving: bytes this team's transaction reserved (0: none)
   uint64_t res_pos = 0;     // serving: the reservation's position in the byte queue
   bool admitted = false;    // serving: the reservation has been granted
+  uint64_t t_round[4] = {0, 0, 0, 0};  // OCC committed attempts: per-round ticks
   uint32_t wait_row = ~0u;  // row whose release the team waits for (~0u: none)
   uint32_t polls = 0;
   uint64_t n_admit_wait = 0;
@@ -145,12 +149,21 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
     }
     uint64_t key_hi = 0, key_lo = 0;
     s.block = ~0u;
-    const int r = attempt<L, K, SCHEME, STRICT>(t, s, active, a, (uint32_t)(txn < 0 ? 0 : txn), &key_hi, &key_lo);
+    const int r = attempt<L, K, SCHEME, STRICT>(t, s, active, a, (uint32_t)(txn < 0 ? 0 : txn), attempts >= 2,
+                                                &key_hi, &key_lo);
     if (t.tl == 0 && txn >= 0) {
       const uint64_t dt = wall_clock64() - now;
       if (!active) t_wait += dt;
       else if (r == COMMIT) t_useful += dt;
       else t_abort += dt;
+      if constexpr (SCHEME == CC_OCC) {
+        if (active && r == COMMIT) {
+          t_round[0] += s.tr[0] - now;
+          t_round[1] += s.tr[1] - s.tr[0];
+          t_round[2] += s.tr[2] - s.tr[1];
+          t_round[3] += s.tr[3] - s.tr[2];
+        }
+      }
     }
     if (active) {
       ++attempts;
@@ -212,6 +225,9 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
                  c4 = wave_sum(n_gave), c5 = wave_max(max_att), c6 = wave_sum(n_defer), c7 = wave_sum(n_ovf);
   const uint64_t c8 = wave_sum(t_useful), c9 = wave_sum(t_abort), c10 = wave_sum(t_wait),
                  c11 = wave_sum(n_admit_wait);
+  uint64_t cr[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) cr[i] = wave_sum(t_round[i]);
   if (t.lane == 0) {
     if (c0) atomicAdd((unsigned long long *)&a.ctl->stats[DS_COMMITTED], (unsigned long long)c0);
     if (c1) atomicAdd((unsigned long long *)&a.ctl->stats[DS_ATTEMPTS], (unsigned long long)c1);
@@ -225,6 +241,9 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
     if (c9) atomicAdd((unsigned long long *)&a.ctl->stats[DS_T_ABORT], (unsigned long long)c9);
     if (c10) atomicAdd((unsigned long long *)&a.ctl->stats[DS_T_WAIT], (unsigned long long)c10);
     if (c11) atomicAdd((unsigned long long *)&a.ctl->stats[DS_ADMIT_WAITS], (unsigned long long)c11);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (cr[i]) atomicAdd((unsigned long long *)&a.ctl->stats[DS_R1 + i], (unsigned long long)cr[i]);
   }
 }
 

@@ -163,6 +163,18 @@ def test_wait_unlock_flag_is_rejected():
         assert np.array_equal(eng.tables()[0], tabs[0])
 
 
+@pytest.mark.parametrize("flags", ["precheck", "precheck+eager", "no-precheck"])
+@pytest.mark.parametrize("theta", [0.6, 0.99])
+def test_occ_precheck(theta, flags):
+    b_ = binding()
+    f = {"precheck": b_.CC_RUN_PRECHECK, "precheck+eager": b_.CC_RUN_PRECHECK | b_.CC_RUN_EAGER_INSTALL,
+         "no-precheck": b_.CC_RUN_NO_PRECHECK}[flags]
+    tabs, b = wl.kv_workload(n_rows=20_000, n_fields=4, n_txns=20_000, ops=16, theta=theta, seed=37)
+    run_and_check(tabs, b, "occ", flags=f)
+    tabs, b = wl.order_entry_workload(1, 1_000, seed=38)
+    run_and_check(tabs, b, "occ", flags=f)
+
+
 @pytest.mark.parametrize("theta", [0.6, 0.99])
 def test_occ_eager_install(theta):
     # values stored in the validation round and undone on abort; aborted
