@@ -645,7 +645,8 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
       // the epochs are stalled on conflicts; finish with the plain passes
       const uint64_t pending = b.n_txns - done;
       if ((done - done_before) * 256 < pending || done == done_before) {
-        cc_status st = plain_passes(std::max(1, b.epoch_grid / 8), b.epoch_grid / 8 > 1 ? wpw : 1u, false);
+        // continue as a plain run would: same grid, then 8x smaller passes
+        cc_status st = plain_passes(b.epoch_grid, wpw, false);
         if (st) return st;
         break;
       }
