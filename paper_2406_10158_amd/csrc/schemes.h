@@ -102,8 +102,8 @@ __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool a
   const uint64_t ticket = t.claim(&a.ctl->ticket, alive, 1) + 1;
   order_point<STRICT>();
   s.tr[1] = wall_clock64();
-  // R3: validation loads, and -- in the same round -- the new values stored
-  // under the write locks (eager install)
+  // R3: validation loads (with CC_RUN_EAGER_INSTALL also the new values,
+  // stored under the write locks in the same round)
   bool bad = false, unfixable = false;
   uint64_t seen[K];  // read-only rows: the word found at validation
 #pragma unroll
