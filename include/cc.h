@@ -169,9 +169,6 @@ enum cc_mode { CC_MODE_PLAIN = 0, CC_MODE_EPOCH = 1, CC_MODE_SERVE = 2 };
                                      runs from a transaction's third attempt on (repeated failures are
                                      the sign of contention) */
 #define CC_RUN_NO_PRECHECK 0x10u  /* OCC: never run the pre-check round */
-#define CC_RUN_NO_REPAIR 0x20u    /* OCC: abort when a read-only row moved, instead of re-reading it at
-                                     its newer committed version (the default for batches without
-                                     CC_WRITE_SLOT) */
 #define CC_RUN_EAGER_INSTALL 0x2u /* OCC: store new values in the validation round (undo on abort) instead
                                      of after validation succeeds; measured ~3% slower on the key-value
                                      workload, kept for comparison */
@@ -219,7 +216,6 @@ enum cc_stat {
   CC_STAT_OCC_R2_NS = 20,  /*   round 2 (values + ticket), round 3 (validation + install) and round 4 */
   CC_STAT_OCC_R3_NS = 21,  /*   (release) */
   CC_STAT_OCC_R4_NS = 22,
-  CC_STAT_REPAIRS = 23,    /* OCC: commits that needed a read repair */
   CC_N_STATS = 32
 };
 

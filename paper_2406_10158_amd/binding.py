@@ -35,11 +35,10 @@ CC_RUN_EAGER_INSTALL = 0x2
 CC_RUN_WAIT_UNLOCK = 0x4
 CC_RUN_PRECHECK = 0x8
 CC_RUN_NO_PRECHECK = 0x10
-CC_RUN_NO_REPAIR = 0x20
 STAT_NAMES = ["committed", "attempts", "abort_lock", "abort_valid", "kernel_ns", "run_ns", "tickets",
               "max_attempts", "lat_p50_ns", "lat_p99_ns", "epochs", "passes", "deferred", "grid",
               "t_useful_ns", "t_abort_ns", "t_wait_ns", "gave_up", "admit_waits",
-              "occ_r1_ns", "occ_r2_ns", "occ_r3_ns", "occ_r4_ns", "repairs"]
+              "occ_r1_ns", "occ_r2_ns", "occ_r3_ns", "occ_r4_ns"]
 CC_N_STATS = 32
 
 OP_DTYPE = np.dtype([("row", "<u4"), ("table", "<u2"), ("field", "u1"), ("kind", "u1"), ("arg", "<i8")])

@@ -482,8 +482,8 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   if (lanes != 1 && lanes != 4 && lanes != 16 && lanes != 64) return fail(c, CC_E_INVAL, "lanes_per_txn must be 1, 4, 16 or 64");
   const uint32_t wpw = p.waves_per_wg ? p.waves_per_wg : 1;
   if (wpw < 1 || wpw > 16) return fail(c, CC_E_INVAL, "waves_per_wg must be 1..16");
-  if (p.flags & ~(CC_RUN_STRICT_FENCES | CC_RUN_EAGER_INSTALL | CC_RUN_WAIT_UNLOCK | CC_RUN_PRECHECK |
-                  CC_RUN_NO_PRECHECK | CC_RUN_NO_REPAIR))
+  if (p.flags &
+      ~(CC_RUN_STRICT_FENCES | CC_RUN_EAGER_INSTALL | CC_RUN_WAIT_UNLOCK | CC_RUN_PRECHECK | CC_RUN_NO_PRECHECK))
     return fail(c, CC_E_INVAL, "unknown run flag");
   if (p.flags & CC_RUN_WAIT_UNLOCK)
     // Switched off: two teams of one wavefront that block each other both see
@@ -516,7 +516,6 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   a.eager_install = (p.flags & CC_RUN_EAGER_INSTALL) ? 1u : 0u;
   a.wait_unlock = (p.flags & CC_RUN_WAIT_UNLOCK) ? 1u : 0u;
   a.precheck = (p.flags & CC_RUN_PRECHECK) ? 2u : ((p.flags & CC_RUN_NO_PRECHECK) ? 0u : 1u);
-  a.repair = (p.flags & CC_RUN_NO_REPAIR) || b.has_slot ? 0u : 1u;
 
   const uint32_t defer = p.defer_after ? p.defer_after : (p.mode == CC_MODE_SERVE ? 256 : 16);
   a.pass = 0;
@@ -682,7 +681,6 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   b.stats[CC_STAT_ADMIT_WAITS] = h.stats[DS_ADMIT_WAITS];
   for (int i = 0; i < 4; ++i)
     b.stats[CC_STAT_OCC_R1_NS + i] = (uint64_t)((double)h.stats[DS_R1 + i] * ns_per_tick);
-  b.stats[CC_STAT_REPAIRS] = h.stats[DS_REPAIRS];
   b.ran = true;
   if (b.n_txns) {
     std::vector<cc_outcome> o(b.n_txns);

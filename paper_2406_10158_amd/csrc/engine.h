@@ -61,7 +61,6 @@ enum DevStat {
   DS_R2 = 13,           //   validate+install / release)
   DS_R3 = 14,
   DS_R4 = 15,
-  DS_REPAIRS = 16,      // OCC: attempts that committed after a read repair
   DS_N = 24
 };
 
@@ -102,8 +101,7 @@ struct RunArgs {
   uint32_t eager_install;  // OCC: store values in the validation round (undo on abort)
   uint32_t wait_unlock;    // after a lock failure, poll the held row until it is free
   uint32_t precheck;       // OCC load-only round before any lock: 0 never, 1 on retries, 2 always
-  uint32_t repair;         // OCC: repair moved read-only rows instead of aborting
-  uint32_t pad4;
+  uint32_t pad4[2];
 };
 
 // Host-side launchers (kernels.hip).

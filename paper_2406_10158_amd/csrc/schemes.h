@@ -40,7 +40,7 @@ constexpr uint64_t OCC_LOCK = 1ull << 63;
 
 template <int L, int K, bool STRICT>
 __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a,
-                                           bool precheck, uint64_t *hi, uint64_t *lo, bool *repaired) {
+                                           bool precheck, uint64_t *hi, uint64_t *lo) {
   bool fail = false;
   uint32_t blk = ~0u;
   bool pre_fail = false;
@@ -104,52 +104,17 @@ __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool a
   s.tr[1] = wall_clock64();
   // R3: validation loads (with CC_RUN_EAGER_INSTALL also the new values,
   // stored under the write locks in the same round)
-  bool bad = false, unfixable = false;
-  uint64_t seen[K];  // read-only rows: the word found at validation
+  bool bad = false;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    seen[k] = s.v[k];
     if (alive && s.valid[k] && op_leader(s.rowk[k])) {
-      if (!op_written(s.rowk[k])) {
-        seen[k] = ld_word(a.words + op_row(s.rowk[k]));
-        if (seen[k] != s.v[k]) {
-          bad = true;
-          // a newer committed version, older than our ticket, can be read instead
-          unfixable |= (seen[k] & OCC_LOCK) || seen[k] >= ticket;
-        }
-      }
-      if ((s.v[k] & ~OCC_LOCK) >= ticket) bad = unfixable = true;
+      if (!op_written(s.rowk[k])) bad |= ld_word(a.words + op_row(s.rowk[k])) != s.v[k];
+      bad |= (s.v[k] & ~OCC_LOCK) >= ticket;
     }
   }
   const bool eager = a.eager_install != 0;
   if (eager) install_values<L, K>(t, s, alive, a);
-  bool valid_fail = t.any(bad);
-  // Read repair (default when no operation computes its value from another's
-  // read): a transaction whose only failures are read-only rows that moved
-  // to a newer committed version below its ticket re-reads those rows'
-  // values at that version and re-checks the words, instead of aborting
-  // while it holds its write locks.  Its writes do not depend on these
-  // values, and the re-check comes after the ticket, so the serial-order
-  // argument above is unchanged.
-  const bool repair = alive && valid_fail && a.repair && !eager && !t.any(unfixable);
-  if (ballot(repair)) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (repair && s.valid[k] && !op_written(s.rowk[k])) {
-        s.x[k] = ld_val(a.data + s.elem[k]);
-        if (op_leader(s.rowk[k])) s.v[k] = seen[k];
-      }
-    }
-    order_point<STRICT>();
-    bool moved = false;
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (repair && s.valid[k] && op_leader(s.rowk[k]) && !op_written(s.rowk[k]))
-        moved |= ld_word(a.words + op_row(s.rowk[k])) != s.v[k];
-    const bool ok = !t.any(moved);
-    if (repair && ok) valid_fail = false;
-    if (repair) *repaired = ok;
-  }
+  const bool valid_fail = t.any(bad);
   const bool commit = alive && !valid_fail;
   if (!eager) install_values<L, K>(t, s, commit, a);
   order_point<STRICT>();

@@ -16,10 +16,10 @@ struct MaxThreads {
 
 template <int L, int K, int SCHEME, bool STRICT>
 __device__ __forceinline__ int attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a, uint32_t txn,
-                                       bool retry, uint64_t *hi, uint64_t *lo, bool *repaired) {
+                                       bool retry, uint64_t *hi, uint64_t *lo) {
   if constexpr (SCHEME == CC_OCC) {
     const bool precheck = a.precheck == 2 || (a.precheck == 1 && retry);
-    return occ_attempt<L, K, STRICT>(t, s, active, a, precheck, hi, lo, repaired);
+    return occ_attempt<L, K, STRICT>(t, s, active, a, precheck, hi, lo);
   }
   else if constexpr (SCHEME == CC_2PL_NW) return tpl_attempt<L, K, STRICT>(t, s, active, a, txn, hi, lo);
   else if constexpr (SCHEME == CC_TO) return to_attempt<L, K, STRICT, false>(t, s, active, a, hi, lo);
@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
   uint64_t t_round[4] = {0, 0, 0, 0};  // OCC committed attempts: per-round ticks
   uint32_t wait_row = ~0u;  // row whose release the team waits for (~0u: none)
   uint32_t polls = 0;
-  uint64_t n_admit_wait = 0, n_repair = 0;
+  uint64_t n_admit_wait = 0;
 
   for (;;) {
     const bool need = txn < 0 && !done;
@@ -149,10 +149,8 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
     }
     uint64_t key_hi = 0, key_lo = 0;
     s.block = ~0u;
-    bool repaired = false;
     const int r = attempt<L, K, SCHEME, STRICT>(t, s, active, a, (uint32_t)(txn < 0 ? 0 : txn), attempts >= 2,
-                                                &key_hi, &key_lo, &repaired);
-    if (active && repaired && t.tl == 0) ++n_repair;
+                                                &key_hi, &key_lo);
     if (t.tl == 0 && txn >= 0) {
       const uint64_t dt = wall_clock64() - now;
       if (!active) t_wait += dt;
@@ -230,7 +228,6 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
   uint64_t cr[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) cr[i] = wave_sum(t_round[i]);
-  const uint64_t c12 = wave_sum(n_repair);
   if (t.lane == 0) {
     if (c0) atomicAdd((unsigned long long *)&a.ctl->stats[DS_COMMITTED], (unsigned long long)c0);
     if (c1) atomicAdd((unsigned long long *)&a.ctl->stats[DS_ATTEMPTS], (unsigned long long)c1);
@@ -247,7 +244,6 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
       if (cr[i]) atomicAdd((unsigned long long *)&a.ctl->stats[DS_R1 + i], (unsigned long long)cr[i]);
-    if (c12) atomicAdd((unsigned long long *)&a.ctl->stats[DS_REPAIRS], (unsigned long long)c12);
   }
 }
 

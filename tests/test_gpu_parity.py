@@ -175,21 +175,6 @@ def test_occ_precheck(theta, flags):
     run_and_check(tabs, b, "occ", flags=f)
 
 
-@pytest.mark.parametrize("theta", [0.9, 0.99])
-def test_occ_read_repair(theta):
-    # read-only rows that moved to a newer version below the ticket are re-read instead of aborting
-    b_ = binding()
-    tabs, b = wl.kv_workload(n_rows=20_000, n_fields=4, n_txns=30_000, ops=16, theta=theta, seed=47)
-    out, reads, final, st = run_and_check(tabs, b, "occ", lanes_per_txn=16, waves_per_wg=4)
-    assert st["repairs"] > 0
-    out, reads, final, st = run_and_check(tabs, b, "occ", flags=b_.CC_RUN_NO_REPAIR, lanes_per_txn=16, waves_per_wg=4)
-    assert st["repairs"] == 0
-    # batches with computed writes never repair
-    tabs, b = wl.order_entry_workload(1, 1_000, seed=48)
-    out, reads, final, st = run_and_check(tabs, b, "occ")
-    assert st["repairs"] == 0
-
-
 @pytest.mark.parametrize("theta", [0.6, 0.99])
 def test_occ_eager_install(theta):
     # values stored in the validation round and undone on abort; aborted
