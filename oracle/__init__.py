@@ -18,6 +18,10 @@ order out of all k! must do so (``bruteforce_count``).  The paper's own check
 is acyclicity of a conflict graph built from an event log (Section 3.4,
 "Measurements and Verification"); replaying a total order is a stronger form
 of the same test.
+
+The deterministic scheme (GaccO, conflict-graph ordering) does fix a unique
+outcome: ``id_order_expected`` is the serial execution in transaction-id
+order, compared element by element.
 """
 from __future__ import annotations
 
@@ -109,6 +113,22 @@ def replay(tables, batch, order):
 def serial_execute(tables, batch):
     """Execute every transaction of the batch serially in id order (no concurrency)."""
     return replay(tables, batch, np.arange(batch.n_txns, dtype=np.int64))
+
+
+def id_order_expected(tables, batch):
+    """Expected (final_tables, reads) of a conflict-graph-ordering run (GaccO).
+
+    GaccO gathers every (transaction id, data item) access into an access
+    table, orders each item's accesses by transaction id, and hands the item
+    to its accessors one after the other in that order, reads and writes alike
+    (Section 2, "Conflict Graph Ordering"; Section 3, "Conflict Graph
+    Ordering").  Every conflict between two transactions is therefore ordered
+    from the smaller id to the larger, the conflict graph is acyclic with the
+    id order as a topological order, and the run is equivalent to executing
+    the transactions serially in id order.  The outcome is unique (the scheme
+    is deterministic), so parity is element by element against this replay.
+    """
+    return serial_execute(tables, batch)
 
 
 def serial_order(status, serial_hi, serial_lo):
