@@ -138,7 +138,7 @@ def suite_schemes(args, binding, workload):
                                              ops=args.ops, theta=theta, seed=args.seed)
         h = workload.hottest_row_writes(batch)[1]
         eng = binding.Engine(tables)
-        for scheme in ("occ", "2pl_nw", "to", "mvcc", "tictoc"):
+        for scheme in ("occ", "2pl_nw", "to", "mvcc", "tictoc", "gacco"):
             bid = eng.submit(batch, scheme)
             rec = {"suite": "schemes", "theta": theta, "scheme": scheme, "hot_row_writes": h}
             try:
@@ -156,7 +156,7 @@ def suite_order_entry(args, binding, workload):
     for w in (1, 8, 64):
         tables, batch = workload.order_entry_workload(w, args.oe_txns, seed=args.seed)
         eng = binding.Engine(tables)
-        for scheme in ("occ", "2pl_nw", "to", "mvcc", "tictoc"):
+        for scheme in ("occ", "2pl_nw", "to", "mvcc", "tictoc", "gacco"):
             bid = eng.submit(batch, scheme)
             rec = {"suite": "order_entry", "warehouses": w, "txns": batch.n_txns, "scheme": scheme}
             try:
@@ -332,7 +332,7 @@ def main():
             traffic = t["total_bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
-                "kernel": "txn_kernel", "launches_per_step": launches,
+                "kernel": "gacco_kernel" if args.scheme == "gacco" else "txn_kernel", "launches_per_step": launches,
                 "algorithmic_bytes_per_launch": int(alg / launches),
                 "avg_launch_ms": round(k_step_s * 1e3 / launches, 4)}
 

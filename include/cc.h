@@ -3,7 +3,7 @@
  *
  * The engine executes a batch of read / read-modify-write transactions
  * concurrently against tables resident in device memory (HBM), under one of
- * five concurrency-control schemes, and reports per transaction a serial key
+ * six concurrency-control schemes, and reports per transaction a serial key
  * that orders the committed transactions into an equivalent serial execution.
  *
  * Problem statement followed (paper Section 4.1, "Constraints" and
@@ -60,9 +60,15 @@ enum cc_scheme {
   CC_2PL_NW = 1, /* two-phase locking, no-wait */
   CC_TO = 2,     /* basic timestamp ordering: commit bit + 31-bit RTS + 31-bit WTS */
   CC_MVCC = 3,   /* multi-version timestamp ordering (TO word + version pointer) */
-  CC_TICTOC = 4  /* TicToc: lock bit + 15-bit delta + 48-bit WTS */
+  CC_TICTOC = 4, /* TicToc: lock bit + 15-bit delta + 48-bit WTS */
+  CC_GACCO = 5   /* GaccO, conflict-graph ordering (Section 2 and Section 3, "Conflict Graph
+                    Ordering"): preprocessing sorts every row's accesses by transaction id into
+                    a lock table; each row is then handed to its accessors in that order, reads
+                    and writes alike.  Deterministic, no aborts.  Needs each transaction's ops
+                    after the previous transaction's (first_op nondecreasing) and
+                    CC_MODE_PLAIN; accepts only CC_RUN_STRICT_FENCES. */
 };
-#define CC_N_SCHEMES 5
+#define CC_N_SCHEMES 6
 
 /*
  * Operation kinds.  An operation touches one field of one row.  Its read
@@ -114,7 +120,8 @@ enum cc_txn_status { CC_PENDING = 0, CC_COMMITTED = 1 };
  *   OCC, 2PL:  (0, ticket)  -- ticket drawn from one device counter while the
  *                              transaction holds all its write locks;
  *   TO, MVCC:  (0, ts)      -- the timestamp of the committing attempt;
- *   TicToc:    (commit_ts, ticket).
+ *   TicToc:    (commit_ts, ticket);
+ *   GaccO:     (0, transaction index) -- the scheme's order is the id order.
  * attempts counts executions of the transaction, so attempts-1 are aborts
  * (the paper's abort rate is aborts / committed, Section 4.1 "Metric
  * Selection").  commit_ns is the device wall-clock time of the commit,
@@ -216,6 +223,8 @@ enum cc_stat {
   CC_STAT_OCC_R2_NS = 20,  /*   round 2 (values + ticket), round 3 (validation + install) and round 4 */
   CC_STAT_OCC_R3_NS = 21,  /*   (release) */
   CC_STAT_OCC_R4_NS = 22,
+  CC_STAT_PREP_NS = 23,    /* GaccO: preprocessing (access table, radix sort, lock table), HIP events;
+                              part of CC_STAT_RUN_NS */
   CC_N_STATS = 32
 };
 
@@ -257,7 +266,8 @@ cc_status cc_read_table(cc_ctx *ctx, uint32_t table_id, int64_t *out, int out_on
  * Validate a batch of n_txns transactions over n_ops operations and stage it
  * in device memory for `scheme`.  txns/ops are host arrays (on_device = 0).
  * Errors: CC_E_INVAL (bad scheme/kind, op ranges outside the ops array,
- * WRITE_SLOT source not earlier, too many ops in a txn), CC_E_RANGE,
+ * WRITE_SLOT source not earlier, too many ops in a txn; for CC_GACCO, a
+ * transaction whose first_op is below the previous one's), CC_E_RANGE,
  * CC_E_DUPROW.  *batch_id receives a handle valid until cc_release_batch or
  * cc_destroy.  Zero transactions is a valid (empty) batch.
  */
@@ -281,7 +291,10 @@ cc_status cc_check_batch(uint32_t n_tables, const uint64_t *n_rows, const uint32
  * each run applies its writes to the current tables.
  * params may be NULL (all defaults).  Returns CC_E_LIVELOCK if a transaction
  * exhausted max_attempts (its status stays CC_PENDING and it left no writes),
- * CC_E_TS_OVERFLOW if a timestamp field overflowed.
+ * CC_E_TS_OVERFLOW if a timestamp field overflowed.  CC_GACCO runs every
+ * transaction exactly once after its preprocessing (CC_STAT_PREP_NS); it
+ * returns CC_E_LIVELOCK only if a transaction waited more than 4 s for its
+ * turn on a row, which a consistent lock table rules out.
  */
 cc_status cc_run(cc_ctx *ctx, uint64_t batch_id, const cc_run_params *params);
 

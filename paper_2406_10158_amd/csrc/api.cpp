@@ -33,6 +33,8 @@ struct Batch {
   int64_t *d_reads = nullptr;
   uint32_t *d_list = nullptr;  // pending transactions between passes
   uint64_t *d_nodes = nullptr; // MVCC history nodes (3 words per op)
+  uint32_t *d_rank = nullptr;    // GaccO: per row-group leader, its position in the sorted access table
+  uint32_t *d_gscratch = nullptr;// GaccO: access-table and sort buffers
   int64_t *d_arrival = nullptr;           // serving: arrival ticks per transaction
   std::vector<int64_t> arrival_ns;        // host copy, for latency statistics
   hipGraphExec_t epoch_graph = nullptr;  // captured epochs for the last epoch-mode parameters
@@ -59,7 +61,7 @@ struct cc_ctx {
   Ctl *d_ctl = nullptr;
   std::map<uint64_t, Batch> batches;
   uint64_t next_batch = 1;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   std::string err;
 };
 
@@ -121,6 +123,10 @@ void free_batch(Batch &b) {
   if (b.d_reads) (void)hipFree(b.d_reads);
   if (b.d_list) (void)hipFree(b.d_list);
   if (b.d_nodes) (void)hipFree(b.d_nodes);
+  if (b.d_rank) (void)hipFree(b.d_rank);
+  if (b.d_gscratch) (void)hipFree(b.d_gscratch);
+  b.d_rank = nullptr;
+  b.d_gscratch = nullptr;
   if (b.epoch_graph) (void)hipGraphExecDestroy(b.epoch_graph);
   if (b.d_arrival) (void)hipFree(b.d_arrival);
   b.d_arrival = nullptr;
@@ -322,14 +328,18 @@ namespace {
 // Validate a batch against table shapes and build its device descriptors.
 cc_status validate_and_pack(cc_ctx *c, const std::vector<Table> &tables, const cc_txn *txns, uint64_t n_txns,
                             const cc_op *ops, uint64_t n_ops, std::vector<DevOp> *dops_out,
-                            std::vector<DevTxn> *dtx_out, uint32_t *max_ops_out, bool *has_slot_out) {
+                            std::vector<DevTxn> *dtx_out, uint32_t *max_ops_out, bool *has_slot_out,
+                            bool *txn_ordered_out) {
   if ((n_txns && !txns) || (n_ops && !ops)) return fail(c, CC_E_INVAL, "null array");
   if (n_txns > 0xFFFFFFFFull || n_ops > 0xFFFFFFFFull) return fail(c, CC_E_RANGE, "batch too large");
   std::vector<DevOp> dummy_ops;
   std::vector<DevTxn> dummy_tx;
   std::vector<DevOp> &dops = dops_out ? *dops_out : dummy_ops;
   std::vector<DevTxn> &dtx = dtx_out ? *dtx_out : dummy_tx;
-  dops.assign(n_ops, DevOp{0, 0, 0});
+  // operations no transaction refers to are marked as followers: they never
+  // enter GaccO's access table
+  dops.assign(n_ops, DevOp{FOLLOWER_BIT, 0, 0});
+  bool txn_ordered = true;  // every transaction's ops come after the previous one's
   dtx.assign(n_txns, DevTxn{0, 0});
   std::vector<uint8_t> used(n_ops, 0);  // every op belongs to at most one transaction
   std::vector<uint64_t> keys;           // (table,row) of row leaders, for the duplicate check
@@ -340,6 +350,7 @@ cc_status validate_and_pack(cc_ctx *c, const std::vector<Table> &tables, const c
     if (x.reserved != 0) return fail(c, CC_E_INVAL, "cc_txn.reserved must be 0");
     if (x.n_ops > CC_MAX_OPS_PER_TXN) return fail(c, CC_E_INVAL, "transaction has too many ops");
     if (x.first_op > n_ops || x.n_ops > n_ops - x.first_op) return fail(c, CC_E_INVAL, "op range outside ops");
+    if (t > 0 && x.first_op < txns[t - 1].first_op) txn_ordered = false;
     for (uint32_t i = 0; i < x.n_ops; ++i) {
       if (used[x.first_op + i]) return fail(c, CC_E_INVAL, "transactions share operations");
       used[x.first_op + i] = 1;
@@ -387,6 +398,7 @@ cc_status validate_and_pack(cc_ctx *c, const std::vector<Table> &tables, const c
   }
   if (max_ops_out) *max_ops_out = max_ops;
   if (has_slot_out) *has_slot_out = has_slot;
+  if (txn_ordered_out) *txn_ordered_out = txn_ordered;
   return CC_OK;
 }
 
@@ -399,6 +411,79 @@ std::vector<Table> layout_tables(uint32_t n_tables, const uint64_t *n_rows, cons
     cells += n_rows[t] * n_fields[t];
   }
   return v;
+}
+
+// GaccO run: CC initialisation, preprocessing (access table, sort, lock
+// table), one execution pass.  Every transaction runs exactly once.
+constexpr uint64_t GACCO_WAIT_LIMIT_MS = 4000;
+
+cc_status run_gacco(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes, uint32_t wpw) {
+  if (p.mode != CC_MODE_PLAIN)
+    return fail(c, CC_E_INVAL,
+                "CC_GACCO runs in CC_MODE_PLAIN only: it never aborts, so epochs have nothing to retry, and it "
+                "orders the whole batch before running it");
+  if (p.flags & ~CC_RUN_STRICT_FENCES) return fail(c, CC_E_INVAL, "CC_GACCO accepts only CC_RUN_STRICT_FENCES");
+  GaccoArgs a{};
+  a.ops = b.d_ops;
+  a.txns = b.d_txns;
+  a.n_txns = b.n_txns;
+  a.rank = b.d_rank;
+  a.data = c->d_data;
+  a.words = c->d_words;
+  a.out = b.d_out;
+  a.reads = b.d_reads;
+  a.ctl = c->d_ctl;
+  a.wait_limit_ticks = (uint64_t)c->wallclock_khz * GACCO_WAIT_LIMIT_MS;
+  const uint64_t poll_ns = p.backoff_ns ? p.backoff_ns : 200;
+  a.poll_ticks = (uint32_t)std::max<uint64_t>(1, poll_ns * c->wallclock_khz / 1000000ull);
+  a.ns_per_tick_q16 = (uint32_t)((1000000ull << 16) / c->wallclock_khz);
+  a.has_slot = b.has_slot ? 1u : 0u;
+  const bool strict = (p.flags & CC_RUN_STRICT_FENCES) != 0;
+
+  HIP_OR(c, hipEventRecord(c->ev[0], c->stream));
+  // the lock table sets the word of every accessed row, so words need no clearing
+  HIP_OR(c, launch_init(c->stream, c->d_words, 0, nullptr, 0, b.d_out, b.n_txns, c->d_ctl, p.ts_start));
+  HIP_OR(c, hipEventRecord(c->ev[4], c->stream));
+  HIP_OR(c, gacco_prepare(c->stream, b.d_ops, b.n_ops, (uint32_t)c->total_rows, c->d_words, b.d_rank, b.d_gscratch,
+                          c->d_ctl));
+  HIP_OR(c, hipEventRecord(c->ev[5], c->stream));
+  HIP_OR(c, hipEventRecord(c->ev[1], c->stream));
+  int grid_used = 0;
+  if (b.n_txns) {
+    hipError_t e = launch_gacco(c->stream, (int)lanes, (int)b.max_ops, (int)wpw, (int)p.grid, strict, a, c->n_cu,
+                                &grid_used);
+    if (e != hipSuccess) return launch_error(c, e);
+  }
+  HIP_OR(c, hipEventRecord(c->ev[2], c->stream));
+  HIP_OR(c, hipEventRecord(c->ev[3], c->stream));
+  HIP_OR(c, hipStreamSynchronize(c->stream));
+  Ctl h{};
+  HIP_OR(c, hipMemcpy(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+  float ms_run = 0, ms_prep = 0, ms_kernel = 0;
+  HIP_OR(c, hipEventElapsedTime(&ms_run, c->ev[0], c->ev[3]));
+  HIP_OR(c, hipEventElapsedTime(&ms_prep, c->ev[4], c->ev[5]));
+  HIP_OR(c, hipEventElapsedTime(&ms_kernel, c->ev[1], c->ev[2]));
+  std::memset(b.stats, 0, sizeof(b.stats));
+  b.stats[CC_STAT_COMMITTED] = h.stats[DS_COMMITTED];
+  b.stats[CC_STAT_ATTEMPTS] = h.stats[DS_ATTEMPTS];
+  b.stats[CC_STAT_KERNEL_NS] = (uint64_t)((double)ms_kernel * 1e6);
+  b.stats[CC_STAT_RUN_NS] = (uint64_t)((double)ms_run * 1e6);
+  b.stats[CC_STAT_PREP_NS] = (uint64_t)((double)ms_prep * 1e6);
+  b.stats[CC_STAT_MAX_ATTEMPTS] = h.stats[DS_MAX_ATTEMPTS];
+  b.stats[CC_STAT_PASSES] = b.n_txns ? 1 : 0;
+  b.stats[CC_STAT_GRID] = (uint64_t)grid_used;
+  const double ns_per_tick = 1e6 / (double)c->wallclock_khz;
+  b.stats[CC_STAT_T_USEFUL_NS] = (uint64_t)((double)h.stats[DS_T_USEFUL] * ns_per_tick);
+  b.stats[CC_STAT_T_WAIT_NS] = (uint64_t)((double)h.stats[DS_T_WAIT] * ns_per_tick);
+  b.ran = true;
+  if (b.n_txns) {
+    std::vector<cc_outcome> o(b.n_txns);
+    HIP_OR(c, hipMemcpy(o.data(), b.d_out, b.n_txns * sizeof(cc_outcome), hipMemcpyDeviceToHost));
+    latency_percentiles(o, &b.stats[CC_STAT_LAT_P50_NS], &b.stats[CC_STAT_LAT_P99_NS]);
+  }
+  if (h.stop) return fail(c, CC_E_LIVELOCK, "CC_GACCO: a transaction waited past the limit for its turn on a row");
+  if (h.stats[DS_COMMITTED] != b.n_txns) return fail(c, CC_E_LIVELOCK, "CC_GACCO: not every transaction ran");
+  return CC_OK;
 }
 
 }  // namespace
@@ -416,8 +501,11 @@ cc_status cc_check_batch(uint32_t n_tables, const uint64_t *n_rows, const uint32
     cells += n_rows[t] * n_fields[t];
   }
   if (rows > CC_MAX_TOTAL_ROWS || cells > CC_MAX_TOTAL_CELLS) return CC_E_RANGE;
-  return validate_and_pack(nullptr, layout_tables(n_tables, n_rows, n_fields), txns, n_txns, ops, n_ops, nullptr,
-                           nullptr, nullptr, nullptr);
+  bool ordered = true;
+  const cc_status st = validate_and_pack(nullptr, layout_tables(n_tables, n_rows, n_fields), txns, n_txns, ops, n_ops,
+                                         nullptr, nullptr, nullptr, nullptr, &ordered);
+  if (st == CC_OK && scheme == CC_GACCO && !ordered) return CC_E_INVAL;
+  return st;
 }
 
 cc_status cc_submit_batch(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, const cc_op *ops, uint64_t n_ops,
@@ -431,9 +519,11 @@ cc_status cc_submit_batch(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, const 
   std::vector<DevOp> dops;
   std::vector<DevTxn> dtx;
   uint32_t max_ops = 0;
-  bool has_slot = false;
-  cc_status st = validate_and_pack(c, c->tables, txns, n_txns, ops, n_ops, &dops, &dtx, &max_ops, &has_slot);
+  bool has_slot = false, ordered = true;
+  cc_status st = validate_and_pack(c, c->tables, txns, n_txns, ops, n_ops, &dops, &dtx, &max_ops, &has_slot, &ordered);
   if (st) return st;
+  if (scheme == CC_GACCO && !ordered)
+    return fail(c, CC_E_INVAL, "CC_GACCO needs each transaction's ops after the previous transaction's (first_op nondecreasing)");
 
   Batch b;
   b.scheme = scheme;
@@ -448,7 +538,10 @@ cc_status cc_submit_batch(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, const 
       (e = alloc((void **)&b.d_out, n_txns * sizeof(DevOutcome))) != hipSuccess ||
       (e = alloc((void **)&b.d_reads, n_ops * sizeof(int64_t))) != hipSuccess ||
       (e = alloc((void **)&b.d_list, n_txns * sizeof(uint32_t))) != hipSuccess ||
-      (scheme == CC_MVCC && (e = alloc((void **)&b.d_nodes, n_ops * 3 * sizeof(uint64_t))) != hipSuccess)) {
+      (scheme == CC_MVCC && (e = alloc((void **)&b.d_nodes, n_ops * 3 * sizeof(uint64_t))) != hipSuccess) ||
+      (scheme == CC_GACCO && (e = alloc((void **)&b.d_rank, n_ops * sizeof(uint32_t))) != hipSuccess) ||
+      (scheme == CC_GACCO &&
+       (e = alloc((void **)&b.d_gscratch, gacco_scratch_words(n_ops) * sizeof(uint32_t))) != hipSuccess)) {
     free_batch(b);
     return hip_fail(c, e, "batch allocation");
   }
@@ -492,6 +585,7 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
     // single-wavefront pass, which never defers, they can conflict forever.
     return fail(c, CC_E_INVAL, "CC_RUN_WAIT_UNLOCK is disabled (same-wavefront retries can livelock)");
   if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
+  if (b.scheme == CC_GACCO) return run_gacco(c, b, p, lanes, wpw);
 
   RunArgs a{};
   a.ops = b.d_ops;

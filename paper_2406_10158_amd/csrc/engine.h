@@ -72,6 +72,7 @@ struct Ctl {
   uint64_t budget_reserved;  // serving: bytes ever reserved (a FIFO position counter)
   uint64_t budget_released;  // serving: bytes ever released
   uint64_t stats[DS_N];
+  uint64_t stop;             // GaccO: set by a team whose wait exceeded its limit; every team then exits
 };
 
 // Kernel arguments for a transaction run.
@@ -103,6 +104,35 @@ struct RunArgs {
   uint32_t precheck;       // OCC load-only round before any lock: 0 never, 1 on retries, 2 always
   uint32_t pad4[2];
 };
+
+// Kernel arguments for a GaccO execution (gacco_exec.hip).
+struct GaccoArgs {
+  const DevOp *ops;
+  const DevTxn *txns;
+  uint64_t n_txns;
+  const uint32_t *rank;  // per row-group leader: its position in the sorted access table
+  int64_t *data;
+  uint64_t *words;       // per row: the position whose turn it is
+  DevOutcome *out;
+  int64_t *reads;
+  Ctl *ctl;
+  uint64_t wait_limit_ticks;  // a team waiting longer than this without progress stops the run
+  uint32_t poll_ticks;        // sleep per access queued ahead of the team on a row, wall-clock ticks
+  uint32_t ns_per_tick_q16;
+  uint32_t has_slot;
+  uint32_t pad;
+};
+
+// GaccO preprocessing (gacco.hip): clears ctl->stop, then builds the access
+// table, sorts it stably by row (radix sort) and writes the lock table (turn
+// counters in `words`, per-leader ranks).  `scratch` holds
+// gacco_scratch_words(n_ops) 32-bit words.
+uint64_t gacco_scratch_words(uint64_t n_ops);
+hipError_t gacco_prepare(hipStream_t s, const DevOp *ops, uint64_t n_ops, uint32_t sentinel, uint64_t *words,
+                         uint32_t *rank, uint32_t *scratch, Ctl *ctl);
+// GaccO execution; hipErrorInvalidValue for an unsupported (lanes, ops per txn).
+hipError_t launch_gacco(hipStream_t s, int lanes, int max_ops, int waves_per_wg, int grid, bool strict,
+                        const GaccoArgs &a, int n_cu, int *grid_used);
 
 // Host-side launchers (kernels.hip).
 hipError_t launch_init(hipStream_t s, uint64_t *words, uint64_t n_words, uint64_t *aux, uint64_t n_aux,

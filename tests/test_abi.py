@@ -111,6 +111,20 @@ def test_check_batch_structural_errors(b):
     assert b.cc_check_batch([(1 << 28, 1), (1, 1)], empty_t, empty_o, 0) == b.CC_E_RANGE
 
 
+def test_check_batch_gacco_needs_transactions_in_op_order(b):
+    # GaccO sorts each row's accesses into transaction order by a stable sort
+    # of the ops array, so transaction t's ops must come after t-1's
+    txns, ops = _batch(rows=[1, 2, 3, 4])
+    two = np.zeros(2, b.TXN_DTYPE)
+    two["first_op"] = [2, 0]
+    two["n_ops"] = [2, 2]
+    assert b.cc_check_batch(SHAPES, two, ops, b.CC_GACCO) == b.CC_E_INVAL
+    assert b.cc_check_batch(SHAPES, two, ops, b.CC_OCC) == 0
+    two["first_op"] = [0, 2]
+    assert b.cc_check_batch(SHAPES, two, ops, b.CC_GACCO) == 0
+    assert b.cc_check_batch(SHAPES, two, ops, 6) == b.CC_E_INVAL  # one past the last scheme
+
+
 def test_check_batch_accepts_generated_workloads(b):
     from paper_2406_10158_amd import workload as wl
     tabs, bt = wl.order_entry_workload(2, 200, seed=1)
@@ -119,6 +133,7 @@ def test_check_batch_accepts_generated_workloads(b):
     (tab,), kb = wl.kv_workload(n_rows=1000, n_fields=10, n_txns=500, ops=(2, 64), theta=0.99)
     txns, ops = b.pack_batch(kb)
     assert b.cc_check_batch([tab.shape], txns, ops, 4) == 0
+    assert b.cc_check_batch([tab.shape], txns, ops, b.CC_GACCO) == 0
 
 
 def test_init_without_a_gpu_fails_cleanly(b):
