@@ -264,6 +264,18 @@ def hottest_row_writes(batch: Batch, table_id: int = 0) -> tuple[int, int]:
     return int(rows[i]), int(counts[i])
 
 
+def hottest_row_accesses(batch: Batch, table_id: int = 0) -> tuple[int, int]:
+    """(row, number of transactions accessing it) of the most accessed row, reads included."""
+    m = batch.table == table_id
+    if not m.any():
+        return -1, 0
+    txn_of_op = np.repeat(np.arange(batch.n_txns, dtype=np.int64), batch.n_ops.astype(np.int64))
+    pairs = np.unique(batch.row[m].astype(np.int64) * batch.n_txns + txn_of_op[m])
+    rows, counts = np.unique(pairs // batch.n_txns, return_counts=True)
+    i = int(np.argmax(counts))
+    return int(rows[i]), int(counts[i])
+
+
 # ----------------------------------------------------------------------------
 # Order-entry (TPC-C-style NewOrder / Payment) workloads
 # ----------------------------------------------------------------------------

@@ -91,3 +91,15 @@ def test_hottest_row_chain_length_grows_with_theta():
         b = wl.kv_batch(100_000, 10, 20_000, ops=16, theta=th, seed=0)
         hs.append(wl.hottest_row_writes(b)[1])
     assert hs == sorted(hs) and hs[-1] > 20 * hs[0]
+
+
+def test_hottest_row_accesses_counts_transactions_not_ops():
+    # two transactions touch row 3 (one of them with two fields), one touches row 5
+    b = wl._pack([3, 2], np.array([3, 3, 7, 3, 5]), np.zeros(5, np.int64), np.array([0, 1, 0, 0, 0]),
+                 np.array([1, 0, 0, 0, 1]), np.zeros(5, np.int64), {})
+    assert wl.hottest_row_accesses(b) == (3, 2)
+    assert wl.hottest_row_writes(b) == (3, 1)  # one of its accesses writes
+    b2 = wl.kv_batch(100_000, 10, 20_000, ops=16, theta=0.9, seed=0)
+    row, n = wl.hottest_row_accesses(b2)
+    assert n >= wl.hottest_row_writes(b2)[1]
+    assert n == len(set(np.repeat(np.arange(b2.n_txns), 16)[b2.row == row].tolist()))
