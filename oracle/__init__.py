@@ -131,6 +131,36 @@ def id_order_expected(tables, batch):
     return serial_execute(tables, batch)
 
 
+def resolve_keys(index_keys, batch, op_keys):
+    """Rows that keyed operations name, through each table's index.
+
+    The paper's index is a sorted array of a table's keys kept with the row
+    ids and searched by binary search (Section 3.4, "Index"); the result of a
+    lookup is simply the row that holds the key.  ``index_keys[t]`` is None
+    for a table without an index, else an int64 array whose element i is row
+    i's key (all distinct).  For an operation on an indexed table
+    ``op_keys[op]`` is its key; other operations keep ``batch.row``.  Plain
+    dictionary lookups, no search.  Raises KeyError for a key no row holds.
+    """
+    rows = np.array(batch.row, dtype=np.int64, copy=True)
+    op_keys = np.asarray(op_keys, np.int64)
+    for t, keys in enumerate(index_keys):
+        if keys is None:
+            continue
+        where = {int(k): i for i, k in enumerate(np.asarray(keys, np.int64).tolist())}
+        for op in np.nonzero(np.asarray(batch.table) == t)[0].tolist():
+            rows[op] = where[int(op_keys[op])]
+    return rows
+
+
+def with_rows(batch, rows):
+    """A copy of ``batch`` whose operations name ``rows``."""
+    import copy
+    b = copy.copy(batch)
+    b.row = np.ascontiguousarray(rows, np.uint32)
+    return b
+
+
 def serial_order(status, serial_hi, serial_lo):
     """Committed transaction ids sorted by their (serial_hi, serial_lo) keys.
 

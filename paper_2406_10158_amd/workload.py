@@ -264,6 +264,29 @@ def hottest_row_writes(batch: Batch, table_id: int = 0) -> tuple[int, int]:
     return int(rows[i]), int(counts[i])
 
 
+def index_keys(n_rows: int, seed: int = 0) -> np.ndarray:
+    """Distinct random int64 keys, one per row (row i's key at index i), for a table with an index."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    keys = rng.integers(-(1 << 62), 1 << 62, size=n_rows, dtype=np.int64)
+    while True:
+        u, first = np.unique(keys, return_index=True)
+        if len(u) == n_rows:
+            return keys
+        dup = np.ones(n_rows, bool)
+        dup[first] = False
+        keys[dup] = rng.integers(-(1 << 62), 1 << 62, size=int(dup.sum()), dtype=np.int64)
+
+
+def keyed_ops(batch: Batch, keys_by_table) -> np.ndarray:
+    """Per-op lookup keys: the key of the op's row for tables with keys (keys_by_table[t]), else 0."""
+    out = np.zeros(batch.total_ops, np.int64)
+    for t, keys in enumerate(keys_by_table):
+        if keys is not None:
+            m = batch.table == t
+            out[m] = np.asarray(keys, np.int64)[batch.row[m].astype(np.int64)]
+    return out
+
+
 def hottest_row_accesses(batch: Batch, table_id: int = 0) -> tuple[int, int]:
     """(row, number of transactions accessing it) of the most accessed row, reads included."""
     m = batch.table == table_id

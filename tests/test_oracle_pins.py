@@ -302,3 +302,37 @@ def test_lock_table_model_with_descending_access_order_is_the_reverse_replay():
     assert np.array_equal(reads, rev_reads)
     assert all(np.array_equal(x, y) for x, y in zip(fin, rev_fin))
     assert not np.array_equal(reads, oracle.id_order_expected(tabs, b)[1])
+
+
+# ---------------------------------------------------------------------------
+# Index lookups (the sorted-array index): the dictionary resolution is pinned
+# against brute force and against a binary search of the sorted keys.
+# ---------------------------------------------------------------------------
+def test_resolve_keys_matches_brute_force_and_sorted_search():
+    rng = np.random.default_rng(21)
+    keys = wl.index_keys(3_000, seed=21)
+    assert len(np.unique(keys)) == len(keys)
+    b = wl.kv_batch(3_000, 2, 200, ops=5, theta=0.9, seed=22)
+    tabs = [wl.kv_table(3_000, 2)]
+    ok = wl.keyed_ops(b, [keys])
+    rows = oracle.resolve_keys([keys], b, ok)
+    assert np.array_equal(rows, b.row.astype(np.int64))
+    for op in rng.integers(0, b.total_ops, 50).tolist():
+        assert rows[op] == int(np.nonzero(keys == ok[op])[0][0])
+    order = np.argsort(keys, kind="stable")
+    pos = np.searchsorted(keys[order], ok)
+    assert np.array_equal(order[pos], rows)
+    # the resolved batch replays like the row-addressed one
+    f1, r1 = oracle.serial_execute(tabs, b)
+    f2, r2 = oracle.serial_execute(tabs, oracle.with_rows(b, rows))
+    assert np.array_equal(r1, r2) and np.array_equal(f1[0], f2[0])
+
+
+def test_resolve_keys_rejects_unknown_keys_and_leaves_unindexed_tables():
+    keys = np.array([7, -3, 11], np.int64)
+    b = wl._pack([2], np.array([0, 2]), np.array([0, 1]), np.zeros(2, np.int64), np.zeros(2, np.int64),
+                 np.zeros(2, np.int64), {})
+    rows = oracle.resolve_keys([keys, None], b, np.array([-3, 999], np.int64))
+    assert rows.tolist() == [1, 2]  # the second op's table has no index: its row stands
+    with pytest.raises(KeyError):
+        oracle.resolve_keys([keys, None], b, np.array([8, 0], np.int64))
