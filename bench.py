@@ -174,6 +174,32 @@ def suite_order_entry(args, binding, workload):
         eng.close()
 
 
+def suite_index(args, binding, workload):
+    """Key-value batches that name rows by key: no index, binary search, 16-way tree (OCC and GaccO)."""
+    keys = workload.index_keys(args.rows, seed=args.seed)
+    for theta in (0.0, 0.6, 0.9):
+        tables, batch = workload.kv_workload(n_rows=args.rows, n_fields=args.fields, n_txns=args.txns,
+                                             ops=args.ops, theta=theta, seed=args.seed)
+        op_keys = workload.keyed_ops(batch, [keys])
+        eng = binding.Engine(tables)
+        eng.create_index(0, keys)
+        for scheme in ("occ", "gacco"):
+            for method in ("none", "bsearch", "tree"):
+                bid = eng.submit(batch, scheme) if method == "none" else eng.submit_keyed(batch, op_keys, scheme)
+                flags = binding.CC_RUN_INDEX_TREE if method == "tree" else 0
+                rec = {"suite": "index", "theta": theta, "scheme": scheme, "lookup": method}
+                try:
+                    rec.update(_run_stats(eng, bid, batch.n_txns, flags=flags))
+                    st = binding.cc_stats(eng.ctx, bid)
+                    rec["index_ms"] = round(st["index_ns"] / 1e6, 3)
+                    rec["index_share"] = round(st["index_ns"] / max(st["run_ns"], 1), 3)
+                except binding.CCError as e:
+                    rec["error"] = str(e)
+                _emit(rec)
+                eng.release(bid)
+        eng.close()
+
+
 def suite_batching(args, binding, workload):
     """Uneven transactions (2-64 ops), Zipf 0.8: autotuned plain and epoch launches per batch size."""
     from paper_2406_10158_amd import autotune
@@ -253,7 +279,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probes", action="store_true", help="only run the memory micro-benchmarks")
-    ap.add_argument("--suite", choices=["schemes", "order_entry", "batching", "serving"],
+    ap.add_argument("--suite", choices=["schemes", "order_entry", "batching", "serving", "index"],
                     help="run a measurement suite instead of the headline step (JSON line per point)")
     ap.add_argument("--oe-txns", type=int, default=100_000)
     ap.add_argument("--serve-arrivals", type=int, default=100_000)
@@ -274,7 +300,7 @@ def main():
         binding.cc_destroy(ctx)
         return
     if args.suite:
-        {"schemes": suite_schemes, "order_entry": suite_order_entry, "batching": suite_batching,
+        {"schemes": suite_schemes, "order_entry": suite_order_entry, "batching": suite_batching, "index": suite_index,
          "serving": suite_serving}[args.suite](args, binding, workload)
         return
 

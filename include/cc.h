@@ -176,6 +176,9 @@ enum cc_mode { CC_MODE_PLAIN = 0, CC_MODE_EPOCH = 1, CC_MODE_SERVE = 2 };
                                      runs from a transaction's third attempt on (repeated failures are
                                      the sign of contention) */
 #define CC_RUN_NO_PRECHECK 0x10u  /* OCC: never run the pre-check round */
+#define CC_RUN_INDEX_TREE 0x20u   /* keyed batches: look keys up by descending the index's 16-way tree
+                                     (one 128-byte node per level) instead of by binary search of the
+                                     sorted keys */
 #define CC_RUN_EAGER_INSTALL 0x2u /* OCC: store new values in the validation round (undo on abort) instead
                                      of after validation succeeds; measured ~3% slower on the key-value
                                      workload, kept for comparison */
@@ -225,6 +228,7 @@ enum cc_stat {
   CC_STAT_OCC_R4_NS = 22,
   CC_STAT_PREP_NS = 23,    /* GaccO: preprocessing (access table, radix sort, lock table), HIP events;
                               part of CC_STAT_RUN_NS */
+  CC_STAT_INDEX_NS = 24,   /* keyed batches: the index lookups, HIP events; part of CC_STAT_RUN_NS */
   CC_N_STATS = 32
 };
 
@@ -273,6 +277,40 @@ cc_status cc_read_table(cc_ctx *ctx, uint32_t table_id, int64_t *out, int out_on
  */
 cc_status cc_submit_batch(cc_ctx *ctx, const cc_txn *txns, uint64_t n_txns, const cc_op *ops, uint64_t n_ops,
                           int scheme, int on_device, uint64_t *batch_id);
+
+/*
+ * Give a table a sorted-array index (paper Section 3.4 "Index": the indexed
+ * column is sorted and copied to device memory with the row ids; a lookup is
+ * a search of the sorted array).  keys[i] (host array, n == the table's row
+ * count) is row i's key; keys must be distinct and below INT64_MAX (the
+ * padding value).  The engine sorts the (key, row) pairs on the host, copies
+ * them to the device and builds a static 16-way search tree over them (each
+ * level holds the largest key of every 16-key node below it; used with
+ * CC_RUN_INDEX_TREE).  Load-time work, not part of any run.  Errors:
+ * CC_E_INVAL (duplicate or reserved key, wrong n), CC_E_RANGE, CC_E_STATE
+ * (a keyed batch is still submitted: release it first).
+ */
+cc_status cc_create_index(cc_ctx *ctx, uint32_t table_id, const int64_t *keys, uint64_t n);
+
+/*
+ * cc_submit_batch for batches that name rows by key: for an op on a table
+ * with an index, op_keys[i] is its key and ops[i].row must be 0; ops on other
+ * tables use ops[i].row as usual (their op_keys entry is ignored).  Row-group
+ * and duplicate checks compare keys.  Each cc_run first looks every key up on
+ * the device (after CC initialisation, inside the measured window:
+ * CC_STAT_INDEX_NS) and returns CC_E_RANGE, with nothing executed, if a key
+ * names no row.  op_keys is a host array of n_ops entries, copied.
+ */
+cc_status cc_submit_batch_keyed(cc_ctx *ctx, const cc_txn *txns, uint64_t n_txns, const cc_op *ops, uint64_t n_ops,
+                                const int64_t *op_keys, int scheme, int on_device, uint64_t *batch_id);
+
+/*
+ * For a keyed batch after a run: rows[i] (host array, n_ops entries) is the
+ * row within its table that op i accessed -- the lookup's result for keyed
+ * ops, ops[i].row for the others.  CC_E_STATE for a batch without keyed ops
+ * or not yet run.
+ */
+cc_status cc_fetch_rows(cc_ctx *ctx, uint64_t batch_id, uint32_t *rows);
 
 /*
  * Host-only validation of a batch against table shapes (n_tables tables of

@@ -36,10 +36,11 @@ CC_RUN_EAGER_INSTALL = 0x2
 CC_RUN_WAIT_UNLOCK = 0x4
 CC_RUN_PRECHECK = 0x8
 CC_RUN_NO_PRECHECK = 0x10
+CC_RUN_INDEX_TREE = 0x20
 STAT_NAMES = ["committed", "attempts", "abort_lock", "abort_valid", "kernel_ns", "run_ns", "tickets",
               "max_attempts", "lat_p50_ns", "lat_p99_ns", "epochs", "passes", "deferred", "grid",
               "t_useful_ns", "t_abort_ns", "t_wait_ns", "gave_up", "admit_waits",
-              "occ_r1_ns", "occ_r2_ns", "occ_r3_ns", "occ_r4_ns", "prep_ns"]
+              "occ_r1_ns", "occ_r2_ns", "occ_r3_ns", "occ_r4_ns", "prep_ns", "index_ns"]
 CC_N_STATS = 32
 
 OP_DTYPE = np.dtype([("row", "<u4"), ("table", "<u2"), ("field", "u1"), ("kind", "u1"), ("arg", "<i8")])
@@ -74,6 +75,10 @@ _SIGS = {
     "cc_check_batch": (_S, [ctypes.c_uint32, _P, _P, _P, ctypes.c_uint64, _P, ctypes.c_uint64, ctypes.c_int]),
     "cc_submit_batch": (_S, [_P, _P, ctypes.c_uint64, _P, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
                              ctypes.POINTER(ctypes.c_uint64)]),
+    "cc_submit_batch_keyed": (_S, [_P, _P, ctypes.c_uint64, _P, ctypes.c_uint64, _P, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_uint64)]),
+    "cc_create_index": (_S, [_P, ctypes.c_uint32, _P, ctypes.c_uint64]),
+    "cc_fetch_rows": (_S, [_P, ctypes.c_uint64, _P]),
     "cc_run": (_S, [_P, ctypes.c_uint64, ctypes.POINTER(cc_run_params)]),
     "cc_fetch_outcomes": (_S, [_P, ctypes.c_uint64, _P, _P, ctypes.c_int]),
     "cc_stats": (_S, [_P, ctypes.c_uint64, _P, ctypes.c_uint32]),
@@ -196,6 +201,28 @@ def cc_submit_batch(ctx, txns: np.ndarray, ops: np.ndarray, scheme: int) -> int:
     return int(bid.value)
 
 
+def cc_submit_batch_keyed(ctx, txns: np.ndarray, ops: np.ndarray, op_keys: np.ndarray, scheme: int) -> int:
+    txns = _host(txns, TXN_DTYPE)
+    ops = _host(ops, OP_DTYPE)
+    keys = _host(op_keys, np.int64)
+    assert len(keys) == len(ops)
+    bid = ctypes.c_uint64()
+    _check(lib.cc_submit_batch_keyed(ctx, _ptr(txns), len(txns), _ptr(ops), len(ops), _ptr(keys), scheme, 0,
+                                     ctypes.byref(bid)), ctx)
+    return int(bid.value)
+
+
+def cc_create_index(ctx, table_id: int, keys: np.ndarray) -> None:
+    keys = _host(keys, np.int64)
+    _check(lib.cc_create_index(ctx, table_id, _ptr(keys), len(keys)), ctx)
+
+
+def cc_fetch_rows(ctx, batch_id: int, n_ops: int) -> np.ndarray:
+    rows = np.zeros(max(n_ops, 1), np.uint32)
+    _check(lib.cc_fetch_rows(ctx, batch_id, _ptr(rows)), ctx)
+    return rows[:n_ops]
+
+
 def run_params(lanes_per_txn=0, waves_per_wg=0, grid=0, mode=CC_MODE_PLAIN, max_attempts=0, max_epochs=0,
                flags=0, backoff_ns=0, defer_after=0, ts_start=0, hbm_cap_bytes=0) -> cc_run_params:
     return cc_run_params(lanes_per_txn, waves_per_wg, grid, mode, max_attempts, max_epochs, flags, backoff_ns,
@@ -251,6 +278,7 @@ class Engine:
 
     def __init__(self, tables, device: int = 0, stream=None):
         self.ctx = cc_init(device, stream)
+        self.indexed = set()
         self.shapes = [tuple(t.shape) for t in tables]
         self.ids = [cc_create_table(self.ctx, int(s[0]), int(s[1])) for s in self.shapes]
         for i, t in zip(self.ids, tables):
@@ -273,6 +301,21 @@ class Engine:
             scheme = SCHEMES[scheme]
         txns, ops = pack_batch(batch)
         return cc_submit_batch(self.ctx, txns, ops, scheme)
+
+    def create_index(self, table_id, keys):
+        cc_create_index(self.ctx, self.ids[table_id], keys)
+        self.indexed.add(int(table_id))
+
+    def submit_keyed(self, batch, op_keys, scheme) -> int:
+        """Submit with rows named by key on tables that have an index (their ops' row fields are sent as 0)."""
+        if isinstance(scheme, str):
+            scheme = SCHEMES[scheme]
+        txns, ops = pack_batch(batch)
+        ops["row"][np.isin(ops["table"], sorted(self.indexed))] = 0
+        return cc_submit_batch_keyed(self.ctx, txns, ops, op_keys, scheme)
+
+    def rows(self, batch_id, n_ops):
+        return cc_fetch_rows(self.ctx, batch_id, n_ops)
 
     def run(self, batch_id, **kw):
         cc_run(self.ctx, batch_id, run_params(**kw))

@@ -33,6 +33,10 @@ struct Batch {
   int64_t *d_reads = nullptr;
   uint32_t *d_list = nullptr;  // pending transactions between passes
   uint64_t *d_nodes = nullptr; // MVCC history nodes (3 words per op)
+  bool keyed = false;            // some ops name their row by key (cc_submit_batch_keyed)
+  int64_t *d_opkeys = nullptr;   // keyed batches: per-op key
+  uint32_t *d_meta = nullptr;    // keyed batches: per-op keyed flag, table, field
+  uint32_t *d_rows = nullptr;    // keyed batches: per-op row found by the last run's lookups
   uint32_t *d_rank = nullptr;    // GaccO: per row-group leader, its position in the sorted access table
   uint32_t *d_gscratch = nullptr;// GaccO: access-table and sort buffers
   int64_t *d_arrival = nullptr;           // serving: arrival ticks per transaction
@@ -45,6 +49,13 @@ struct Batch {
 };
 
 }  // namespace
+
+struct DevIndex {
+  int64_t *keys = nullptr;
+  uint32_t *rows = nullptr;
+  int64_t *tree = nullptr;
+  IndexDesc desc{};
+};
 
 struct cc_ctx {
   int device = 0;
@@ -59,9 +70,11 @@ struct cc_ctx {
   uint64_t *d_words = nullptr;
   uint64_t *d_aux = nullptr;
   Ctl *d_ctl = nullptr;
+  std::vector<DevIndex> indexes;      // per table (empty entries: no index)
+  IndexDesc *d_idx = nullptr;         // device copy of every table's IndexDesc
   std::map<uint64_t, Batch> batches;
   uint64_t next_batch = 1;
-  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   std::string err;
 };
 
@@ -116,6 +129,21 @@ cc_status launch_error(cc_ctx *c, hipError_t e) {
   return hip_fail(c, e, "transaction kernel launch");
 }
 
+// Resolve a keyed batch's keys on the device, after CC initialisation and
+// inside the run's window; *ms receives the lookup kernel's time.
+cc_status resolve_keys(cc_ctx *c, Batch &b, const cc_run_params &p, float *ms) {
+  HIP_OR(c, hipEventRecord(c->ev[6], c->stream));
+  HIP_OR(c, launch_index_lookup(c->stream, (p.flags & CC_RUN_INDEX_TREE) != 0, b.d_opkeys, b.d_meta, b.d_ops,
+                                b.d_rows, b.n_ops, c->d_idx, c->d_ctl));
+  HIP_OR(c, hipEventRecord(c->ev[7], c->stream));
+  uint64_t miss = 0;
+  HIP_OR(c, hipMemcpyAsync(&miss, &c->d_ctl->stats[DS_INDEX_MISS], sizeof miss, hipMemcpyDeviceToHost, c->stream));
+  HIP_OR(c, hipStreamSynchronize(c->stream));
+  HIP_OR(c, hipEventElapsedTime(ms, c->ev[6], c->ev[7]));
+  if (miss) return fail(c, CC_E_RANGE, std::to_string(miss) + " keys name no row of their table's index");
+  return CC_OK;
+}
+
 void free_batch(Batch &b) {
   if (b.d_ops) (void)hipFree(b.d_ops);
   if (b.d_txns) (void)hipFree(b.d_txns);
@@ -123,6 +151,12 @@ void free_batch(Batch &b) {
   if (b.d_reads) (void)hipFree(b.d_reads);
   if (b.d_list) (void)hipFree(b.d_list);
   if (b.d_nodes) (void)hipFree(b.d_nodes);
+  if (b.d_opkeys) (void)hipFree(b.d_opkeys);
+  if (b.d_meta) (void)hipFree(b.d_meta);
+  if (b.d_rows) (void)hipFree(b.d_rows);
+  b.d_opkeys = nullptr;
+  b.d_meta = nullptr;
+  b.d_rows = nullptr;
   if (b.d_rank) (void)hipFree(b.d_rank);
   if (b.d_gscratch) (void)hipFree(b.d_gscratch);
   b.d_rank = nullptr;
@@ -253,6 +287,12 @@ cc_status cc_destroy(cc_ctx *c) {
   activate(c);
   (void)hipStreamSynchronize(c->stream);
   for (auto &kv : c->batches) free_batch(kv.second);
+  for (auto &ix : c->indexes) {
+    if (ix.keys) (void)hipFree(ix.keys);
+    if (ix.rows) (void)hipFree(ix.rows);
+    if (ix.tree) (void)hipFree(ix.tree);
+  }
+  if (c->d_idx) (void)hipFree(c->d_idx);
   if (c->d_data) (void)hipFree(c->d_data);
   if (c->d_words) (void)hipFree(c->d_words);
   if (c->d_aux) (void)hipFree(c->d_aux);
@@ -329,7 +369,8 @@ namespace {
 cc_status validate_and_pack(cc_ctx *c, const std::vector<Table> &tables, const cc_txn *txns, uint64_t n_txns,
                             const cc_op *ops, uint64_t n_ops, std::vector<DevOp> *dops_out,
                             std::vector<DevTxn> *dtx_out, uint32_t *max_ops_out, bool *has_slot_out,
-                            bool *txn_ordered_out) {
+                            bool *txn_ordered_out, const int64_t *op_keys = nullptr,
+                            const std::vector<bool> *indexed = nullptr) {
   if ((n_txns && !txns) || (n_ops && !ops)) return fail(c, CC_E_INVAL, "null array");
   if (n_txns > 0xFFFFFFFFull || n_ops > 0xFFFFFFFFull) return fail(c, CC_E_RANGE, "batch too large");
   std::vector<DevOp> dummy_ops;
@@ -342,7 +383,7 @@ cc_status validate_and_pack(cc_ctx *c, const std::vector<Table> &tables, const c
   bool txn_ordered = true;  // every transaction's ops come after the previous one's
   dtx.assign(n_txns, DevTxn{0, 0});
   std::vector<uint8_t> used(n_ops, 0);  // every op belongs to at most one transaction
-  std::vector<uint64_t> keys;           // (table,row) of row leaders, for the duplicate check
+  std::vector<std::pair<uint32_t, int64_t>> keys;  // (table, row or key) of row leaders, for the duplicate check
   uint32_t max_ops = 0;
   bool has_slot = false;
   for (uint64_t t = 0; t < n_txns; ++t) {
@@ -359,32 +400,41 @@ cc_status validate_and_pack(cc_ctx *c, const std::vector<Table> &tables, const c
     keys.clear();
     uint32_t group_start = 0;
     bool group_written = false;
+    // an op's row identity: its key on a table with an index (keyed batch), else its row
+    auto keyed = [&](const cc_op &o) { return op_keys && indexed && o.table < indexed->size() && (*indexed)[o.table]; };
+    auto ident = [&](uint32_t k) -> int64_t {
+      const cc_op &o = ops[x.first_op + k];
+      return keyed(o) ? op_keys[x.first_op + k] : (int64_t)o.row;
+    };
     for (uint32_t i = 0; i < x.n_ops; ++i) {
       const cc_op &o = ops[x.first_op + i];
       if (o.table >= tables.size()) return fail(c, CC_E_RANGE, "op table out of range");
       const Table &tb = tables[o.table];
-      if (o.row >= tb.n_rows || o.field >= tb.n_fields) return fail(c, CC_E_RANGE, "op row/field out of range");
+      const bool kd = keyed(o);
+      if (kd && o.row != 0) return fail(c, CC_E_INVAL, "an op on an indexed table names its row by key; row must be 0");
+      if ((!kd && o.row >= tb.n_rows) || o.field >= tb.n_fields) return fail(c, CC_E_RANGE, "op row/field out of range");
       if (o.kind > CC_WRITE_SLOT) return fail(c, CC_E_INVAL, "unknown op kind");
       if (o.kind == CC_WRITE_SLOT) {
         has_slot = true;
         if ((uint32_t)(o.arg & 0xFF) >= i) return fail(c, CC_E_INVAL, "WRITE_SLOT source is not an earlier op");
       }
-      const bool follower = i > 0 && ops[x.first_op + i - 1].table == o.table && ops[x.first_op + i - 1].row == o.row;
+      const bool follower = i > 0 && ops[x.first_op + i - 1].table == o.table && ident(i - 1) == ident(i);
       if (!follower) {
         for (uint32_t j = group_start; j < i; ++j)
           if (group_written) dops[x.first_op + j].rowk |= WRITTEN_BIT;
         group_start = i;
         group_written = false;
-        keys.push_back(((uint64_t)o.table << 32) | o.row);
+        keys.emplace_back((uint32_t)o.table, ident(i));
       } else {
         for (uint32_t j = group_start; j < i; ++j)
           if (ops[x.first_op + j].field == o.field) return fail(c, CC_E_DUPROW, "field repeated within a txn");
       }
       group_written |= o.kind != CC_READ;
-      const uint64_t grow = tb.row_base + o.row;
+      // keyed ops get their row and cell from the lookup at the start of each run
+      const uint64_t grow = kd ? 0 : tb.row_base + o.row;
       DevOp d;
       d.rowk = (uint32_t)grow | ((uint32_t)o.kind << KIND_SHIFT) | (follower ? FOLLOWER_BIT : 0u);
-      d.elem = (uint32_t)(tb.elem_base + (uint64_t)o.row * tb.n_fields + o.field);
+      d.elem = kd ? 0u : (uint32_t)(tb.elem_base + (uint64_t)o.row * tb.n_fields + o.field);
       d.arg = o.arg;
       dops[x.first_op + i] = d;
     }
@@ -422,7 +472,8 @@ cc_status run_gacco(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes,
     return fail(c, CC_E_INVAL,
                 "CC_GACCO runs in CC_MODE_PLAIN only: it never aborts, so epochs have nothing to retry, and it "
                 "orders the whole batch before running it");
-  if (p.flags & ~CC_RUN_STRICT_FENCES) return fail(c, CC_E_INVAL, "CC_GACCO accepts only CC_RUN_STRICT_FENCES");
+  if (p.flags & ~(CC_RUN_STRICT_FENCES | CC_RUN_INDEX_TREE))
+    return fail(c, CC_E_INVAL, "CC_GACCO accepts only CC_RUN_STRICT_FENCES and CC_RUN_INDEX_TREE");
   GaccoArgs a{};
   a.ops = b.d_ops;
   a.txns = b.d_txns;
@@ -443,6 +494,11 @@ cc_status run_gacco(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes,
   HIP_OR(c, hipEventRecord(c->ev[0], c->stream));
   // the lock table sets the word of every accessed row, so words need no clearing
   HIP_OR(c, launch_init(c->stream, c->d_words, 0, nullptr, 0, b.d_out, b.n_txns, c->d_ctl, p.ts_start));
+  float ms_index = 0;
+  if (b.keyed) {
+    cc_status st = resolve_keys(c, b, p, &ms_index);
+    if (st) return st;
+  }
   HIP_OR(c, hipEventRecord(c->ev[4], c->stream));
   HIP_OR(c, gacco_prepare(c->stream, b.d_ops, b.n_ops, (uint32_t)c->total_rows, c->d_words, b.d_rank, b.d_gscratch,
                           c->d_ctl));
@@ -469,6 +525,7 @@ cc_status run_gacco(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes,
   b.stats[CC_STAT_KERNEL_NS] = (uint64_t)((double)ms_kernel * 1e6);
   b.stats[CC_STAT_RUN_NS] = (uint64_t)((double)ms_run * 1e6);
   b.stats[CC_STAT_PREP_NS] = (uint64_t)((double)ms_prep * 1e6);
+  b.stats[CC_STAT_INDEX_NS] = (uint64_t)((double)ms_index * 1e6);
   b.stats[CC_STAT_MAX_ATTEMPTS] = h.stats[DS_MAX_ATTEMPTS];
   b.stats[CC_STAT_PASSES] = b.n_txns ? 1 : 0;
   b.stats[CC_STAT_GRID] = (uint64_t)grid_used;
@@ -508,22 +565,42 @@ cc_status cc_check_batch(uint32_t n_tables, const uint64_t *n_rows, const uint32
   return st;
 }
 
-cc_status cc_submit_batch(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, const cc_op *ops, uint64_t n_ops,
-                          int scheme, int on_device, uint64_t *batch_id) {
+static cc_status submit_impl(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, const cc_op *ops, uint64_t n_ops,
+                             const int64_t *op_keys, int scheme, int on_device, uint64_t *batch_id) {
   if (!c || !batch_id) return CC_E_INVAL;
   *batch_id = 0;
   if (scheme < 0 || scheme >= CC_N_SCHEMES) return fail(c, CC_E_INVAL, "unknown scheme");
   if (on_device) return fail(c, CC_E_INVAL, "device-resident batch submission is not supported; pass host arrays");
   if (!c->frozen) return fail(c, CC_E_STATE, "load the tables before submitting a batch");
   if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
+  std::vector<bool> indexed(c->tables.size(), false);
+  for (size_t t = 0; t < c->indexes.size() && t < indexed.size(); ++t) indexed[t] = c->indexes[t].keys != nullptr;
   std::vector<DevOp> dops;
   std::vector<DevTxn> dtx;
   uint32_t max_ops = 0;
   bool has_slot = false, ordered = true;
-  cc_status st = validate_and_pack(c, c->tables, txns, n_txns, ops, n_ops, &dops, &dtx, &max_ops, &has_slot, &ordered);
+  cc_status st = validate_and_pack(c, c->tables, txns, n_txns, ops, n_ops, &dops, &dtx, &max_ops, &has_slot, &ordered,
+                                   op_keys, op_keys ? &indexed : nullptr);
   if (st) return st;
   if (scheme == CC_GACCO && !ordered)
     return fail(c, CC_E_INVAL, "CC_GACCO needs each transaction's ops after the previous transaction's (first_op nondecreasing)");
+  // keyed ops of the transactions (ops no transaction refers to are never looked up)
+  std::vector<uint32_t> meta;
+  std::vector<uint32_t> rows0;
+  bool keyed = false;
+  if (op_keys) {
+    meta.assign(n_ops, 0u);
+    rows0.assign(n_ops, 0u);
+    for (uint64_t i = 0; i < n_ops; ++i) rows0[i] = ops[i].row;
+    for (uint64_t t = 0; t < n_txns; ++t)
+      for (uint32_t i = 0; i < txns[t].n_ops; ++i) {
+        const uint64_t k = txns[t].first_op + i;
+        if (indexed[ops[k].table]) {
+          meta[k] = META_KEYED | ((uint32_t)ops[k].table << 16) | ops[k].field;
+          keyed = true;
+        }
+      }
+  }
 
   Batch b;
   b.scheme = scheme;
@@ -531,6 +608,7 @@ cc_status cc_submit_batch(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, const 
   b.n_ops = n_ops;
   b.max_ops = max_ops;
   b.has_slot = has_slot;
+  b.keyed = keyed;
   auto alloc = [&](void **p, size_t bytes) -> hipError_t { return hipMalloc(p, bytes ? bytes : 16); };
   hipError_t e;
   if ((e = alloc((void **)&b.d_ops, n_ops * sizeof(DevOp))) != hipSuccess ||
@@ -541,18 +619,131 @@ cc_status cc_submit_batch(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, const 
       (scheme == CC_MVCC && (e = alloc((void **)&b.d_nodes, n_ops * 3 * sizeof(uint64_t))) != hipSuccess) ||
       (scheme == CC_GACCO && (e = alloc((void **)&b.d_rank, n_ops * sizeof(uint32_t))) != hipSuccess) ||
       (scheme == CC_GACCO &&
-       (e = alloc((void **)&b.d_gscratch, gacco_scratch_words(n_ops) * sizeof(uint32_t))) != hipSuccess)) {
+       (e = alloc((void **)&b.d_gscratch, gacco_scratch_words(n_ops) * sizeof(uint32_t))) != hipSuccess) ||
+      (keyed && (e = alloc((void **)&b.d_opkeys, n_ops * sizeof(int64_t))) != hipSuccess) ||
+      (keyed && (e = alloc((void **)&b.d_meta, n_ops * sizeof(uint32_t))) != hipSuccess) ||
+      (keyed && (e = alloc((void **)&b.d_rows, n_ops * sizeof(uint32_t))) != hipSuccess)) {
     free_batch(b);
     return hip_fail(c, e, "batch allocation");
   }
-  if (n_ops) HIP_OR(c, hipMemcpyAsync(b.d_ops, dops.data(), n_ops * sizeof(DevOp), hipMemcpyHostToDevice, c->stream));
-  if (n_txns)
-    HIP_OR(c, hipMemcpyAsync(b.d_txns, dtx.data(), n_txns * sizeof(DevTxn), hipMemcpyHostToDevice, c->stream));
-  if (n_ops) HIP_OR(c, hipMemsetAsync(b.d_reads, 0, n_ops * sizeof(int64_t), c->stream));
-  HIP_OR(c, hipStreamSynchronize(c->stream));
+  auto copy_in = [&]() -> hipError_t {
+    hipError_t r = hipSuccess;
+    if (n_ops) r = hipMemcpyAsync(b.d_ops, dops.data(), n_ops * sizeof(DevOp), hipMemcpyHostToDevice, c->stream);
+    if (r == hipSuccess && n_txns)
+      r = hipMemcpyAsync(b.d_txns, dtx.data(), n_txns * sizeof(DevTxn), hipMemcpyHostToDevice, c->stream);
+    if (r == hipSuccess && n_ops) r = hipMemsetAsync(b.d_reads, 0, n_ops * sizeof(int64_t), c->stream);
+    if (r == hipSuccess && keyed)
+      r = hipMemcpyAsync(b.d_opkeys, op_keys, n_ops * sizeof(int64_t), hipMemcpyHostToDevice, c->stream);
+    if (r == hipSuccess && keyed)
+      r = hipMemcpyAsync(b.d_meta, meta.data(), n_ops * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream);
+    if (r == hipSuccess && keyed)
+      r = hipMemcpyAsync(b.d_rows, rows0.data(), n_ops * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream);
+    if (r == hipSuccess) r = hipStreamSynchronize(c->stream);
+    return r;
+  };
+  if ((e = copy_in()) != hipSuccess) {
+    free_batch(b);
+    return hip_fail(c, e, "batch upload");
+  }
   const uint64_t id = c->next_batch++;
   c->batches[id] = b;
   *batch_id = id;
+  return CC_OK;
+}
+
+cc_status cc_submit_batch(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, const cc_op *ops, uint64_t n_ops,
+                          int scheme, int on_device, uint64_t *batch_id) {
+  return submit_impl(c, txns, n_txns, ops, n_ops, nullptr, scheme, on_device, batch_id);
+}
+
+cc_status cc_submit_batch_keyed(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, const cc_op *ops, uint64_t n_ops,
+                                const int64_t *op_keys, int scheme, int on_device, uint64_t *batch_id) {
+  if (!op_keys && n_ops) return fail(c, CC_E_INVAL, "op_keys is NULL");
+  return submit_impl(c, txns, n_txns, ops, n_ops, op_keys, scheme, on_device, batch_id);
+}
+
+cc_status cc_create_index(cc_ctx *c, uint32_t tid, const int64_t *keys, uint64_t n) {
+  if (!c || (!keys && n)) return CC_E_INVAL;
+  if (tid >= c->tables.size()) return fail(c, CC_E_RANGE, "unknown table");
+  if (n != c->tables[tid].n_rows) return fail(c, CC_E_INVAL, "one key per row of the table");
+  if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
+  cc_status st = freeze(c);
+  if (st) return st;
+  for (auto &kv : c->batches)
+    if (kv.second.keyed) return fail(c, CC_E_STATE, "release the keyed batches before changing an index");
+  // sort (key, row) on the host: index construction is load-time work
+  std::vector<std::pair<int64_t, uint32_t>> kr(n);
+  for (uint64_t i = 0; i < n; ++i) {
+    if (keys[i] == INT64_MAX) return fail(c, CC_E_INVAL, "INT64_MAX is reserved (index padding)");
+    kr[i] = {keys[i], (uint32_t)i};
+  }
+  std::sort(kr.begin(), kr.end());
+  for (uint64_t i = 1; i < n; ++i)
+    if (kr[i].first == kr[i - 1].first) return fail(c, CC_E_INVAL, "index keys must be distinct");
+  auto pad16 = [](uint64_t m) { return (m + 15) / 16 * 16; };
+  std::vector<int64_t> level0(pad16(std::max<uint64_t>(n, 1)), INT64_MAX);
+  std::vector<uint32_t> rows(std::max<uint64_t>(n, 1), 0u);
+  for (uint64_t i = 0; i < n; ++i) {
+    level0[i] = kr[i].first;
+    rows[i] = kr[i].second;
+  }
+  // upper levels: the largest key of each 16-key node of the level below
+  std::vector<int64_t> tree;
+  IndexDesc d{};
+  d.n = n;
+  std::vector<int64_t> cur = level0;
+  uint64_t real = n;  // entries of `cur` that are keys (the rest is padding)
+  uint32_t levels = 0;
+  while (cur.size() > 16) {
+    if (levels >= INDEX_MAX_LEVELS) return fail(c, CC_E_RANGE, "index too large");
+    const uint64_t nodes = (real + 15) / 16;
+    std::vector<int64_t> up(pad16(nodes), INT64_MAX);
+    for (uint64_t j = 0; j < nodes; ++j) up[j] = cur[std::min(j * 16 + 15, real - 1)];
+    real = nodes;
+    ++levels;
+    d.level_off[levels] = tree.size();
+    tree.insert(tree.end(), up.begin(), up.end());
+    cur.swap(up);
+  }
+  d.levels = levels;
+  const Table &t = c->tables[tid];
+  d.row_base = t.row_base;
+  d.elem_base = t.elem_base;
+  d.n_fields = t.n_fields;
+  if (c->indexes.size() < c->tables.size()) c->indexes.resize(c->tables.size());
+  DevIndex &ix = c->indexes[tid];
+  if (ix.keys) (void)hipFree(ix.keys);
+  if (ix.rows) (void)hipFree(ix.rows);
+  if (ix.tree) (void)hipFree(ix.tree);
+  ix = DevIndex{};
+  HIP_OR(c, hipMalloc(&ix.keys, level0.size() * sizeof(int64_t)));
+  HIP_OR(c, hipMalloc(&ix.rows, rows.size() * sizeof(uint32_t)));
+  HIP_OR(c, hipMalloc(&ix.tree, std::max<size_t>(tree.size(), 1) * sizeof(int64_t)));
+  HIP_OR(c, hipMemcpyAsync(ix.keys, level0.data(), level0.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  HIP_OR(c, hipMemcpyAsync(ix.rows, rows.data(), rows.size() * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
+  if (!tree.empty())
+    HIP_OR(c, hipMemcpyAsync(ix.tree, tree.data(), tree.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  d.keys = ix.keys;
+  d.rows = ix.rows;
+  d.tree = ix.tree;
+  ix.desc = d;
+  if (!c->d_idx) HIP_OR(c, hipMalloc(&c->d_idx, CC_MAX_TABLES * sizeof(IndexDesc)));
+  std::vector<IndexDesc> all(CC_MAX_TABLES, IndexDesc{});
+  for (size_t i = 0; i < c->indexes.size(); ++i) all[i] = c->indexes[i].desc;
+  HIP_OR(c, hipMemcpyAsync(c->d_idx, all.data(), all.size() * sizeof(IndexDesc), hipMemcpyHostToDevice, c->stream));
+  HIP_OR(c, hipStreamSynchronize(c->stream));
+  return CC_OK;
+}
+
+cc_status cc_fetch_rows(cc_ctx *c, uint64_t batch_id, uint32_t *rows) {
+  if (!c || !rows) return CC_E_INVAL;
+  auto it = c->batches.find(batch_id);
+  if (it == c->batches.end()) return fail(c, CC_E_NOBATCH, "unknown batch");
+  Batch &b = it->second;
+  if (!b.keyed) return fail(c, CC_E_STATE, "the batch has no keyed operations");
+  if (!b.ran) return fail(c, CC_E_STATE, "batch has not been run");
+  if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
+  if (b.n_ops) HIP_OR(c, hipMemcpy(rows, b.d_rows, b.n_ops * sizeof(uint32_t), hipMemcpyDeviceToHost));
   return CC_OK;
 }
 
@@ -575,8 +766,8 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   if (lanes != 1 && lanes != 4 && lanes != 16 && lanes != 64) return fail(c, CC_E_INVAL, "lanes_per_txn must be 1, 4, 16 or 64");
   const uint32_t wpw = p.waves_per_wg ? p.waves_per_wg : 1;
   if (wpw < 1 || wpw > 16) return fail(c, CC_E_INVAL, "waves_per_wg must be 1..16");
-  if (p.flags &
-      ~(CC_RUN_STRICT_FENCES | CC_RUN_EAGER_INSTALL | CC_RUN_WAIT_UNLOCK | CC_RUN_PRECHECK | CC_RUN_NO_PRECHECK))
+  if (p.flags & ~(CC_RUN_STRICT_FENCES | CC_RUN_EAGER_INSTALL | CC_RUN_WAIT_UNLOCK | CC_RUN_PRECHECK |
+                  CC_RUN_NO_PRECHECK | CC_RUN_INDEX_TREE))
     return fail(c, CC_E_INVAL, "unknown run flag");
   if (p.flags & CC_RUN_WAIT_UNLOCK)
     // Switched off: two teams of one wavefront that block each other both see
@@ -623,6 +814,11 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   HIP_OR(c, hipEventRecord(c->ev[0], c->stream));
   HIP_OR(c, launch_init(c->stream, c->d_words, c->total_rows, c->d_aux, b.scheme == CC_MVCC ? c->total_rows : 0,
                         b.d_out, b.n_txns, c->d_ctl, p.ts_start));
+  float ms_index = 0;
+  if (b.keyed) {
+    cc_status st = resolve_keys(c, b, p, &ms_index);
+    if (st) return st;
+  }
   Ctl h{};
   double kernel_ms = 0;
   uint32_t passes = 0, epochs = 0;
@@ -775,6 +971,7 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   b.stats[CC_STAT_ADMIT_WAITS] = h.stats[DS_ADMIT_WAITS];
   for (int i = 0; i < 4; ++i)
     b.stats[CC_STAT_OCC_R1_NS + i] = (uint64_t)((double)h.stats[DS_R1 + i] * ns_per_tick);
+  b.stats[CC_STAT_INDEX_NS] = (uint64_t)((double)ms_index * 1e6);
   b.ran = true;
   if (b.n_txns) {
     std::vector<cc_outcome> o(b.n_txns);

@@ -61,6 +61,7 @@ enum DevStat {
   DS_R2 = 13,           //   validate+install / release)
   DS_R3 = 14,
   DS_R4 = 15,
+  DS_INDEX_MISS = 16,   // keyed operations whose key no row holds
   DS_N = 24
 };
 
@@ -104,6 +105,34 @@ struct RunArgs {
   uint32_t precheck;       // OCC load-only round before any lock: 0 never, 1 on retries, 2 always
   uint32_t pad4[2];
 };
+
+// A table's index on the device (index.hip): the table's keys sorted, with
+// their rows, and a static 16-way search tree over them.  Level 0 is the
+// sorted keys, padded with INT64_MAX to a multiple of 16; level l+1 holds the
+// largest key of each 16-key node of level l, padded the same way; the top
+// level is one node.
+constexpr int INDEX_MAX_LEVELS = 8;
+struct IndexDesc {
+  const int64_t *keys;   // level 0
+  const uint32_t *rows;  // row of each sorted key
+  const int64_t *tree;   // levels 1..levels, level l at level_off[l]
+  uint64_t n;            // keys (rows of the table)
+  uint64_t level_off[INDEX_MAX_LEVELS + 1];
+  uint64_t row_base;     // the table's first global row
+  uint64_t elem_base;    // the table's first cell
+  uint32_t n_fields;
+  uint32_t levels;       // tree levels above level 0
+};
+
+// Per-op metadata of a keyed batch: bit 31 keyed, bits 16-23 table, 0-7 field.
+constexpr uint32_t META_KEYED = 1u << 31;
+
+// Resolve the keys of a keyed batch: patch each keyed op's row and cell in
+// `ops`, record its row (within its table) in rows_out, count misses in
+// ctl->stats[DS_INDEX_MISS].  tree = false: binary search of the sorted keys;
+// true: descent of the 16-way tree.  One lane per op either way.
+hipError_t launch_index_lookup(hipStream_t s, bool tree, const int64_t *op_keys, const uint32_t *meta, DevOp *ops,
+                               uint32_t *rows_out, uint64_t n_ops, const IndexDesc *idx, Ctl *ctl);
 
 // Kernel arguments for a GaccO execution (gacco_exec.hip).
 struct GaccoArgs {
