@@ -3,7 +3,7 @@
  *
  * The engine executes a batch of read / read-modify-write transactions
  * concurrently against tables resident in device memory (HBM), under one of
- * six concurrency-control schemes, and reports per transaction a serial key
+ * seven concurrency-control schemes, and reports per transaction a serial key
  * that orders the committed transactions into an equivalent serial execution.
  *
  * Problem statement followed (paper Section 4.1, "Constraints" and
@@ -61,14 +61,18 @@ enum cc_scheme {
   CC_TO = 2,     /* basic timestamp ordering: commit bit + 31-bit RTS + 31-bit WTS */
   CC_MVCC = 3,   /* multi-version timestamp ordering (TO word + version pointer) */
   CC_TICTOC = 4, /* TicToc: lock bit + 15-bit delta + 48-bit WTS */
-  CC_GACCO = 5   /* GaccO, conflict-graph ordering (Section 2 and Section 3, "Conflict Graph
+  CC_GACCO = 5,  /* GaccO, conflict-graph ordering (Section 2 and Section 3, "Conflict Graph
                     Ordering"): preprocessing sorts every row's accesses by transaction id into
                     a lock table; each row is then handed to its accessors in that order, reads
                     and writes alike.  Deterministic, no aborts.  Needs each transaction's ops
                     after the previous transaction's (first_op nondecreasing) and
-                    CC_MODE_PLAIN; accepts only CC_RUN_STRICT_FENCES. */
+                    CC_MODE_PLAIN; accepts only CC_RUN_STRICT_FENCES and CC_RUN_INDEX_TREE. */
+  CC_2PL_WD = 6  /* two-phase locking, wait-die (Section 2 "Two-Phase Locking", Section 3.5): a
+                    transaction older than the exclusive holder of a lock it needs keeps its
+                    locks and waits (a state of its team, at most 64 times per attempt); any
+                    other conflict aborts it.  Age = index in the batch.  Lock word as 2PL. */
 };
-#define CC_N_SCHEMES 6
+#define CC_N_SCHEMES 7
 
 /*
  * Operation kinds.  An operation touches one field of one row.  Its read
@@ -117,8 +121,9 @@ enum cc_txn_status { CC_PENDING = 0, CC_COMMITTED = 1 };
 /*
  * Per-transaction outcome.  Sorting committed transactions by
  * (serial_hi, serial_lo) gives a serial order equivalent to the run:
- *   OCC, 2PL:  (0, ticket)  -- ticket drawn from one device counter while the
- *                              transaction holds all its write locks;
+ *   OCC, 2PL (both forms):  (0, ticket)  -- ticket drawn from one device
+ *                              counter while the transaction holds all its
+ *                              write locks;
  *   TO, MVCC:  (0, ts)      -- the timestamp of the committing attempt;
  *   TicToc:    (commit_ts, ticket);
  *   GaccO:     (0, transaction index) -- the scheme's order is the id order.
@@ -229,6 +234,7 @@ enum cc_stat {
   CC_STAT_PREP_NS = 23,    /* GaccO: preprocessing (access table, radix sort, lock table), HIP events;
                               part of CC_STAT_RUN_NS */
   CC_STAT_INDEX_NS = 24,   /* keyed batches: the index lookups, HIP events; part of CC_STAT_RUN_NS */
+  CC_STAT_WD_WAITS = 25,   /* CC_2PL_WD: times a transaction kept its locks and waited */
   CC_N_STATS = 32
 };
 

@@ -801,6 +801,7 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   a.eager_install = (p.flags & CC_RUN_EAGER_INSTALL) ? 1u : 0u;
   a.wait_unlock = (p.flags & CC_RUN_WAIT_UNLOCK) ? 1u : 0u;
   a.precheck = (p.flags & CC_RUN_PRECHECK) ? 2u : ((p.flags & CC_RUN_NO_PRECHECK) ? 0u : 1u);
+  a.wd_wait_limit = 64;
 
   const uint32_t defer = p.defer_after ? p.defer_after : (p.mode == CC_MODE_SERVE ? 256 : 16);
   a.pass = 0;
@@ -969,6 +970,7 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   b.stats[CC_STAT_T_WAIT_NS] = (uint64_t)((double)h.stats[DS_T_WAIT] * ns_per_tick);
   b.stats[CC_STAT_GAVE_UP] = h.stats[DS_GAVE_UP];
   b.stats[CC_STAT_ADMIT_WAITS] = h.stats[DS_ADMIT_WAITS];
+  b.stats[CC_STAT_WD_WAITS] = h.stats[DS_WD_WAITS];
   for (int i = 0; i < 4; ++i)
     b.stats[CC_STAT_OCC_R1_NS + i] = (uint64_t)((double)h.stats[DS_R1 + i] * ns_per_tick);
   b.stats[CC_STAT_INDEX_NS] = (uint64_t)((double)ms_index * 1e6);

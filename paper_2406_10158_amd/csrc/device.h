@@ -168,6 +168,7 @@ struct Slots {
   uint32_t oi[K]; // op index in the batch
   bool got[K];    // this slot holds its row's lock
   bool valid[K];
+  bool sh[K];     // 2PL wait-die: this slot holds a shared lock (kept while the team waits)
   uint32_t block; // a row another transaction held when this attempt failed to lock (~0u: none)
   uint64_t tr[4]; // wall clock at the end of each round (OCC; for the per-round time breakdown)
 };
@@ -217,7 +218,7 @@ __device__ __forceinline__ void install_values(const Team<L> &t, const Slots<K> 
   }
 }
 
-enum AttemptResult { COMMIT = 0, ABORT_LOCK = 1, ABORT_VALID = 2, TS_OVERFLOW = 3 };
+enum AttemptResult { COMMIT = 0, ABORT_LOCK = 1, ABORT_VALID = 2, TS_OVERFLOW = 3, WAITING = 4 };
 
 // Bound on compare-and-swap retries inside one latch-free critical section.
 constexpr int CAS_RETRIES = 64;

@@ -62,6 +62,7 @@ enum DevStat {
   DS_R3 = 14,
   DS_R4 = 15,
   DS_INDEX_MISS = 16,   // keyed operations whose key no row holds
+  DS_WD_WAITS = 17,     // 2PL wait-die: times a team kept its locks and waited
   DS_N = 24
 };
 
@@ -103,7 +104,8 @@ struct RunArgs {
   uint32_t eager_install;  // OCC: store values in the validation round (undo on abort)
   uint32_t wait_unlock;    // after a lock failure, poll the held row until it is free
   uint32_t precheck;       // OCC load-only round before any lock: 0 never, 1 on retries, 2 always
-  uint32_t pad4[2];
+  uint32_t wd_wait_limit;  // 2PL wait-die: waits of one attempt before it dies anyway
+  uint32_t pad5;
 };
 
 // A table's index on the device (index.hip): the table's keys sorted, with
@@ -186,6 +188,7 @@ CCE_DECLARE_LAUNCH(launch_txn_2pl)
 CCE_DECLARE_LAUNCH(launch_txn_to)
 CCE_DECLARE_LAUNCH(launch_txn_mvcc)
 CCE_DECLARE_LAUNCH(launch_txn_tictoc)
+CCE_DECLARE_LAUNCH(launch_txn_2plwd)
 #undef CCE_DECLARE_LAUNCH
 
 // Memory micro-benchmarks (roofline.hip); see cc_probe in cc.h.

@@ -116,6 +116,7 @@ hipError_t launch_txn(hipStream_t s, int scheme, int lanes, int max_ops, int wav
     case CC_TO: return launch_txn_to(s, lanes, max_ops, waves_per_wg, grid, strict, a, n_cu, grid_used);
     case CC_MVCC: return launch_txn_mvcc(s, lanes, max_ops, waves_per_wg, grid, strict, a, n_cu, grid_used);
     case CC_TICTOC: return launch_txn_tictoc(s, lanes, max_ops, waves_per_wg, grid, strict, a, n_cu, grid_used);
+    case CC_2PL_WD: return launch_txn_2plwd(s, lanes, max_ops, waves_per_wg, grid, strict, a, n_cu, grid_used);
     default: return hipErrorInvalidValue;
   }
 }

@@ -216,6 +216,103 @@ __device__ __forceinline__ int tpl_attempt(const Team<L> &t, Slots<K> &s, bool a
 }
 
 // ===========================================================================
+// Two-phase locking, wait-die (paper Section 2 "Two-Phase Locking": a
+// transaction that finds a lock held waits if it is older than the holder
+// and dies -- aborts -- if it is younger; Section 3.5 implements tpl_nw and
+// tpl_wd over the same lock word, Table 2).  Same word and rounds as the
+// no-wait form above; the age of a transaction is its index in the batch
+// (smaller = older), kept across its restarts, so every transaction is
+// eventually the oldest and cannot starve.
+//   R1  take the locks not yet held.  A failure on a row held exclusively by
+//       a younger transaction means wait: the attempt returns WAITING with
+//       every lock it got still held, and the team retries the missing ones
+//       on a later iteration of the persistent loop.  Any other failure (a
+//       younger requester, readers in the way, or the attempt's waits used
+//       up) means die: release everything and abort.
+//   R2, R3 as no-wait.
+// Waiting only along older-to-younger edges keeps the waits-for graph
+// acyclic, and the youngest holder never waits, so some transaction always
+// finishes.  The wait is a state of the team in the persistent loop, not a
+// spin: the loop keeps running every other team of the wavefront, so a
+// holder in the same wavefront is not starved (Section 3.4, "Spin Lock"),
+// and the holder keeps its lock while the waiter waits, so the two do not
+// retry in lockstep.  Serial key (0, ticket) as 2PL.
+// ===========================================================================
+template <int L, int K, bool STRICT>
+__device__ __forceinline__ int tplwd_attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a,
+                                             uint32_t txn, bool resume, bool may_wait, uint64_t *hi,
+                                             uint64_t *lo) {
+  bool die = false, wait = false;
+  uint32_t blk = ~0u;
+  const uint64_t me = txn & 0x7FFFFFFFu;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (!resume) {
+      s.got[k] = false;
+      s.sh[k] = false;
+    }
+    if (active && s.valid[k] && op_leader(s.rowk[k]) && !s.got[k]) {
+      uint64_t *w = a.words + op_row(s.rowk[k]);
+      uint64_t seen = 0;
+      if (op_written(s.rowk[k])) {
+        uint64_t expected = 0;
+        s.got[k] = cas_word(w, &expected, TPL_EXCL | (me << 32));
+        seen = expected;
+      } else {
+        const uint64_t old = add_word(w, 1ull);
+        s.got[k] = !(old & TPL_EXCL);
+        s.sh[k] = s.got[k];
+        if (!s.got[k]) add_word(w, ~0ull);  // take the increment back out
+        seen = old;
+      }
+      if (!s.got[k]) {
+        if (blk == ~0u) blk = op_row(s.rowk[k]);
+        const uint64_t holder = (seen >> 32) & 0x7FFFFFFFu;
+        const bool can_wait = may_wait && (seen & TPL_EXCL) && me < holder;
+        wait |= can_wait;
+        die |= !can_wait;
+      }
+    }
+  }
+  order_point<STRICT>();
+  s.block = blocking_row(t, blk);
+  const bool any_die = t.any(die);
+  const bool any_wait = !any_die && t.any(wait);
+  if (active && any_die) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (!s.got[k]) continue;
+      uint64_t *w = a.words + op_row(s.rowk[k]);
+      if (s.sh[k]) add_word(w, ~0ull);
+      else and_word(w, TPL_COUNT);
+      s.got[k] = false;
+      s.sh[k] = false;
+    }
+  }
+  const bool alive = active && !any_die && !any_wait;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (alive && s.valid[k]) s.x[k] = ld_val(a.data + s.elem[k]);
+  const uint64_t ticket = t.claim(&a.ctl->ticket, alive, 1) + 1;
+  order_point<STRICT>();
+  install_values<L, K>(t, s, alive, a);
+  order_point<STRICT>();
+  if (alive) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (!s.got[k]) continue;
+      uint64_t *w = a.words + op_row(s.rowk[k]);
+      if (s.sh[k]) add_word(w, ~0ull);
+      else and_word(w, TPL_COUNT);
+    }
+  }
+  *hi = 0;
+  *lo = ticket;
+  if (!active) return COMMIT;
+  return any_die ? ABORT_LOCK : (any_wait ? WAITING : COMMIT);
+}
+
+// ===========================================================================
 // Basic timestamp ordering, and its multi-version form (paper Section 2
 // "Timestamp Ordering" and "MVCC"; Section 3.5 "Basic TO" and "MVCC";
 // word = commit/dirty bit, 31-bit RTS, 31-bit WTS, Table 2; MVCC adds a

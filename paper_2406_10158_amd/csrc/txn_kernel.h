@@ -16,12 +16,14 @@ struct MaxThreads {
 
 template <int L, int K, int SCHEME, bool STRICT>
 __device__ __forceinline__ int attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a, uint32_t txn,
-                                       bool retry, uint64_t *hi, uint64_t *lo) {
+                                       bool retry, bool resume, bool may_wait, uint64_t *hi, uint64_t *lo) {
   if constexpr (SCHEME == CC_OCC) {
     const bool precheck = a.precheck == 2 || (a.precheck == 1 && retry);
     return occ_attempt<L, K, STRICT>(t, s, active, a, precheck, hi, lo);
   }
   else if constexpr (SCHEME == CC_2PL_NW) return tpl_attempt<L, K, STRICT>(t, s, active, a, txn, hi, lo);
+  else if constexpr (SCHEME == CC_2PL_WD)
+    return tplwd_attempt<L, K, STRICT>(t, s, active, a, txn, resume, may_wait, hi, lo);
   else if constexpr (SCHEME == CC_TO) return to_attempt<L, K, STRICT, false>(t, s, active, a, hi, lo);
   else if constexpr (SCHEME == CC_MVCC) return to_attempt<L, K, STRICT, true>(t, s, active, a, hi, lo);
   else return tictoc_attempt<L, K, STRICT>(t, s, active, a, hi, lo);
@@ -52,6 +54,9 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
   uint32_t wait_row = ~0u;  // row whose release the team waits for (~0u: none)
   uint32_t polls = 0;
   uint64_t n_admit_wait = 0;
+  bool resume = false;      // 2PL wait-die: the team waits holding locks; its next attempt continues this one
+  uint32_t waits = 0;       // 2PL wait-die: waits of the current attempt
+  uint64_t n_waits = 0;
 
   for (;;) {
     const bool need = txn < 0 && !done;
@@ -66,6 +71,8 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
         reserved = 0;
         admitted = false;
         wait_row = ~0u;
+        resume = false;
+        waits = 0;
       } else {
         done = true;
       }
@@ -129,8 +136,11 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
       first = d.first;
       n = d.n;
     }
+    // a waiting team (2PL wait-die) keeps its staged operations and locks
+    const bool keep = SCHEME == CC_2PL_WD && resume;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
+      if (keep) continue;
       const uint32_t idx = (uint32_t)t.tl + (uint32_t)(k * L);
       s.valid[k] = active && idx < n;
       s.oi[k] = first + idx;
@@ -150,10 +160,10 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
     uint64_t key_hi = 0, key_lo = 0;
     s.block = ~0u;
     const int r = attempt<L, K, SCHEME, STRICT>(t, s, active, a, (uint32_t)(txn < 0 ? 0 : txn), attempts >= 2,
-                                                &key_hi, &key_lo);
+                                                keep, waits < a.wd_wait_limit, &key_hi, &key_lo);
     if (t.tl == 0 && txn >= 0) {
       const uint64_t dt = wall_clock64() - now;
-      if (!active) t_wait += dt;
+      if (!active || r == WAITING) t_wait += dt;
       else if (r == COMMIT) t_useful += dt;
       else t_abort += dt;
       if constexpr (SCHEME == CC_OCC) {
@@ -165,7 +175,16 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
         }
       }
     }
-    if (active) {
+    if (active && r == WAITING) {
+      // wait-die: keep the locks and try the missing ones again shortly (a
+      // wait is not an attempt; an attempt's waits are bounded)
+      ++waits;
+      if (t.tl == 0) ++n_waits;
+      resume = true;
+      ready_at = now + 1 + (mix64(((uint64_t)txn << 20) ^ waits) % ((uint64_t)a.backoff_ticks * (1 + (waits < 8 ? waits : 8))));
+    } else if (active) {
+      resume = false;
+      waits = 0;
       ++attempts;
       ++pass_att;
       ++n_att;
@@ -224,7 +243,7 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
   const uint64_t c0 = wave_sum(n_commit), c1 = wave_sum(n_att), c2 = wave_sum(n_lock), c3 = wave_sum(n_valid),
                  c4 = wave_sum(n_gave), c5 = wave_max(max_att), c6 = wave_sum(n_defer), c7 = wave_sum(n_ovf);
   const uint64_t c8 = wave_sum(t_useful), c9 = wave_sum(t_abort), c10 = wave_sum(t_wait),
-                 c11 = wave_sum(n_admit_wait);
+                 c11 = wave_sum(n_admit_wait), c13 = wave_sum(n_waits);
   uint64_t cr[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) cr[i] = wave_sum(t_round[i]);
@@ -241,6 +260,7 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
     if (c9) atomicAdd((unsigned long long *)&a.ctl->stats[DS_T_ABORT], (unsigned long long)c9);
     if (c10) atomicAdd((unsigned long long *)&a.ctl->stats[DS_T_WAIT], (unsigned long long)c10);
     if (c11) atomicAdd((unsigned long long *)&a.ctl->stats[DS_ADMIT_WAITS], (unsigned long long)c11);
+    if (c13) atomicAdd((unsigned long long *)&a.ctl->stats[DS_WD_WAITS], (unsigned long long)c13);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
       if (cr[i]) atomicAdd((unsigned long long *)&a.ctl->stats[DS_R1 + i], (unsigned long long)cr[i]);

@@ -12,7 +12,7 @@ if ROOT not in sys.path:
 
 import oracle  # noqa: E402
 
-SCHEMES = ["occ", "2pl_nw", "to", "mvcc", "tictoc"]
+SCHEMES = ["occ", "2pl_nw", "to", "mvcc", "tictoc", "2pl_wd"]
 
 
 def binding():

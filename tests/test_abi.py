@@ -122,7 +122,7 @@ def test_check_batch_gacco_needs_transactions_in_op_order(b):
     assert b.cc_check_batch(SHAPES, two, ops, b.CC_OCC) == 0
     two["first_op"] = [0, 2]
     assert b.cc_check_batch(SHAPES, two, ops, b.CC_GACCO) == 0
-    assert b.cc_check_batch(SHAPES, two, ops, 6) == b.CC_E_INVAL  # one past the last scheme
+    assert b.cc_check_batch(SHAPES, two, ops, b.CC_2PL_WD + 1) == b.CC_E_INVAL  # one past the last scheme
 
 
 def test_check_batch_accepts_generated_workloads(b):

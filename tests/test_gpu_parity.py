@@ -16,7 +16,7 @@ from paper_2406_10158_amd import workload as wl
 pytestmark = pytest.mark.gpu
 
 IMPLEMENTED = SCHEMES
-TICKETED = ["occ", "2pl_nw", "to", "mvcc"]  # serial key (0, counter)
+TICKETED = ["occ", "2pl_nw", "to", "mvcc", "2pl_wd"]  # serial key (0, counter)
 
 
 @pytest.fixture(scope="module", autouse=True)
