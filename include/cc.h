@@ -181,6 +181,10 @@ enum cc_mode { CC_MODE_PLAIN = 0, CC_MODE_EPOCH = 1, CC_MODE_SERVE = 2 };
                                      runs from a transaction's third attempt on (repeated failures are
                                      the sign of contention) */
 #define CC_RUN_NO_PRECHECK 0x10u  /* OCC: never run the pre-check round */
+#define CC_RUN_LATCH 0x40u        /* latch variants of the non-deterministic schemes (paper Section 4.2,
+                                     Exp-7): a 32-bit latch per row guards its control word, and every
+                                     update of the word is a critical section [latch, load, store,
+                                     unlatch] instead of one 64-bit atomic.  Not for CC_GACCO. */
 #define CC_RUN_INDEX_TREE 0x20u   /* keyed batches: look keys up by descending the index's 16-way tree
                                      (one 128-byte node per level) instead of by binary search of the
                                      sorted keys */

@@ -72,6 +72,7 @@ struct cc_ctx {
   Ctl *d_ctl = nullptr;
   std::vector<DevIndex> indexes;      // per table (empty entries: no index)
   IndexDesc *d_idx = nullptr;         // device copy of every table's IndexDesc
+  uint32_t *d_latch = nullptr;        // CC_RUN_LATCH: one latch per global row
   std::map<uint64_t, Batch> batches;
   uint64_t next_batch = 1;
   hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -293,6 +294,7 @@ cc_status cc_destroy(cc_ctx *c) {
     if (ix.tree) (void)hipFree(ix.tree);
   }
   if (c->d_idx) (void)hipFree(c->d_idx);
+  if (c->d_latch) (void)hipFree(c->d_latch);
   if (c->d_data) (void)hipFree(c->d_data);
   if (c->d_words) (void)hipFree(c->d_words);
   if (c->d_aux) (void)hipFree(c->d_aux);
@@ -767,7 +769,7 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   const uint32_t wpw = p.waves_per_wg ? p.waves_per_wg : 1;
   if (wpw < 1 || wpw > 16) return fail(c, CC_E_INVAL, "waves_per_wg must be 1..16");
   if (p.flags & ~(CC_RUN_STRICT_FENCES | CC_RUN_EAGER_INSTALL | CC_RUN_WAIT_UNLOCK | CC_RUN_PRECHECK |
-                  CC_RUN_NO_PRECHECK | CC_RUN_INDEX_TREE))
+                  CC_RUN_NO_PRECHECK | CC_RUN_INDEX_TREE | CC_RUN_LATCH))
     return fail(c, CC_E_INVAL, "unknown run flag");
   if (p.flags & CC_RUN_WAIT_UNLOCK)
     // Switched off: two teams of one wavefront that block each other both see
@@ -802,6 +804,14 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   a.wait_unlock = (p.flags & CC_RUN_WAIT_UNLOCK) ? 1u : 0u;
   a.precheck = (p.flags & CC_RUN_PRECHECK) ? 2u : ((p.flags & CC_RUN_NO_PRECHECK) ? 0u : 1u);
   a.wd_wait_limit = 64;
+  if (p.flags & CC_RUN_LATCH) {
+    if (!c->d_latch) {
+      // latches are free between critical sections, so they are cleared once
+      HIP_OR(c, hipMalloc(&c->d_latch, std::max<uint64_t>(c->total_rows, 1) * sizeof(uint32_t)));
+      HIP_OR(c, hipMemsetAsync(c->d_latch, 0, std::max<uint64_t>(c->total_rows, 1) * sizeof(uint32_t), c->stream));
+    }
+    a.latch = c->d_latch;
+  }
 
   const uint32_t defer = p.defer_after ? p.defer_after : (p.mode == CC_MODE_SERVE ? 256 : 16);
   a.pass = 0;
@@ -826,6 +836,7 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   int first_grid = 0;
   bool epoch_limit = false;
   const bool strict = (p.flags & CC_RUN_STRICT_FENCES) != 0;
+  const bool latch = (p.flags & CC_RUN_LATCH) != 0;
 
   // Plain passes over the pending transactions: each pass runs 8x fewer
   // workgroups than the last, down to a single wavefront that never defers,
@@ -848,8 +859,8 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
       a.defer_after = last ? 0u : defer;
       HIP_OR(c, hipEventRecord(c->ev[1], c->stream));
       int grid_used = 0;
-      hipError_t e = launch_txn(c->stream, b.scheme, (int)lanes, (int)b.max_ops, (int)waves, grid, strict, a, c->n_cu,
-                                &grid_used);
+      hipError_t e = launch_txn(c->stream, b.scheme, (int)lanes, (int)b.max_ops, (int)waves, grid, strict, latch, a,
+                                c->n_cu, &grid_used);
       if (e != hipSuccess) return launch_error(c, e);
       HIP_OR(c, hipEventRecord(c->ev[2], c->stream));
       HIP_OR(c, hipStreamSynchronize(c->stream));
@@ -895,8 +906,8 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
       for (uint32_t i = 0; i < EPOCHS_PER_GRAPH && e == hipSuccess; ++i) {
         e = launch_compact(c->stream, b.d_out, b.n_txns, a.max_attempts, b.d_list, c->d_ctl);
         if (e == hipSuccess)
-          e = launch_txn(c->stream, b.scheme, (int)lanes, (int)b.max_ops, (int)wpw, (int)p.grid, strict, a, c->n_cu,
-                         &grid_used);
+          e = launch_txn(c->stream, b.scheme, (int)lanes, (int)b.max_ops, (int)wpw, (int)p.grid, strict, latch, a,
+                         c->n_cu, &grid_used);
       }
       const hipError_t e2 = hipStreamEndCapture(c->stream, &g);
       if (e != hipSuccess) {
@@ -982,6 +993,7 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
       for (uint64_t t = 0; t < b.n_txns; ++t) o[t].commit_ns -= b.arrival_ns[t];
     latency_percentiles(o, &b.stats[CC_STAT_LAT_P50_NS], &b.stats[CC_STAT_LAT_P99_NS]);
   }
+  if (h.stats[DS_LATCH_STUCK]) return fail(c, CC_E_LIVELOCK, "a row latch was not obtained within the spin limit");
   if (h.stats[DS_TS_OVERFLOW]) return fail(c, CC_E_TS_OVERFLOW, "timestamp overflow during the run");
   if (epoch_limit) return fail(c, CC_E_LIVELOCK, "max_epochs reached with transactions pending");
   if (h.stats[DS_COMMITTED] != b.n_txns) {

@@ -63,6 +63,7 @@ enum DevStat {
   DS_R4 = 15,
   DS_INDEX_MISS = 16,   // keyed operations whose key no row holds
   DS_WD_WAITS = 17,     // 2PL wait-die: times a team kept its locks and waited
+  DS_LATCH_STUCK = 18,  // CC_RUN_LATCH: latches not obtained within the spin limit (run invalid)
   DS_N = 24
 };
 
@@ -106,6 +107,7 @@ struct RunArgs {
   uint32_t precheck;       // OCC load-only round before any lock: 0 never, 1 on retries, 2 always
   uint32_t wd_wait_limit;  // 2PL wait-die: waits of one attempt before it dies anyway
   uint32_t pad5;
+  uint32_t *latch;         // CC_RUN_LATCH: one 32-bit latch per global row (else unused)
 };
 
 // A table's index on the device (index.hip): the table's keys sorted, with
@@ -177,12 +179,12 @@ hipError_t launch_compact(hipStream_t s, const DevOutcome *out, uint64_t n_txns,
 // Runs one plain batch: returns hipErrorInvalidValue for an unsupported
 // (lanes, ops-per-lane) combination.
 hipError_t launch_txn(hipStream_t s, int scheme, int lanes, int max_ops, int waves_per_wg, int grid,
-                      bool strict, const RunArgs &a, int n_cu, int *grid_used);
+                      bool strict, bool latch, const RunArgs &a, int n_cu, int *grid_used);
 
 // Per-scheme launchers (txn_<scheme>.hip).
-#define CCE_DECLARE_LAUNCH(NAME)                                                                           \
-  hipError_t NAME(hipStream_t s, int lanes, int max_ops, int waves_per_wg, int grid, bool strict, const RunArgs &a, \
-                  int n_cu, int *grid_used);
+#define CCE_DECLARE_LAUNCH(NAME)                                                                    \
+  hipError_t NAME(hipStream_t s, int lanes, int max_ops, int waves_per_wg, int grid, bool strict, bool latch, \
+                  const RunArgs &a, int n_cu, int *grid_used);
 CCE_DECLARE_LAUNCH(launch_txn_occ)
 CCE_DECLARE_LAUNCH(launch_txn_2pl)
 CCE_DECLARE_LAUNCH(launch_txn_to)

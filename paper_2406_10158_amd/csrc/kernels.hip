@@ -109,14 +109,14 @@ hipError_t launch_init(hipStream_t s, uint64_t *words, uint64_t n_words, uint64_
 }
 
 hipError_t launch_txn(hipStream_t s, int scheme, int lanes, int max_ops, int waves_per_wg, int grid, bool strict,
-                      const RunArgs &a, int n_cu, int *grid_used) {
+                      bool latch, const RunArgs &a, int n_cu, int *grid_used) {
   switch (scheme) {
-    case CC_OCC: return launch_txn_occ(s, lanes, max_ops, waves_per_wg, grid, strict, a, n_cu, grid_used);
-    case CC_2PL_NW: return launch_txn_2pl(s, lanes, max_ops, waves_per_wg, grid, strict, a, n_cu, grid_used);
-    case CC_TO: return launch_txn_to(s, lanes, max_ops, waves_per_wg, grid, strict, a, n_cu, grid_used);
-    case CC_MVCC: return launch_txn_mvcc(s, lanes, max_ops, waves_per_wg, grid, strict, a, n_cu, grid_used);
-    case CC_TICTOC: return launch_txn_tictoc(s, lanes, max_ops, waves_per_wg, grid, strict, a, n_cu, grid_used);
-    case CC_2PL_WD: return launch_txn_2plwd(s, lanes, max_ops, waves_per_wg, grid, strict, a, n_cu, grid_used);
+    case CC_OCC: return launch_txn_occ(s, lanes, max_ops, waves_per_wg, grid, strict, latch, a, n_cu, grid_used);
+    case CC_2PL_NW: return launch_txn_2pl(s, lanes, max_ops, waves_per_wg, grid, strict, latch, a, n_cu, grid_used);
+    case CC_TO: return launch_txn_to(s, lanes, max_ops, waves_per_wg, grid, strict, latch, a, n_cu, grid_used);
+    case CC_MVCC: return launch_txn_mvcc(s, lanes, max_ops, waves_per_wg, grid, strict, latch, a, n_cu, grid_used);
+    case CC_TICTOC: return launch_txn_tictoc(s, lanes, max_ops, waves_per_wg, grid, strict, latch, a, n_cu, grid_used);
+    case CC_2PL_WD: return launch_txn_2plwd(s, lanes, max_ops, waves_per_wg, grid, strict, latch, a, n_cu, grid_used);
     default: return hipErrorInvalidValue;
   }
 }

@@ -12,6 +12,74 @@
 
 namespace cce {
 
+// ---------------------------------------------------------------------------
+// Control-word updates.  By default each is one 64-bit atomic on the word
+// (the paper's latch-free form, Section 3.5).  With LATCH (CC_RUN_LATCH) a
+// 32-bit latch per row guards the word instead, as in the paper's latch
+// variants of the schemes (Section 4.2, Exp-7): every write of the word,
+// releases included, takes the latch, so each update is a critical section
+// [latch, load, store, unlatch] equivalent to the atomic it replaces, and
+// plain loads of the word stay valid.  The CAS on the latch, the section and
+// the release are one iteration of the spin loop (Section 3.4, "Spin
+// Lock"): a lane of the same wavefront that holds the latch finishes its
+// section in the iteration it took the latch, so spinning lanes cannot
+// block it.
+// ---------------------------------------------------------------------------
+constexpr uint32_t LATCH_SPINS = 1u << 22;
+
+template <bool STRICT, class F>
+__device__ __forceinline__ uint64_t latched(const RunArgs &a, uint64_t *w, F f) {
+  uint32_t *lt = a.latch + (w - a.words);
+  for (uint32_t it = 0; it < LATCH_SPINS; ++it) {
+    uint32_t e = 0;
+    if (__hip_atomic_compare_exchange_strong(lt, &e, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT)) {
+      const uint64_t old = ld_word(w);
+      const uint64_t nw = f(old);
+      if (nw != old) st_word(w, nw);
+      order_point<STRICT>();  // the word's new value is performed before the latch is free
+      __hip_atomic_store(lt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return old;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  // a latch no one released in 2^22 tries: cc_run reports the run as failed
+  add_word(&a.ctl->stats[DS_LATCH_STUCK], 1ull);
+  return ld_word(w);
+}
+
+template <bool LATCH, bool STRICT>
+__device__ __forceinline__ uint64_t w_or(const RunArgs &a, uint64_t *w, uint64_t v) {
+  if constexpr (LATCH) return latched<STRICT>(a, w, [&](uint64_t o) { return o | v; });
+  else return or_word(w, v);
+}
+template <bool LATCH, bool STRICT>
+__device__ __forceinline__ uint64_t w_and(const RunArgs &a, uint64_t *w, uint64_t v) {
+  if constexpr (LATCH) return latched<STRICT>(a, w, [&](uint64_t o) { return o & v; });
+  else return and_word(w, v);
+}
+template <bool LATCH, bool STRICT>
+__device__ __forceinline__ uint64_t w_add(const RunArgs &a, uint64_t *w, uint64_t v) {
+  if constexpr (LATCH) return latched<STRICT>(a, w, [&](uint64_t o) { return o + v; });
+  else return add_word(w, v);
+}
+template <bool LATCH, bool STRICT>
+__device__ __forceinline__ bool w_cas(const RunArgs &a, uint64_t *w, uint64_t *expected, uint64_t desired) {
+  if constexpr (LATCH) {
+    const uint64_t want = *expected;
+    const uint64_t old = latched<STRICT>(a, w, [&](uint64_t o) { return o == want ? desired : o; });
+    *expected = old;
+    return old == want;
+  } else {
+    return cas_word(w, expected, desired);
+  }
+}
+template <bool LATCH, bool STRICT>
+__device__ __forceinline__ void w_st(const RunArgs &a, uint64_t *w, uint64_t v) {
+  if constexpr (LATCH) (void)latched<STRICT>(a, w, [&](uint64_t) { return v; });
+  else st_word(w, v);
+}
+
 // ===========================================================================
 // OCC, Silo-style (paper Section 2 "Optimistic Concurrency Control";
 // Section 3.5 "OCC"; control word per row = lock bit + 63-bit TID, Table 2).
@@ -38,7 +106,7 @@ namespace cce {
 // ===========================================================================
 constexpr uint64_t OCC_LOCK = 1ull << 63;
 
-template <int L, int K, bool STRICT>
+template <int L, int K, bool STRICT, bool LATCH>
 __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a,
                                            bool precheck, uint64_t *hi, uint64_t *lo) {
   bool fail = false;
@@ -72,7 +140,7 @@ __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool a
     if (go && s.valid[k] && op_leader(s.rowk[k]) && (!precheck || op_written(s.rowk[k]))) {
       uint64_t *w = a.words + op_row(s.rowk[k]);
       if (op_written(s.rowk[k])) {
-        const uint64_t old = or_word(w, OCC_LOCK);
+        const uint64_t old = w_or<LATCH, STRICT>(a, w, OCC_LOCK);
         s.v[k] = old;
         s.got[k] = !(old & OCC_LOCK);
         if (!s.got[k] && blk == ~0u) blk = op_row(s.rowk[k]);
@@ -93,7 +161,7 @@ __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool a
   if (active && lock_fail) {
 #pragma unroll
     for (int k = 0; k < K; ++k)
-      if (s.got[k]) st_word(a.words + op_row(s.rowk[k]), s.v[k]);
+      if (s.got[k]) w_st<LATCH, STRICT>(a, a.words + op_row(s.rowk[k]), s.v[k]);
   }
   // R2: values under the locks / after the observed words, and the ticket
 #pragma unroll
@@ -133,7 +201,7 @@ __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool a
   // validation, which a restored old TID would not guarantee.
 #pragma unroll
   for (int k = 0; k < K; ++k)
-    if (alive && s.got[k]) st_word(a.words + op_row(s.rowk[k]), (commit || eager) ? ticket : s.v[k]);
+    if (alive && s.got[k]) w_st<LATCH, STRICT>(a, a.words + op_row(s.rowk[k]), (commit || eager) ? ticket : s.v[k]);
   s.tr[3] = wall_clock64();
   *hi = 0;
   *lo = ticket;
@@ -156,7 +224,7 @@ __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool a
 constexpr uint64_t TPL_EXCL = 1ull << 63;
 constexpr uint64_t TPL_COUNT = (1ull << 31) - 1ull;
 
-template <int L, int K, bool STRICT>
+template <int L, int K, bool STRICT, bool LATCH>
 __device__ __forceinline__ int tpl_attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a,
                                            uint32_t txn, uint64_t *hi, uint64_t *lo) {
   bool fail = false;
@@ -170,11 +238,11 @@ __device__ __forceinline__ int tpl_attempt(const Team<L> &t, Slots<K> &s, bool a
       uint64_t *w = a.words + op_row(s.rowk[k]);
       if (op_written(s.rowk[k])) {
         uint64_t expected = 0;
-        s.got[k] = cas_word(w, &expected, TPL_EXCL | ((uint64_t)(txn & 0x7FFFFFFFu) << 32));
+        s.got[k] = w_cas<LATCH, STRICT>(a, w, &expected, TPL_EXCL | ((uint64_t)(txn & 0x7FFFFFFFu) << 32));
         if (!s.got[k] && (expected & TPL_EXCL) && blk == ~0u) blk = op_row(s.rowk[k]);
         fail |= !s.got[k];
       } else {
-        const uint64_t old = add_word(w, 1ull);
+        const uint64_t old = w_add<LATCH, STRICT>(a, w, 1ull);
         shared[k] = true;  // our increment is in the word until we take it out
         s.got[k] = !(old & TPL_EXCL);
         if (!s.got[k] && blk == ~0u) blk = op_row(s.rowk[k]);
@@ -190,8 +258,8 @@ __device__ __forceinline__ int tpl_attempt(const Team<L> &t, Slots<K> &s, bool a
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       uint64_t *w = a.words + op_row(s.rowk[k]);
-      if (shared[k]) add_word(w, ~0ull);
-      else if (s.got[k]) and_word(w, TPL_COUNT);
+      if (shared[k]) w_add<LATCH, STRICT>(a, w, ~0ull);
+      else if (s.got[k]) w_and<LATCH, STRICT>(a, w, TPL_COUNT);
     }
   }
 #pragma unroll
@@ -205,8 +273,8 @@ __device__ __forceinline__ int tpl_attempt(const Team<L> &t, Slots<K> &s, bool a
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       uint64_t *w = a.words + op_row(s.rowk[k]);
-      if (shared[k]) add_word(w, ~0ull);
-      else if (s.got[k]) and_word(w, TPL_COUNT);
+      if (shared[k]) w_add<LATCH, STRICT>(a, w, ~0ull);
+      else if (s.got[k]) w_and<LATCH, STRICT>(a, w, TPL_COUNT);
     }
   }
   *hi = 0;
@@ -238,7 +306,7 @@ __device__ __forceinline__ int tpl_attempt(const Team<L> &t, Slots<K> &s, bool a
 // and the holder keeps its lock while the waiter waits, so the two do not
 // retry in lockstep.  Serial key (0, ticket) as 2PL.
 // ===========================================================================
-template <int L, int K, bool STRICT>
+template <int L, int K, bool STRICT, bool LATCH>
 __device__ __forceinline__ int tplwd_attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a,
                                              uint32_t txn, bool resume, bool may_wait, uint64_t *hi,
                                              uint64_t *lo) {
@@ -256,13 +324,13 @@ __device__ __forceinline__ int tplwd_attempt(const Team<L> &t, Slots<K> &s, bool
       uint64_t seen = 0;
       if (op_written(s.rowk[k])) {
         uint64_t expected = 0;
-        s.got[k] = cas_word(w, &expected, TPL_EXCL | (me << 32));
+        s.got[k] = w_cas<LATCH, STRICT>(a, w, &expected, TPL_EXCL | (me << 32));
         seen = expected;
       } else {
-        const uint64_t old = add_word(w, 1ull);
+        const uint64_t old = w_add<LATCH, STRICT>(a, w, 1ull);
         s.got[k] = !(old & TPL_EXCL);
         s.sh[k] = s.got[k];
-        if (!s.got[k]) add_word(w, ~0ull);  // take the increment back out
+        if (!s.got[k]) w_add<LATCH, STRICT>(a, w, ~0ull);  // take the increment back out
         seen = old;
       }
       if (!s.got[k]) {
@@ -283,8 +351,8 @@ __device__ __forceinline__ int tplwd_attempt(const Team<L> &t, Slots<K> &s, bool
     for (int k = 0; k < K; ++k) {
       if (!s.got[k]) continue;
       uint64_t *w = a.words + op_row(s.rowk[k]);
-      if (s.sh[k]) add_word(w, ~0ull);
-      else and_word(w, TPL_COUNT);
+      if (s.sh[k]) w_add<LATCH, STRICT>(a, w, ~0ull);
+      else w_and<LATCH, STRICT>(a, w, TPL_COUNT);
       s.got[k] = false;
       s.sh[k] = false;
     }
@@ -302,8 +370,8 @@ __device__ __forceinline__ int tplwd_attempt(const Team<L> &t, Slots<K> &s, bool
     for (int k = 0; k < K; ++k) {
       if (!s.got[k]) continue;
       uint64_t *w = a.words + op_row(s.rowk[k]);
-      if (s.sh[k]) add_word(w, ~0ull);
-      else and_word(w, TPL_COUNT);
+      if (s.sh[k]) w_add<LATCH, STRICT>(a, w, ~0ull);
+      else w_and<LATCH, STRICT>(a, w, TPL_COUNT);
     }
   }
   *hi = 0;
@@ -343,7 +411,7 @@ __device__ __forceinline__ uint64_t to_wts(uint64_t w) { return w & TO_MASK31; }
 __device__ __forceinline__ uint64_t to_word(uint64_t rts, uint64_t wts) { return (rts << 31) | wts; }
 constexpr int MVCC_MAX_WALK = 1 << 16;
 
-template <int L, int K, bool STRICT, bool MV>
+template <int L, int K, bool STRICT, bool MV, bool LATCH>
 __device__ __forceinline__ int to_attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a,
                                           uint64_t *hi, uint64_t *lo) {
   const uint64_t ts = t.claim(&a.ctl->ticket, active, 1) + 1;
@@ -368,7 +436,7 @@ __device__ __forceinline__ int to_attempt(const Team<L> &t, Slots<K> &s, bool ac
         } else if (op_written(s.rowk[k])) {
           if (ts < to_rts(w) || ts < to_wts(w)) {
             bad = true;
-          } else if (cas_word(wp, &w, w | TO_DIRTY)) {
+          } else if (w_cas<LATCH, STRICT>(a, wp, &w, w | TO_DIRTY)) {
             done = true;
             s.got[k] = true;
           }
@@ -381,7 +449,7 @@ __device__ __forceinline__ int to_attempt(const Team<L> &t, Slots<K> &s, bool ac
           }
         } else if (!lead || to_rts(w) >= ts) {
           done = true;
-        } else if (cas_word(wp, &w, to_word(ts, to_wts(w)))) {
+        } else if (w_cas<LATCH, STRICT>(a, wp, &w, to_word(ts, to_wts(w)))) {
           done = true;
         }
       }
@@ -397,7 +465,7 @@ __device__ __forceinline__ int to_attempt(const Team<L> &t, Slots<K> &s, bool ac
   if (active && lock_fail) {
 #pragma unroll
     for (int k = 0; k < K; ++k)
-      if (s.got[k]) st_word(a.words + op_row(s.rowk[k]), s.v[k]);
+      if (s.got[k]) w_st<LATCH, STRICT>(a, a.words + op_row(s.rowk[k]), s.v[k]);
   }
   uint64_t ptr[K];
 #pragma unroll
@@ -451,7 +519,7 @@ __device__ __forceinline__ int to_attempt(const Team<L> &t, Slots<K> &s, bool ac
   if (alive && valid_fail) {
 #pragma unroll
     for (int k = 0; k < K; ++k)
-      if (s.got[k]) st_word(a.words + op_row(s.rowk[k]), s.v[k]);
+      if (s.got[k]) w_st<LATCH, STRICT>(a, a.words + op_row(s.rowk[k]), s.v[k]);
   }
   if (MV) {
     // history nodes for every write op: pre-image, writer ts, cell; link with
@@ -472,7 +540,7 @@ __device__ __forceinline__ int to_attempt(const Team<L> &t, Slots<K> &s, bool ac
   order_point<STRICT>();
 #pragma unroll
   for (int k = 0; k < K; ++k)
-    if (commit && s.got[k]) st_word(a.words + op_row(s.rowk[k]), to_word(ts, ts));
+    if (commit && s.got[k]) w_st<LATCH, STRICT>(a, a.words + op_row(s.rowk[k]), to_word(ts, ts));
   *hi = 0;
   *lo = ts;
   if (!active) return COMMIT;
@@ -503,7 +571,7 @@ constexpr uint64_t TT_DELTA_MAX = (1ull << 15) - 1ull;
 __device__ __forceinline__ uint64_t tt_wts(uint64_t w) { return w & TT_WTS_MASK; }
 __device__ __forceinline__ uint64_t tt_rts(uint64_t w) { return tt_wts(w) + ((w >> 48) & TT_DELTA_MAX); }
 
-template <int L, int K, bool STRICT>
+template <int L, int K, bool STRICT, bool LATCH>
 __device__ __forceinline__ int tictoc_attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a,
                                               uint64_t *hi, uint64_t *lo) {
   bool fail = false;
@@ -514,7 +582,7 @@ __device__ __forceinline__ int tictoc_attempt(const Team<L> &t, Slots<K> &s, boo
     if (active && s.valid[k] && op_leader(s.rowk[k])) {
       uint64_t *w = a.words + op_row(s.rowk[k]);
       if (op_written(s.rowk[k])) {
-        const uint64_t old = or_word(w, TT_LOCK);
+        const uint64_t old = w_or<LATCH, STRICT>(a, w, TT_LOCK);
         s.v[k] = old;
         s.got[k] = !(old & TT_LOCK);
         if (!s.got[k] && blk == ~0u) blk = op_row(s.rowk[k]);
@@ -534,7 +602,7 @@ __device__ __forceinline__ int tictoc_attempt(const Team<L> &t, Slots<K> &s, boo
   if (active && lock_fail) {
 #pragma unroll
     for (int k = 0; k < K; ++k)
-      if (s.got[k]) st_word(a.words + op_row(s.rowk[k]), s.v[k]);
+      if (s.got[k]) w_st<LATCH, STRICT>(a, a.words + op_row(s.rowk[k]), s.v[k]);
   }
   uint64_t cts = 0;
 #pragma unroll
@@ -572,7 +640,7 @@ __device__ __forceinline__ int tictoc_attempt(const Team<L> &t, Slots<K> &s, boo
             wts = cts - TT_DELTA_MAX;
             delta = TT_DELTA_MAX;
           }
-          if (cas_word(wp, &w, wts | (delta << 48))) done = true;
+          if (w_cas<LATCH, STRICT>(a, wp, &w, wts | (delta << 48))) done = true;
         }
       }
       bad |= b || !done;
@@ -583,13 +651,13 @@ __device__ __forceinline__ int tictoc_attempt(const Team<L> &t, Slots<K> &s, boo
   if (alive && valid_fail) {
 #pragma unroll
     for (int k = 0; k < K; ++k)
-      if (s.got[k]) st_word(a.words + op_row(s.rowk[k]), s.v[k]);
+      if (s.got[k]) w_st<LATCH, STRICT>(a, a.words + op_row(s.rowk[k]), s.v[k]);
   }
   install_values<L, K>(t, s, commit, a);
   order_point<STRICT>();
 #pragma unroll
   for (int k = 0; k < K; ++k)
-    if (commit && s.got[k]) st_word(a.words + op_row(s.rowk[k]), cts);
+    if (commit && s.got[k]) w_st<LATCH, STRICT>(a, a.words + op_row(s.rowk[k]), cts);
   *hi = cts;
   *lo = ticket;
   if (!active) return COMMIT;

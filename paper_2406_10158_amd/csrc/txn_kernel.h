@@ -14,26 +14,26 @@ struct MaxThreads {
   static constexpr int value = K <= 1 ? 1024 : (K <= 4 ? 512 : 256);
 };
 
-template <int L, int K, int SCHEME, bool STRICT>
+template <int L, int K, int SCHEME, bool STRICT, bool LATCH>
 __device__ __forceinline__ int attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a, uint32_t txn,
                                        bool retry, bool resume, bool may_wait, uint64_t *hi, uint64_t *lo) {
   if constexpr (SCHEME == CC_OCC) {
     const bool precheck = a.precheck == 2 || (a.precheck == 1 && retry);
-    return occ_attempt<L, K, STRICT>(t, s, active, a, precheck, hi, lo);
+    return occ_attempt<L, K, STRICT, LATCH>(t, s, active, a, precheck, hi, lo);
   }
-  else if constexpr (SCHEME == CC_2PL_NW) return tpl_attempt<L, K, STRICT>(t, s, active, a, txn, hi, lo);
+  else if constexpr (SCHEME == CC_2PL_NW) return tpl_attempt<L, K, STRICT, LATCH>(t, s, active, a, txn, hi, lo);
   else if constexpr (SCHEME == CC_2PL_WD)
-    return tplwd_attempt<L, K, STRICT>(t, s, active, a, txn, resume, may_wait, hi, lo);
-  else if constexpr (SCHEME == CC_TO) return to_attempt<L, K, STRICT, false>(t, s, active, a, hi, lo);
-  else if constexpr (SCHEME == CC_MVCC) return to_attempt<L, K, STRICT, true>(t, s, active, a, hi, lo);
-  else return tictoc_attempt<L, K, STRICT>(t, s, active, a, hi, lo);
+    return tplwd_attempt<L, K, STRICT, LATCH>(t, s, active, a, txn, resume, may_wait, hi, lo);
+  else if constexpr (SCHEME == CC_TO) return to_attempt<L, K, STRICT, false, LATCH>(t, s, active, a, hi, lo);
+  else if constexpr (SCHEME == CC_MVCC) return to_attempt<L, K, STRICT, true, LATCH>(t, s, active, a, hi, lo);
+  else return tictoc_attempt<L, K, STRICT, LATCH>(t, s, active, a, hi, lo);
 }
 
 // ---------------------------------------------------------------------------
 // Plain batch kernel: persistent teams, in-kernel retry until commit (or
 // deferral to the next, less concurrent pass).
 // ---------------------------------------------------------------------------
-template <int L, int K, int SCHEME, bool STRICT>
+template <int L, int K, int SCHEME, bool STRICT, bool LATCH>
 __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
   Team<L> t;
   Slots<K> s;
@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
     }
     uint64_t key_hi = 0, key_lo = 0;
     s.block = ~0u;
-    const int r = attempt<L, K, SCHEME, STRICT>(t, s, active, a, (uint32_t)(txn < 0 ? 0 : txn), attempts >= 2,
+    const int r = attempt<L, K, SCHEME, STRICT, LATCH>(t, s, active, a, (uint32_t)(txn < 0 ? 0 : txn), attempts >= 2,
                                                 keep, waits < a.wd_wait_limit, &key_hi, &key_lo);
     if (t.tl == 0 && txn >= 0) {
       const uint64_t dt = wall_clock64() - now;
@@ -268,11 +268,11 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// dispatch over (lanes per txn, ops per lane, strict)
+// dispatch over (lanes per txn, ops per lane, strict, latch)
 // ---------------------------------------------------------------------------
-template <int L, int K, int SCHEME, bool STRICT>
+template <int L, int K, int SCHEME, bool STRICT, bool LATCH>
 static hipError_t launch_one(hipStream_t s, int waves_per_wg, int grid, const RunArgs &a, int n_cu, int *grid_used) {
-  auto kern = txn_kernel<L, K, SCHEME, STRICT>;
+  auto kern = txn_kernel<L, K, SCHEME, STRICT, LATCH>;
   const int block = 64 * waves_per_wg;
   if (block > MaxThreads<K>::value) return hipErrorInvalidConfiguration;
   if (grid <= 0) {
@@ -294,13 +294,13 @@ static hipError_t launch_one(hipStream_t s, int waves_per_wg, int grid, const Ru
   return hipGetLastError();
 }
 
-template <int SCHEME, bool STRICT>
+template <int SCHEME, bool STRICT, bool LATCH>
 static hipError_t dispatch(hipStream_t s, int lanes, int max_ops, int waves_per_wg, int grid, const RunArgs &a,
                            int n_cu, int *grid_used) {
   const int need_k = (max_ops + lanes - 1) / lanes;
 #define CCE_TRY(LL, KK)                                                                      \
   if (lanes == LL && need_k <= KK)                                                           \
-    return launch_one<LL, KK, SCHEME, STRICT>(s, waves_per_wg, grid, a, n_cu, grid_used);
+    return launch_one<LL, KK, SCHEME, STRICT, LATCH>(s, waves_per_wg, grid, a, n_cu, grid_used);
   CCE_TRY(1, 4)
   CCE_TRY(1, 16)
   CCE_TRY(4, 4)

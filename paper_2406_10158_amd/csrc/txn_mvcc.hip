@@ -1,12 +1,16 @@
-// Instantiation of the transaction kernel for one scheme (CC_MVCC).
+// Instantiation of the transaction kernel for one scheme (CC_MVCC), with
+// latch-free or latched control-word updates.
 #include "txn_kernel.h"
 
 namespace cce {
 
-hipError_t launch_txn_mvcc(hipStream_t s, int lanes, int max_ops, int waves_per_wg, int grid, bool strict,
-                      const RunArgs &a, int n_cu, int *grid_used) {
-  return strict ? dispatch<CC_MVCC, true>(s, lanes, max_ops, waves_per_wg, grid, a, n_cu, grid_used)
-                : dispatch<CC_MVCC, false>(s, lanes, max_ops, waves_per_wg, grid, a, n_cu, grid_used);
+hipError_t launch_txn_mvcc(hipStream_t s, int lanes, int max_ops, int waves_per_wg, int grid, bool strict, bool latch,
+                          const RunArgs &a, int n_cu, int *grid_used) {
+  if (latch)
+    return strict ? dispatch<CC_MVCC, true, true>(s, lanes, max_ops, waves_per_wg, grid, a, n_cu, grid_used)
+                  : dispatch<CC_MVCC, false, true>(s, lanes, max_ops, waves_per_wg, grid, a, n_cu, grid_used);
+  return strict ? dispatch<CC_MVCC, true, false>(s, lanes, max_ops, waves_per_wg, grid, a, n_cu, grid_used)
+                : dispatch<CC_MVCC, false, false>(s, lanes, max_ops, waves_per_wg, grid, a, n_cu, grid_used);
 }
 
 }  // namespace cce

@@ -1,12 +1,16 @@
-// Instantiation of the transaction kernel for one scheme (CC_TICTOC).
+// Instantiation of the transaction kernel for one scheme (CC_TICTOC), with
+// latch-free or latched control-word updates.
 #include "txn_kernel.h"
 
 namespace cce {
 
-hipError_t launch_txn_tictoc(hipStream_t s, int lanes, int max_ops, int waves_per_wg, int grid, bool strict,
-                      const RunArgs &a, int n_cu, int *grid_used) {
-  return strict ? dispatch<CC_TICTOC, true>(s, lanes, max_ops, waves_per_wg, grid, a, n_cu, grid_used)
-                : dispatch<CC_TICTOC, false>(s, lanes, max_ops, waves_per_wg, grid, a, n_cu, grid_used);
+hipError_t launch_txn_tictoc(hipStream_t s, int lanes, int max_ops, int waves_per_wg, int grid, bool strict, bool latch,
+                            const RunArgs &a, int n_cu, int *grid_used) {
+  if (latch)
+    return strict ? dispatch<CC_TICTOC, true, true>(s, lanes, max_ops, waves_per_wg, grid, a, n_cu, grid_used)
+                  : dispatch<CC_TICTOC, false, true>(s, lanes, max_ops, waves_per_wg, grid, a, n_cu, grid_used);
+  return strict ? dispatch<CC_TICTOC, true, false>(s, lanes, max_ops, waves_per_wg, grid, a, n_cu, grid_used)
+                : dispatch<CC_TICTOC, false, false>(s, lanes, max_ops, waves_per_wg, grid, a, n_cu, grid_used);
 }
 
 }  // namespace cce

@@ -206,6 +206,9 @@ def test_gacco_run_rules():
         with pytest.raises(b_.CCError) as e:
             eng.run(bid, flags=b_.CC_RUN_PRECHECK)
         assert e.value.status == b_.CC_E_INVAL
+        with pytest.raises(b_.CCError) as e:
+            eng.run(bid, flags=b_.CC_RUN_LATCH)  # a deterministic scheme has no latch variant
+        assert e.value.status == b_.CC_E_INVAL
         st = eng.run(bid)  # the batch is still usable after the rejected runs
         assert st["committed"] == b.n_txns
     finally:

@@ -316,3 +316,36 @@ def test_autotuner_picks_a_feasible_point():
         eng.run(bid, **params)
         out, reads = eng.outcomes(bid, b.n_txns, b.total_ops)
         assert check(tabs, b, out, reads, eng.tables()).ok
+
+
+# ---------------------------------------------------------------------------
+# Latch variants (CC_RUN_LATCH): every control-word update becomes a critical
+# section under a per-row 32-bit latch; the outcome must still be serializable.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("scheme", IMPLEMENTED)
+@pytest.mark.parametrize("theta", [0.6, 0.99])
+def test_latch_variants_kv(scheme, theta):
+    b_ = binding()
+    tabs, b = wl.kv_workload(n_rows=20_000, n_fields=4, n_txns=20_000, ops=16, theta=theta, seed=41)
+    run_and_check(tabs, b, scheme, flags=b_.CC_RUN_LATCH)
+
+
+@pytest.mark.parametrize("scheme", IMPLEMENTED)
+def test_latch_variants_hot_rows_order_entry_and_tiny(scheme):
+    b_ = binding()
+    n = 20_000
+    b = wl.kv_batch(2, 1, n, ops=2, read_ratio=0.3, arg_range=(-5, 5), seed=42)
+    run_and_check([wl.kv_table(2, 1)], b, scheme, lanes_per_txn=4, flags=b_.CC_RUN_LATCH)
+    tabs, b = wl.order_entry_workload(1, 1_000, seed=43)
+    run_and_check(tabs, b, scheme, flags=b_.CC_RUN_LATCH | b_.CC_RUN_STRICT_FENCES)
+    for seed in range(4):
+        tabs, b = wl.kv_workload(n_rows=3, n_fields=1, n_txns=7, ops=(1, 3), theta=0.0, seed=200 + seed)
+        out, reads, final, st = run_batch(tabs, b, scheme, lanes_per_txn=1, waves_per_wg=1, flags=b_.CC_RUN_LATCH)
+        assert "error" not in st
+        assert oracle.bruteforce_count(tabs, b, np.arange(b.n_txns), reads, final) >= 1
+
+
+def test_latch_variant_in_epoch_mode():
+    b_ = binding()
+    tabs, b = wl.kv_workload(n_rows=20_000, n_fields=4, n_txns=20_000, ops=(2, 64), theta=0.8, seed=44)
+    run_and_check(tabs, b, "occ", mode=b_.CC_MODE_EPOCH, lanes_per_txn=64, flags=b_.CC_RUN_LATCH)
