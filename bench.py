@@ -200,6 +200,26 @@ def suite_index(args, binding, workload):
         eng.close()
 
 
+def suite_latch(args, binding, workload):
+    """Latch-free (default) against latched control-word updates, every non-deterministic scheme."""
+    for theta in (0.0, 0.6, 0.9):
+        tables, batch = workload.kv_workload(n_rows=args.rows, n_fields=args.fields, n_txns=args.txns,
+                                             ops=args.ops, theta=theta, seed=args.seed)
+        eng = binding.Engine(tables)
+        for scheme in ("occ", "2pl_nw", "2pl_wd", "to", "mvcc", "tictoc"):
+            bid = eng.submit(batch, scheme)
+            for latch in (False, True):
+                rec = {"suite": "latch", "theta": theta, "scheme": scheme, "latch": latch}
+                try:
+                    rec.update(_run_stats(eng, bid, batch.n_txns, steps=1, warmup=1,
+                                          flags=binding.CC_RUN_LATCH if latch else 0))
+                except binding.CCError as e:
+                    rec["error"] = str(e)
+                _emit(rec)
+            eng.release(bid)
+        eng.close()
+
+
 def suite_batching(args, binding, workload):
     """Uneven transactions (2-64 ops), Zipf 0.8: autotuned plain and epoch launches per batch size."""
     from paper_2406_10158_amd import autotune
@@ -279,7 +299,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probes", action="store_true", help="only run the memory micro-benchmarks")
-    ap.add_argument("--suite", choices=["schemes", "order_entry", "batching", "serving", "index"],
+    ap.add_argument("--suite", choices=["schemes", "order_entry", "batching", "serving", "index", "latch"],
                     help="run a measurement suite instead of the headline step (JSON line per point)")
     ap.add_argument("--oe-txns", type=int, default=100_000)
     ap.add_argument("--serve-arrivals", type=int, default=100_000)
@@ -301,6 +321,7 @@ def main():
         return
     if args.suite:
         {"schemes": suite_schemes, "order_entry": suite_order_entry, "batching": suite_batching, "index": suite_index,
+         "latch": suite_latch,
          "serving": suite_serving}[args.suite](args, binding, workload)
         return
 
