@@ -131,6 +131,43 @@ def id_order_expected(tables, batch):
     return serial_execute(tables, batch)
 
 
+def kset_ranks(batch):
+    """GPUTx's rank of every transaction: its K-set (Section 2, "Conflict Graph Ordering").
+
+    Conflicts are read-write, write-read and write-write accesses to the same
+    item by two transactions, ordered by transaction id; they form a DAG, and a
+    transaction's rank is its level in a topological sort of it: one more
+    than the largest rank among the earlier transactions it conflicts with,
+    0 if there are none.  Transactions of one rank never conflict, so a K-set
+    runs without concurrency control, and executing the K-sets in rank order
+    is equivalent to the id-order serial execution.  (Read literally, the
+    per-item rule -- an item's k-th conflicting access gets rank k, the
+    transaction takes its largest -- can put two conflicting transactions in
+    one K-set; the DAG level is the rank that makes K-sets conflict-free.)
+    An item is a (table, row); a transaction writes it if any of its
+    operations on it writes.  Plain Python over the transactions in id order.
+    """
+    item_any = {}    # item -> largest rank of any earlier accessor
+    item_write = {}  # item -> rank of the last earlier writer
+    ranks = np.zeros(batch.n_txns, np.int64)
+    for t in range(batch.n_txns):
+        sl = batch.txn_slice(t)
+        acc = {}
+        for op in range(sl.start, sl.stop):
+            item = (int(batch.table[op]), int(batch.row[op]))
+            acc[item] = acc.get(item, False) or int(batch.kind[op]) != READ
+        r = 0
+        for item, writes in acc.items():
+            before = item_any.get(item, -1) if writes else item_write.get(item, -1)
+            r = max(r, before + 1)
+        ranks[t] = r
+        for item, writes in acc.items():
+            item_any[item] = max(item_any.get(item, -1), r)
+            if writes:
+                item_write[item] = r
+    return ranks
+
+
 def resolve_keys(index_keys, batch, op_keys):
     """Rows that keyed operations name, through each table's index.
 

@@ -336,3 +336,73 @@ def test_resolve_keys_rejects_unknown_keys_and_leaves_unindexed_tables():
     assert rows.tolist() == [1, 2]  # the second op's table has no index: its row stands
     with pytest.raises(KeyError):
         oracle.resolve_keys([keys, None], b, np.array([8, 0], np.int64))
+
+
+# ---------------------------------------------------------------------------
+# GPUTx K-sets: the rank recurrence is pinned against the longest path of an
+# explicitly built conflict DAG, K-sets are checked conflict-free pair by
+# pair, and executing K-sets in rank order (any order inside a K-set) must be
+# the id-order replay.
+# ---------------------------------------------------------------------------
+def _accesses(b, t):
+    acc = {}
+    sl = b.txn_slice(t)
+    for op in range(sl.start, sl.stop):
+        item = (int(b.table[op]), int(b.row[op]))
+        acc[item] = acc.get(item, False) or int(b.kind[op]) != oracle.READ
+    return acc
+
+
+def _conflict(a1, a2):
+    return any(i in a2 and (w or a2[i]) for i, w in a1.items())
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_kset_ranks_are_dag_levels_and_conflict_free(seed):
+    tabs, b = wl.kv_workload(n_rows=40, n_fields=2, n_txns=120, ops=(1, 5), theta=0.8, seed=300 + seed)
+    ranks = oracle.kset_ranks(b)
+    acc = [_accesses(b, t) for t in range(b.n_txns)]
+    # longest path by brute force over all conflicting earlier transactions
+    level = np.zeros(b.n_txns, np.int64)
+    for j in range(b.n_txns):
+        preds = [level[i] + 1 for i in range(j) if _conflict(acc[i], acc[j])]
+        level[j] = max(preds, default=0)
+    assert np.array_equal(ranks, level)
+    for i in range(b.n_txns):
+        for j in range(i + 1, b.n_txns):
+            if ranks[i] == ranks[j]:
+                assert not _conflict(acc[i], acc[j]), (i, j)
+    # rank order, shuffled inside each K-set, replays like the id order
+    rng = np.random.default_rng(seed)
+    order = np.lexsort((rng.permutation(b.n_txns), ranks))
+    f1, r1 = oracle.replay(tabs, b, order)
+    f2, r2 = oracle.id_order_expected(tabs, b)
+    assert np.array_equal(r1, r2) and np.array_equal(f1[0], f2[0])
+
+
+def test_literal_per_item_rank_rule_can_merge_conflicting_transactions():
+    # txn 0 touches x (first on x) and y (third on y): literal rank 2
+    # txn 1 writes x after txn 0 (second on x: rank 1) and z (third on z): literal rank 2
+    # both land in K-set 2 although they conflict on x; the DAG levels differ
+    rows, lengths, kinds = [], [], []
+    def txn(items):
+        lengths.append(len(items))
+        for r, k in items:
+            rows.append(r); kinds.append(k)
+    txn([(9, 1)]); txn([(9, 1)]); txn([(7, 1)]); txn([(7, 1)])   # two writers of y=9, two of z=7
+    txn([(1, 1), (9, 1)])                                          # A: x=1 (first on x), y (third on y)
+    txn([(1, 1), (7, 1)])                                          # B: x after A, z (third on z)
+    n = len(rows)
+    b = wl._pack(lengths, np.array(rows), np.zeros(n, np.int64), np.zeros(n, np.int64), np.array(kinds),
+                 np.ones(n, np.int64), {})
+    ranks = oracle.kset_ranks(b)
+    assert ranks[4] == 2 and ranks[5] == 3  # the DAG levels separate A and B
+    # the literal per-item rule: k-th accessor of an item has rank k; a transaction takes its largest
+    seen, lit = {}, []
+    for t in range(b.n_txns):
+        r = 0
+        for item in _accesses(b, t):
+            r = max(r, seen.get(item, 0))
+            seen[item] = seen.get(item, 0) + 1
+        lit.append(r)
+    assert lit[4] == lit[5] == 2 and _conflict(_accesses(b, 4), _accesses(b, 5))
