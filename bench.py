@@ -138,11 +138,13 @@ def suite_schemes(args, binding, workload):
                                              ops=args.ops, theta=theta, seed=args.seed)
         h = workload.hottest_row_writes(batch)[1]
         eng = binding.Engine(tables)
-        for scheme in ("occ", "2pl_nw", "2pl_wd", "to", "mvcc", "tictoc", "gacco"):
+        for scheme in ("occ", "2pl_nw", "2pl_wd", "to", "mvcc", "tictoc", "gacco", "gputx"):
             bid = eng.submit(batch, scheme)
             rec = {"suite": "schemes", "theta": theta, "scheme": scheme, "hot_row_writes": h}
             try:
                 rec.update(_run_stats(eng, bid, batch.n_txns))
+                if scheme == "gputx":
+                    rec["ksets"] = binding.cc_stats(eng.ctx, bid)["ksets"]
             except binding.CCError as e:
                 rec["error"] = str(e)
             _emit(rec)
@@ -156,7 +158,7 @@ def suite_order_entry(args, binding, workload):
     for w in (1, 8, 64):
         tables, batch = workload.order_entry_workload(w, args.oe_txns, seed=args.seed)
         eng = binding.Engine(tables)
-        for scheme in ("occ", "2pl_nw", "2pl_wd", "to", "mvcc", "tictoc", "gacco"):
+        for scheme in ("occ", "2pl_nw", "2pl_wd", "to", "mvcc", "tictoc", "gacco", "gputx"):
             bid = eng.submit(batch, scheme)
             rec = {"suite": "order_entry", "warehouses": w, "txns": batch.n_txns, "scheme": scheme}
             try:

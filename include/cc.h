@@ -67,12 +67,17 @@ enum cc_scheme {
                     and writes alike.  Deterministic, no aborts.  Needs each transaction's ops
                     after the previous transaction's (first_op nondecreasing) and
                     CC_MODE_PLAIN; accepts only CC_RUN_STRICT_FENCES and CC_RUN_INDEX_TREE. */
-  CC_2PL_WD = 6  /* two-phase locking, wait-die (Section 2 "Two-Phase Locking", Section 3.5): a
+  CC_2PL_WD = 6, /* two-phase locking, wait-die (Section 2 "Two-Phase Locking", Section 3.5): a
                     transaction older than the exclusive holder of a lock it needs keeps its
                     locks and waits (a state of its team, at most 64 times per attempt); any
                     other conflict aborts it.  Age = index in the batch.  Lock word as 2PL. */
+  CC_GPUTX = 7   /* GPUTx, conflict-graph ordering by K-sets (Section 2 and Section 3, "Conflict
+                    Graph Ordering"): a transaction's rank is its level in the DAG of
+                    conflicts ordered by transaction id; the transactions of one rank run
+                    together without concurrency control, rank after rank.  Deterministic, no
+                    aborts.  Same batch and run rules as CC_GACCO. */
 };
-#define CC_N_SCHEMES 7
+#define CC_N_SCHEMES 8
 
 /*
  * Operation kinds.  An operation touches one field of one row.  Its read
@@ -126,7 +131,8 @@ enum cc_txn_status { CC_PENDING = 0, CC_COMMITTED = 1 };
  *                              write locks;
  *   TO, MVCC:  (0, ts)      -- the timestamp of the committing attempt;
  *   TicToc:    (commit_ts, ticket);
- *   GaccO:     (0, transaction index) -- the scheme's order is the id order.
+ *   GaccO:     (0, transaction index) -- the scheme's order is the id order;
+ *   GPUTx:     (rank, transaction index) -- K-set, then id.
  * attempts counts executions of the transaction, so attempts-1 are aborts
  * (the paper's abort rate is aborts / committed, Section 4.1 "Metric
  * Selection").  commit_ns is the device wall-clock time of the commit,
@@ -239,6 +245,7 @@ enum cc_stat {
                               part of CC_STAT_RUN_NS */
   CC_STAT_INDEX_NS = 24,   /* keyed batches: the index lookups, HIP events; part of CC_STAT_RUN_NS */
   CC_STAT_WD_WAITS = 25,   /* CC_2PL_WD: times a transaction kept its locks and waited */
+  CC_STAT_KSETS = 26,      /* CC_GPUTX: K-sets (largest rank + 1) */
   CC_N_STATS = 32
 };
 
@@ -280,8 +287,8 @@ cc_status cc_read_table(cc_ctx *ctx, uint32_t table_id, int64_t *out, int out_on
  * Validate a batch of n_txns transactions over n_ops operations and stage it
  * in device memory for `scheme`.  txns/ops are host arrays (on_device = 0).
  * Errors: CC_E_INVAL (bad scheme/kind, op ranges outside the ops array,
- * WRITE_SLOT source not earlier, too many ops in a txn; for CC_GACCO, a
- * transaction whose first_op is below the previous one's), CC_E_RANGE,
+ * WRITE_SLOT source not earlier, too many ops in a txn; for CC_GACCO and
+ * CC_GPUTX, a transaction whose first_op is below the previous one's), CC_E_RANGE,
  * CC_E_DUPROW.  *batch_id receives a handle valid until cc_release_batch or
  * cc_destroy.  Zero transactions is a valid (empty) batch.
  */
@@ -339,10 +346,11 @@ cc_status cc_check_batch(uint32_t n_tables, const uint64_t *n_rows, const uint32
  * each run applies its writes to the current tables.
  * params may be NULL (all defaults).  Returns CC_E_LIVELOCK if a transaction
  * exhausted max_attempts (its status stays CC_PENDING and it left no writes),
- * CC_E_TS_OVERFLOW if a timestamp field overflowed.  CC_GACCO runs every
- * transaction exactly once after its preprocessing (CC_STAT_PREP_NS); it
- * returns CC_E_LIVELOCK only if a transaction waited more than 4 s for its
- * turn on a row, which a consistent lock table rules out.
+ * CC_E_TS_OVERFLOW if a timestamp field overflowed.  CC_GACCO and CC_GPUTX
+ * run every transaction exactly once after their preprocessing
+ * (CC_STAT_PREP_NS; for GPUTx it includes the rank pass and the sort into
+ * K-sets); they return CC_E_LIVELOCK only if a transaction waited more than
+ * 4 s without progress, which a consistent lock table rules out.
  */
 cc_status cc_run(cc_ctx *ctx, uint64_t batch_id, const cc_run_params *params);
 

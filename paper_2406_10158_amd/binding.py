@@ -24,9 +24,9 @@ lib = ctypes.CDLL(_LIB_PATH)
 CC_OK = 0
 CC_E_INVAL, CC_E_RANGE, CC_E_DUPROW, CC_E_NOMEM, CC_E_TS_OVERFLOW = -1, -2, -3, -4, -5
 CC_E_LIVELOCK, CC_E_HIP, CC_E_NODEV, CC_E_STATE, CC_E_NOBATCH = -6, -7, -8, -9, -10
-CC_OCC, CC_2PL_NW, CC_TO, CC_MVCC, CC_TICTOC, CC_GACCO, CC_2PL_WD = 0, 1, 2, 3, 4, 5, 6
+CC_OCC, CC_2PL_NW, CC_TO, CC_MVCC, CC_TICTOC, CC_GACCO, CC_2PL_WD, CC_GPUTX = 0, 1, 2, 3, 4, 5, 6, 7
 SCHEMES = {"occ": CC_OCC, "2pl_nw": CC_2PL_NW, "to": CC_TO, "mvcc": CC_MVCC, "tictoc": CC_TICTOC,
-           "gacco": CC_GACCO, "2pl_wd": CC_2PL_WD}
+           "gacco": CC_GACCO, "2pl_wd": CC_2PL_WD, "gputx": CC_GPUTX}
 CC_READ, CC_ADD, CC_COND_ADD, CC_WRITE_SLOT = 0, 1, 2, 3
 CC_PENDING, CC_COMMITTED = 0, 1
 CC_MODE_PLAIN, CC_MODE_EPOCH, CC_MODE_SERVE = 0, 1, 2
@@ -41,7 +41,7 @@ CC_RUN_LATCH = 0x40
 STAT_NAMES = ["committed", "attempts", "abort_lock", "abort_valid", "kernel_ns", "run_ns", "tickets",
               "max_attempts", "lat_p50_ns", "lat_p99_ns", "epochs", "passes", "deferred", "grid",
               "t_useful_ns", "t_abort_ns", "t_wait_ns", "gave_up", "admit_waits",
-              "occ_r1_ns", "occ_r2_ns", "occ_r3_ns", "occ_r4_ns", "prep_ns", "index_ns", "wd_waits"]
+              "occ_r1_ns", "occ_r2_ns", "occ_r3_ns", "occ_r4_ns", "prep_ns", "index_ns", "wd_waits", "ksets"]
 CC_N_STATS = 32
 
 OP_DTYPE = np.dtype([("row", "<u4"), ("table", "<u2"), ("field", "u1"), ("kind", "u1"), ("arg", "<i8")])

@@ -38,7 +38,8 @@ struct Batch {
   uint32_t *d_meta = nullptr;    // keyed batches: per-op keyed flag, table, field
   uint32_t *d_rows = nullptr;    // keyed batches: per-op row found by the last run's lookups
   uint32_t *d_rank = nullptr;    // GaccO: per row-group leader, its position in the sorted access table
-  uint32_t *d_gscratch = nullptr;// GaccO: access-table and sort buffers
+  uint32_t *d_gscratch = nullptr;// GaccO, GPUTx: access-table and sort buffers
+  uint32_t *d_tscratch = nullptr;// GPUTx: per-transaction ranks, sort buffers, K-set starts
   int64_t *d_arrival = nullptr;           // serving: arrival ticks per transaction
   std::vector<int64_t> arrival_ns;        // host copy, for latency statistics
   hipGraphExec_t epoch_graph = nullptr;  // captured epochs for the last epoch-mode parameters
@@ -73,6 +74,7 @@ struct cc_ctx {
   std::vector<DevIndex> indexes;      // per table (empty entries: no index)
   IndexDesc *d_idx = nullptr;         // device copy of every table's IndexDesc
   uint32_t *d_latch = nullptr;        // CC_RUN_LATCH: one latch per global row
+  uint64_t *d_kstate = nullptr;       // GPUTx: per-row rank state
   std::map<uint64_t, Batch> batches;
   uint64_t next_batch = 1;
   hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -160,6 +162,8 @@ void free_batch(Batch &b) {
   b.d_rows = nullptr;
   if (b.d_rank) (void)hipFree(b.d_rank);
   if (b.d_gscratch) (void)hipFree(b.d_gscratch);
+  if (b.d_tscratch) (void)hipFree(b.d_tscratch);
+  b.d_tscratch = nullptr;
   b.d_rank = nullptr;
   b.d_gscratch = nullptr;
   if (b.epoch_graph) (void)hipGraphExecDestroy(b.epoch_graph);
@@ -295,6 +299,7 @@ cc_status cc_destroy(cc_ctx *c) {
   }
   if (c->d_idx) (void)hipFree(c->d_idx);
   if (c->d_latch) (void)hipFree(c->d_latch);
+  if (c->d_kstate) (void)hipFree(c->d_kstate);
   if (c->d_data) (void)hipFree(c->d_data);
   if (c->d_words) (void)hipFree(c->d_words);
   if (c->d_aux) (void)hipFree(c->d_aux);
@@ -545,6 +550,107 @@ cc_status run_gacco(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes,
   return CC_OK;
 }
 
+uint64_t gputx_scratch_words(uint64_t n_txns) { return 3 * n_txns + 1 + radix_sort_scratch_words(n_txns); }
+
+// GPUTx run: CC initialisation, [index lookups], preprocessing shared with
+// GaccO, the rank pass, the sort into K-sets, and the K-set-ordered
+// execution.  Every transaction runs exactly once.
+cc_status run_gputx(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes, uint32_t wpw) {
+  if (p.mode != CC_MODE_PLAIN)
+    return fail(c, CC_E_INVAL, "CC_GPUTX runs in CC_MODE_PLAIN only: it orders the whole batch before running it");
+  if (p.flags & ~(CC_RUN_STRICT_FENCES | CC_RUN_INDEX_TREE))
+    return fail(c, CC_E_INVAL, "CC_GPUTX accepts only CC_RUN_STRICT_FENCES and CC_RUN_INDEX_TREE");
+  if (!c->d_kstate) HIP_OR(c, hipMalloc(&c->d_kstate, std::max<uint64_t>(c->total_rows, 1) * sizeof(uint64_t)));
+  const uint64_t n = b.n_txns;
+  uint32_t *txn_rank = b.d_tscratch, *iota = txn_rank + n, *kstart = iota + n, *sort_scratch = kstart + n + 1;
+  GputxArgs a{};
+  a.ops = b.d_ops;
+  a.txns = b.d_txns;
+  a.n_txns = n;
+  a.rank = b.d_rank;
+  a.words = c->d_words;
+  a.kstate = c->d_kstate;
+  a.txn_rank = txn_rank;
+  a.kstart = kstart;
+  a.data = c->d_data;
+  a.out = b.d_out;
+  a.reads = b.d_reads;
+  a.ctl = c->d_ctl;
+  a.wait_limit_ticks = (uint64_t)c->wallclock_khz * GACCO_WAIT_LIMIT_MS;
+  const uint64_t poll_ns = p.backoff_ns ? p.backoff_ns : 200;
+  a.poll_ticks = (uint32_t)std::max<uint64_t>(1, poll_ns * c->wallclock_khz / 1000000ull);
+  a.ns_per_tick_q16 = (uint32_t)((1000000ull << 16) / c->wallclock_khz);
+  a.has_slot = b.has_slot ? 1u : 0u;
+  const bool strict = (p.flags & CC_RUN_STRICT_FENCES) != 0;
+
+  HIP_OR(c, hipEventRecord(c->ev[0], c->stream));
+  HIP_OR(c, launch_init(c->stream, c->d_words, 0, nullptr, 0, b.d_out, n, c->d_ctl, 0));
+  float ms_index = 0;
+  if (b.keyed) {
+    cc_status st = resolve_keys(c, b, p, &ms_index);
+    if (st) return st;
+  }
+  HIP_OR(c, hipEventRecord(c->ev[4], c->stream));
+  HIP_OR(c, gacco_prepare(c->stream, b.d_ops, b.n_ops, (uint32_t)c->total_rows, c->d_words, b.d_rank, b.d_gscratch,
+                          c->d_ctl));
+  int grid_used = 0;
+  if (n) {
+    HIP_OR(c, gputx_init_state(c->stream, c->d_kstate, c->total_rows, iota, n));
+    HIP_OR(c, gputx_reset(c->stream, c->d_ctl));
+    hipError_t e = launch_gputx_pass(c->stream, false, (int)lanes, (int)b.max_ops, (int)wpw, (int)p.grid, strict, a,
+                                     c->n_cu, &grid_used);
+    if (e != hipSuccess) return launch_error(c, e);
+    uint32_t *sk = nullptr, *sv = nullptr;
+    HIP_OR(c, radix_sort_pairs(c->stream, txn_rank, iota, n, 32, sort_scratch, &sk, &sv));
+    HIP_OR(c, gputx_kstart(c->stream, sk, n, kstart));
+    HIP_OR(c, gputx_reset(c->stream, c->d_ctl));
+    a.order = sv;
+    a.order_rank = sk;
+  }
+  HIP_OR(c, hipEventRecord(c->ev[5], c->stream));
+  HIP_OR(c, hipEventRecord(c->ev[1], c->stream));
+  if (n) {
+    hipError_t e = launch_gputx_pass(c->stream, true, (int)lanes, (int)b.max_ops, (int)wpw, (int)p.grid, strict, a,
+                                     c->n_cu, &grid_used);
+    if (e != hipSuccess) return launch_error(c, e);
+  }
+  HIP_OR(c, hipEventRecord(c->ev[2], c->stream));
+  HIP_OR(c, hipEventRecord(c->ev[3], c->stream));
+  HIP_OR(c, hipStreamSynchronize(c->stream));
+  Ctl h{};
+  HIP_OR(c, hipMemcpy(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+  float ms_run = 0, ms_prep = 0, ms_kernel = 0;
+  HIP_OR(c, hipEventElapsedTime(&ms_run, c->ev[0], c->ev[3]));
+  HIP_OR(c, hipEventElapsedTime(&ms_prep, c->ev[4], c->ev[5]));
+  HIP_OR(c, hipEventElapsedTime(&ms_kernel, c->ev[1], c->ev[2]));
+  std::memset(b.stats, 0, sizeof(b.stats));
+  b.stats[CC_STAT_COMMITTED] = h.stats[DS_COMMITTED];
+  b.stats[CC_STAT_ATTEMPTS] = h.stats[DS_ATTEMPTS];
+  b.stats[CC_STAT_KERNEL_NS] = (uint64_t)((double)ms_kernel * 1e6);
+  b.stats[CC_STAT_RUN_NS] = (uint64_t)((double)ms_run * 1e6);
+  b.stats[CC_STAT_PREP_NS] = (uint64_t)((double)ms_prep * 1e6);
+  b.stats[CC_STAT_INDEX_NS] = (uint64_t)((double)ms_index * 1e6);
+  b.stats[CC_STAT_MAX_ATTEMPTS] = h.stats[DS_MAX_ATTEMPTS];
+  b.stats[CC_STAT_PASSES] = n ? 1 : 0;
+  b.stats[CC_STAT_GRID] = (uint64_t)grid_used;
+  const double ns_per_tick = 1e6 / (double)c->wallclock_khz;
+  b.stats[CC_STAT_T_USEFUL_NS] = (uint64_t)((double)h.stats[DS_T_USEFUL] * ns_per_tick);
+  b.stats[CC_STAT_T_WAIT_NS] = (uint64_t)((double)h.stats[DS_T_WAIT] * ns_per_tick);
+  b.ran = true;
+  if (n) {
+    std::vector<cc_outcome> o(n);
+    HIP_OR(c, hipMemcpy(o.data(), b.d_out, n * sizeof(cc_outcome), hipMemcpyDeviceToHost));
+    uint64_t ksets = 0;
+    for (auto &x : o)
+      if (x.status == CC_COMMITTED) ksets = std::max<uint64_t>(ksets, x.serial_hi + 1);
+    b.stats[CC_STAT_KSETS] = ksets;
+    latency_percentiles(o, &b.stats[CC_STAT_LAT_P50_NS], &b.stats[CC_STAT_LAT_P99_NS]);
+  }
+  if (h.stop) return fail(c, CC_E_LIVELOCK, "CC_GPUTX: a transaction waited past the limit");
+  if (h.stats[DS_COMMITTED] != n) return fail(c, CC_E_LIVELOCK, "CC_GPUTX: not every transaction ran");
+  return CC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -563,7 +669,7 @@ cc_status cc_check_batch(uint32_t n_tables, const uint64_t *n_rows, const uint32
   bool ordered = true;
   const cc_status st = validate_and_pack(nullptr, layout_tables(n_tables, n_rows, n_fields), txns, n_txns, ops, n_ops,
                                          nullptr, nullptr, nullptr, nullptr, &ordered);
-  if (st == CC_OK && scheme == CC_GACCO && !ordered) return CC_E_INVAL;
+  if (st == CC_OK && (scheme == CC_GACCO || scheme == CC_GPUTX) && !ordered) return CC_E_INVAL;
   return st;
 }
 
@@ -584,8 +690,10 @@ static cc_status submit_impl(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, con
   cc_status st = validate_and_pack(c, c->tables, txns, n_txns, ops, n_ops, &dops, &dtx, &max_ops, &has_slot, &ordered,
                                    op_keys, op_keys ? &indexed : nullptr);
   if (st) return st;
-  if (scheme == CC_GACCO && !ordered)
-    return fail(c, CC_E_INVAL, "CC_GACCO needs each transaction's ops after the previous transaction's (first_op nondecreasing)");
+  const bool ordered_scheme = scheme == CC_GACCO || scheme == CC_GPUTX;
+  if (ordered_scheme && !ordered)
+    return fail(c, CC_E_INVAL,
+                "CC_GACCO and CC_GPUTX need each transaction's ops after the previous transaction's (first_op nondecreasing)");
   // keyed ops of the transactions (ops no transaction refers to are never looked up)
   std::vector<uint32_t> meta;
   std::vector<uint32_t> rows0;
@@ -619,9 +727,11 @@ static cc_status submit_impl(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, con
       (e = alloc((void **)&b.d_reads, n_ops * sizeof(int64_t))) != hipSuccess ||
       (e = alloc((void **)&b.d_list, n_txns * sizeof(uint32_t))) != hipSuccess ||
       (scheme == CC_MVCC && (e = alloc((void **)&b.d_nodes, n_ops * 3 * sizeof(uint64_t))) != hipSuccess) ||
-      (scheme == CC_GACCO && (e = alloc((void **)&b.d_rank, n_ops * sizeof(uint32_t))) != hipSuccess) ||
-      (scheme == CC_GACCO &&
+      (ordered_scheme && (e = alloc((void **)&b.d_rank, n_ops * sizeof(uint32_t))) != hipSuccess) ||
+      (ordered_scheme &&
        (e = alloc((void **)&b.d_gscratch, gacco_scratch_words(n_ops) * sizeof(uint32_t))) != hipSuccess) ||
+      (scheme == CC_GPUTX &&
+       (e = alloc((void **)&b.d_tscratch, gputx_scratch_words(n_txns) * sizeof(uint32_t))) != hipSuccess) ||
       (keyed && (e = alloc((void **)&b.d_opkeys, n_ops * sizeof(int64_t))) != hipSuccess) ||
       (keyed && (e = alloc((void **)&b.d_meta, n_ops * sizeof(uint32_t))) != hipSuccess) ||
       (keyed && (e = alloc((void **)&b.d_rows, n_ops * sizeof(uint32_t))) != hipSuccess)) {
@@ -779,6 +889,7 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
     return fail(c, CC_E_INVAL, "CC_RUN_WAIT_UNLOCK is disabled (same-wavefront retries can livelock)");
   if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
   if (b.scheme == CC_GACCO) return run_gacco(c, b, p, lanes, wpw);
+  if (b.scheme == CC_GPUTX) return run_gputx(c, b, p, lanes, wpw);
 
   RunArgs a{};
   a.ops = b.d_ops;

@@ -97,7 +97,7 @@ struct Team {
     lane = __lane_id();
     tl = lane & (L - 1);
     tb = lane - tl;
-    tmask = (L == 64 ? ~0ull : ((1ull << L) - 1ull)) << tb;
+    tmask = (L == 64 ? ~0ull : ((1ull << (L & 63)) - 1ull)) << tb;
   }
   // any lane of my team has p
   __device__ __forceinline__ bool any(bool p) const { return (ballot(p) & tmask) != 0; }

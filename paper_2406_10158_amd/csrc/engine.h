@@ -161,11 +161,46 @@ struct GaccoArgs {
 // counters in `words`, per-leader ranks).  `scratch` holds
 // gacco_scratch_words(n_ops) 32-bit words.
 uint64_t gacco_scratch_words(uint64_t n_ops);
+// Stable LSD radix sort (8-bit digits) of n (key, value) pairs on their low
+// `bits` key bits.  keys/vals are sorted through `scratch`
+// (radix_sort_scratch_words(n) words); *keys_out / *vals_out point at the
+// result (the input arrays or the first 2n words of scratch).
+uint64_t radix_sort_scratch_words(uint64_t n);
+hipError_t radix_sort_pairs(hipStream_t s, uint32_t *keys, uint32_t *vals, uint64_t n, int bits, uint32_t *scratch,
+                            uint32_t **keys_out, uint32_t **vals_out);
 hipError_t gacco_prepare(hipStream_t s, const DevOp *ops, uint64_t n_ops, uint32_t sentinel, uint64_t *words,
                          uint32_t *rank, uint32_t *scratch, Ctl *ctl);
 // GaccO execution; hipErrorInvalidValue for an unsupported (lanes, ops per txn).
 hipError_t launch_gacco(hipStream_t s, int lanes, int max_ops, int waves_per_wg, int grid, bool strict,
                         const GaccoArgs &a, int n_cu, int *grid_used);
+
+// Kernel arguments for the GPUTx passes (gputx.hip).
+struct GputxArgs {
+  const DevOp *ops;
+  const DevTxn *txns;
+  uint64_t n_txns;
+  const uint32_t *rank;       // per row-group leader: its place in its row's list (the turn it waits for)
+  uint64_t *words;            // per row: the turn
+  uint64_t *kstate;           // per row: (largest rank + 1 of its accessors so far) << 32 | (last writer's rank + 1)
+  uint32_t *txn_rank;         // rank pass output: per transaction
+  const uint32_t *order;      // execution: transaction at each sorted position
+  const uint32_t *order_rank; // execution: its rank
+  const uint32_t *kstart;     // execution: first sorted position of each rank
+  int64_t *data;
+  DevOutcome *out;
+  int64_t *reads;
+  Ctl *ctl;
+  uint64_t wait_limit_ticks;
+  uint32_t poll_ticks;
+  uint32_t ns_per_tick_q16;
+  uint32_t has_slot;
+  uint32_t pad;
+};
+hipError_t launch_gputx_pass(hipStream_t s, bool exec, int lanes, int max_ops, int waves_per_wg, int grid,
+                             bool strict, const GputxArgs &a, int n_cu, int *grid_used);
+hipError_t gputx_init_state(hipStream_t s, uint64_t *kstate, uint64_t n_rows, uint32_t *iota, uint64_t n_txns);
+hipError_t gputx_reset(hipStream_t s, Ctl *ctl);
+hipError_t gputx_kstart(hipStream_t s, const uint32_t *rank_sorted, uint64_t n, uint32_t *kstart);
 
 // Host-side launchers (kernels.hip).
 hipError_t launch_init(hipStream_t s, uint64_t *words, uint64_t n_words, uint64_t *aux, uint64_t n_aux,

@@ -230,39 +230,52 @@ __global__ void __launch_bounds__(64) gacco_reset_kernel(Ctl *ctl) {
   if (threadIdx.x == 0) ctl->stop = 0;
 }
 
-uint64_t gacco_scratch_words(uint64_t n_ops) {
-  const uint64_t tiles = (n_ops + RS_TILE - 1) / RS_TILE;
+uint64_t radix_sort_scratch_words(uint64_t n);
+uint64_t gacco_scratch_words(uint64_t n_ops) { return 2 * n_ops + radix_sort_scratch_words(n_ops); }
+
+hipError_t radix_sort_pairs(hipStream_t s, uint32_t *keys, uint32_t *vals, uint64_t n, int bits, uint32_t *scratch,
+                            uint32_t **keys_out, uint32_t **vals_out) {
+  const uint64_t tiles = (n + RS_TILE - 1) / RS_TILE;
   const uint64_t m = tiles * RS_RADIX;
   const uint64_t chunks = (m + SCAN_CHUNK - 1) / SCAN_CHUNK;
-  return 4 * n_ops + m + chunks + 1;
+  if (tiles > 0xFFFFFFFFull || chunks > 0xFFFFFFFFull) return hipErrorInvalidValue;
+  uint32_t *ka = keys, *va = vals, *kb = scratch, *vb = kb + n, *hist = vb + n, *partial = hist + m;
+  for (int shift = 0; shift < bits && n; shift += 8) {
+    hipLaunchKernelGGL(rs_hist_kernel, dim3((unsigned)tiles), dim3(RS_THREADS), 0, s, ka, n, shift, hist,
+                       (uint32_t)tiles);
+    hipLaunchKernelGGL(scan_sum_kernel, dim3((unsigned)chunks), dim3(RS_THREADS), 0, s, hist, m, partial);
+    hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(RS_THREADS), 0, s, partial, (uint32_t)chunks);
+    hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)chunks), dim3(RS_THREADS), 0, s, hist, m, partial);
+    hipLaunchKernelGGL(rs_scatter_kernel, dim3((unsigned)tiles), dim3(RS_THREADS), 0, s, ka, va, kb, vb, n, shift,
+                       hist, (uint32_t)tiles);
+    uint32_t *t = ka; ka = kb; kb = t;
+    t = va; va = vb; vb = t;
+  }
+  *keys_out = ka;
+  *vals_out = va;
+  return hipGetLastError();
+}
+
+uint64_t radix_sort_scratch_words(uint64_t n) {
+  const uint64_t tiles = (n + RS_TILE - 1) / RS_TILE;
+  const uint64_t m = tiles * RS_RADIX;
+  const uint64_t chunks = (m + SCAN_CHUNK - 1) / SCAN_CHUNK;
+  return 2 * n + m + chunks + 1;
 }
 
 hipError_t gacco_prepare(hipStream_t s, const DevOp *ops, uint64_t n_ops, uint32_t sentinel, uint64_t *words,
                          uint32_t *rank, uint32_t *scratch, Ctl *ctl) {
   hipLaunchKernelGGL(gacco_reset_kernel, dim3(1), dim3(64), 0, s, ctl);
   if (n_ops == 0) return hipGetLastError();
-  const uint64_t tiles = (n_ops + RS_TILE - 1) / RS_TILE;
-  const uint64_t m = tiles * RS_RADIX;
-  const uint64_t chunks = (m + SCAN_CHUNK - 1) / SCAN_CHUNK;
-  if (tiles > 0xFFFFFFFFull || chunks > 0xFFFFFFFFull) return hipErrorInvalidValue;
-  uint32_t *ka = scratch, *va = ka + n_ops, *kb = va + n_ops, *vb = kb + n_ops;
-  uint32_t *hist = vb + n_ops, *partial = hist + m;
+  uint32_t *ka = scratch, *va = ka + n_ops, *sorted_k = nullptr, *sorted_v = nullptr;
   const unsigned blocks = (unsigned)((n_ops + 255) / 256);
   hipLaunchKernelGGL(gacco_keys_kernel, dim3(blocks), dim3(256), 0, s, ops, n_ops, sentinel, ka, va);
   int bits = 0;
   while (bits < 32 && (sentinel >> bits) != 0) ++bits;
-  for (int shift = 0; shift < bits; shift += 8) {
-    hipLaunchKernelGGL(rs_hist_kernel, dim3((unsigned)tiles), dim3(RS_THREADS), 0, s, ka, n_ops, shift, hist,
-                       (uint32_t)tiles);
-    hipLaunchKernelGGL(scan_sum_kernel, dim3((unsigned)chunks), dim3(RS_THREADS), 0, s, hist, m, partial);
-    hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(RS_THREADS), 0, s, partial, (uint32_t)chunks);
-    hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)chunks), dim3(RS_THREADS), 0, s, hist, m, partial);
-    hipLaunchKernelGGL(rs_scatter_kernel, dim3((unsigned)tiles), dim3(RS_THREADS), 0, s, ka, va, kb, vb, n_ops,
-                       shift, hist, (uint32_t)tiles);
-    uint32_t *t = ka; ka = kb; kb = t;
-    t = va; va = vb; vb = t;
-  }
-  hipLaunchKernelGGL(gacco_lock_table_kernel, dim3(blocks), dim3(256), 0, s, ka, va, n_ops, sentinel, words, rank);
+  hipError_t e = radix_sort_pairs(s, ka, va, n_ops, bits, va + n_ops, &sorted_k, &sorted_v);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gacco_lock_table_kernel, dim3(blocks), dim3(256), 0, s, sorted_k, sorted_v, n_ops, sentinel,
+                     words, rank);
   return hipGetLastError();
 }
 

@@ -94,7 +94,7 @@ def test_check_batch_statuses(b, case, status):
 
 def test_check_batch_structural_errors(b):
     txns, ops = _batch(rows=[1, 2, 3])
-    assert b.cc_check_batch(SHAPES, txns, ops, 7) == b.CC_E_INVAL         # unknown scheme
+    assert b.cc_check_batch(SHAPES, txns, ops, b.CC_GPUTX + 1) == b.CC_E_INVAL  # unknown scheme
     t2 = txns.copy(); t2["n_ops"] = 4
     assert b.cc_check_batch(SHAPES, t2, ops, 0) == b.CC_E_INVAL           # op range past the end
     t3 = np.concatenate([txns, txns])
@@ -119,10 +119,11 @@ def test_check_batch_gacco_needs_transactions_in_op_order(b):
     two["first_op"] = [2, 0]
     two["n_ops"] = [2, 2]
     assert b.cc_check_batch(SHAPES, two, ops, b.CC_GACCO) == b.CC_E_INVAL
+    assert b.cc_check_batch(SHAPES, two, ops, b.CC_GPUTX) == b.CC_E_INVAL  # GPUTx has the same rule
     assert b.cc_check_batch(SHAPES, two, ops, b.CC_OCC) == 0
     two["first_op"] = [0, 2]
     assert b.cc_check_batch(SHAPES, two, ops, b.CC_GACCO) == 0
-    assert b.cc_check_batch(SHAPES, two, ops, b.CC_2PL_WD + 1) == b.CC_E_INVAL  # one past the last scheme
+    assert b.cc_check_batch(SHAPES, two, ops, b.CC_GPUTX + 1) == b.CC_E_INVAL  # one past the last scheme
 
 
 def test_check_batch_accepts_generated_workloads(b):

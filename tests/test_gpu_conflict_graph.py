@@ -1,10 +1,11 @@
-"""GaccO (conflict-graph ordering) on the GPU.
+"""The conflict-graph-ordering schemes on the GPU: GaccO and GPUTx.
 
-The scheme is deterministic: its serial order is the transaction-id order, so
-every run is compared element by element with the oracle's id-order replay
+Both are deterministic and equivalent to the transaction-id order, so every
+run is compared element by element with the oracle's id-order replay
 (``oracle.id_order_expected``): every read value, every cell of the final
 tables, and the outcome records (all committed, one attempt each, serial key
-(0, id)).  Cases cover the preprocessing (radix sort passes from 1 to 4,
+(0, id) for GaccO and (K-set rank, id) for GPUTx, the ranks equal to
+``oracle.kset_ranks``).  Cases cover the preprocessing (radix sort passes from 1 to 4,
 ragged sort tiles, operations no transaction uses), the execution (lane
 shapes including multi-word operation sets, grids, strict fences, one hot
 row, row groups and slot writes of the order-entry workload) and the run
@@ -25,14 +26,22 @@ def _announce(request):
     print(f"\n[gpu] module {request.module.__name__}", flush=True)
 
 
-def run_exact(tabs, b, **params):
-    out, reads, final, st = run_batch(tabs, b, "gacco", **params)
+DETERMINISTIC = ["gacco", "gputx"]
+
+
+def run_exact(tabs, b, scheme="gacco", **params):
+    out, reads, final, st = run_batch(tabs, b, scheme, **params)
     assert "error" not in st, st["error"]
     exp_fin, exp_reads = oracle.id_order_expected(tabs, b)
     n = b.n_txns
     assert np.all(out["status"] == oracle.COMMITTED)
     assert np.all(out["attempts"] == 1)
-    assert np.all(out["serial_hi"] == 0)
+    if scheme == "gacco":
+        assert np.all(out["serial_hi"] == 0)
+    else:
+        ranks = oracle.kset_ranks(b)
+        assert np.array_equal(out["serial_hi"].astype(np.int64), ranks)
+        assert st["ksets"] == (int(ranks.max()) + 1 if n else 0)
     assert np.array_equal(out["serial_lo"].astype(np.int64), np.arange(n))
     bad = np.nonzero(np.asarray(reads, np.int64) != exp_reads)[0]
     assert len(bad) == 0, f"{len(bad)} read values differ, first ops {bad[:5].tolist()}"
@@ -43,32 +52,37 @@ def run_exact(tabs, b, **params):
     return out, reads, final, st
 
 
-def test_gacco_tiny_config():
+@pytest.mark.parametrize("scheme", DETERMINISTIC)
+def test_cg_tiny_config(scheme):
     tabs, b = wl.tiny_workload(seed=0)
-    run_exact(tabs, b)
+    run_exact(tabs, b, scheme=scheme)
 
 
 @pytest.mark.parametrize("theta", [0.0, 0.6, 0.9, 0.99])
-def test_gacco_kv(theta):
+@pytest.mark.parametrize("scheme", DETERMINISTIC)
+def test_cg_kv(scheme, theta):
     tabs, b = wl.kv_workload(n_rows=200_000, n_fields=10, n_txns=30_001, ops=16, theta=theta, seed=1)
-    out, reads, final, st = run_exact(tabs, b)
-    print(f"gacco theta={theta}: prep_ms={st['prep_ns']/1e6:.3f} kernel_ms={st['kernel_ns']/1e6:.3f}")
+    out, reads, final, st = run_exact(tabs, b, scheme=scheme)
+    print(f"{scheme} theta={theta}: prep_ms={st['prep_ns']/1e6:.3f} kernel_ms={st['kernel_ns']/1e6:.3f}")
 
 
 @pytest.mark.parametrize("lanes,waves", [(1, 1), (1, 4), (4, 2), (4, 4), (16, 1), (16, 8), (64, 1), (64, 16)])
-def test_gacco_launch_shapes(lanes, waves):
+@pytest.mark.parametrize("scheme", DETERMINISTIC)
+def test_cg_launch_shapes(scheme, lanes, waves):
     ops = (1, 16) if lanes == 1 else (2, 64)
     tabs, b = wl.kv_workload(n_rows=5_000, n_fields=4, n_txns=7_777, ops=ops, theta=0.9, seed=lanes * 31 + waves)
-    run_exact(tabs, b, lanes_per_txn=lanes, waves_per_wg=waves)
+    run_exact(tabs, b, lanes_per_txn=lanes, waves_per_wg=waves, scheme=scheme)
 
 
-def test_gacco_grid_sizes():
+@pytest.mark.parametrize("scheme", DETERMINISTIC)
+def test_cg_grid_sizes(scheme):
     tabs, b = wl.kv_workload(n_rows=2_000, n_fields=2, n_txns=5_000, ops=8, theta=0.99, seed=2)
     for grid in (1, 3, 64, 4096):
-        run_exact(tabs, b, grid=grid, waves_per_wg=2)
+        run_exact(tabs, b, grid=grid, waves_per_wg=2, scheme=scheme)
 
 
-def test_gacco_one_row_in_every_transaction():
+@pytest.mark.parametrize("scheme", DETERMINISTIC)
+def test_cg_one_row_in_every_transaction(scheme):
     # every transaction touches row 0 (read or add) and three random rows: row
     # 0's chain is the whole batch, handed over 20k times in id order
     n = 20_000
@@ -80,34 +94,37 @@ def test_gacco_one_row_in_every_transaction():
     rows[:, 0] = 0
     assert all(len(set(r)) == 4 for r in rows.tolist())
     tabs = [wl.kv_table(1_000, 2)]
-    run_exact(tabs, b, lanes_per_txn=4)
+    run_exact(tabs, b, lanes_per_txn=4, scheme=scheme)
 
 
-def test_gacco_edge_sizes():
+@pytest.mark.parametrize("scheme", DETERMINISTIC)
+def test_cg_edge_sizes(scheme):
     tabs = [wl.kv_table(64, 2)]
     b0 = wl.kv_batch(64, 2, 0, ops=4, seed=0)
-    out, reads, final, st = run_batch(tabs, b0, "gacco")
+    out, reads, final, st = run_batch(tabs, b0, scheme)
     assert "error" not in st and st["committed"] == 0 and np.array_equal(final[0], tabs[0])
-    run_exact(tabs, wl.kv_batch(64, 2, 1, ops=5, seed=1))
+    run_exact(tabs, wl.kv_batch(64, 2, 1, ops=5, seed=1), scheme=scheme)
     b2 = wl.kv_batch(64, 2, 50, ops=(0, 3), seed=2)
     assert (b2.n_ops == 0).any()
-    run_exact(tabs, b2)
+    run_exact(tabs, b2, scheme=scheme)
     # transactions longer than 64 operations: operation sets span several words
     tabs3 = [wl.kv_table(4_000, 1)]
     b3 = wl.kv_batch(4_000, 1, 40, ops=(1, 256), theta=0.6, seed=3)
     assert b3.n_ops.max() > 192
-    run_exact(tabs3, b3, lanes_per_txn=64, waves_per_wg=2)
+    run_exact(tabs3, b3, lanes_per_txn=64, waves_per_wg=2, scheme=scheme)
 
 
 @pytest.mark.parametrize("n_rows,n_ops", [(200, 3 * 4096 + 17), (60_000, 4096 - 3), (70_000, 5 * 4096 + 1)])
-def test_gacco_sort_tiles_and_passes(n_rows, n_ops):
+@pytest.mark.parametrize("scheme", DETERMINISTIC)
+def test_cg_sort_tiles_and_passes(scheme, n_rows, n_ops):
     # 1 or 3 radix passes (row ids below 2^8 / 2^24), ragged last sort tile
     ops = 4
     b = wl.kv_batch(n_rows, 1, (n_ops + ops - 1) // ops, ops=ops, theta=0.9, seed=n_ops)
-    run_exact([wl.kv_table(n_rows, 1)], b)
+    run_exact([wl.kv_table(n_rows, 1)], b, scheme=scheme)
 
 
-def test_gacco_four_sort_passes():
+@pytest.mark.parametrize("scheme", DETERMINISTIC)
+def test_cg_four_sort_passes(scheme):
     # total rows beyond 2^24 need a fourth 8-bit digit; the accessed rows sit
     # on both sides of 2^24
     n_rows = (1 << 24) + 1000
@@ -124,10 +141,11 @@ def test_gacco_four_sort_passes():
             while len(set(r.tolist())) < ops:
                 r = rng.integers(0, n_rows, ops)
             b.row[s] = r
-    run_exact([np.zeros((n_rows, 1), np.int64)], b)
+    run_exact([np.zeros((n_rows, 1), np.int64)], b, scheme=scheme)
 
 
-def test_gacco_unused_ops_stay_out_of_the_access_table():
+@pytest.mark.parametrize("scheme", DETERMINISTIC)
+def test_cg_unused_ops_stay_out_of_the_access_table(scheme):
     # ops no transaction refers to (gaps in the ops array) must not hold a turn
     b_ = binding()
     tabs = [wl.kv_table(100, 1)]
@@ -142,7 +160,7 @@ def test_gacco_unused_ops_stay_out_of_the_access_table():
         txns2["first_op"][t] = s + t
     eng = b_.Engine(tabs)
     try:
-        bid = b_.cc_submit_batch(eng.ctx, txns2, ops2, b_.CC_GACCO)
+        bid = b_.cc_submit_batch(eng.ctx, txns2, ops2, b_.SCHEMES[scheme])
         st = eng.run(bid)
         out, reads = eng.outcomes(bid, b.n_txns, len(ops2))
         final = eng.tables()
@@ -157,31 +175,35 @@ def test_gacco_unused_ops_stay_out_of_the_access_table():
 
 
 @pytest.mark.parametrize("warehouses", [1, 8])
-def test_gacco_order_entry(warehouses):
+@pytest.mark.parametrize("scheme", DETERMINISTIC)
+def test_cg_order_entry(scheme, warehouses):
     tabs, b = wl.order_entry_workload(warehouses, 4_000, seed=warehouses)
-    out, reads, final, st = run_exact(tabs, b)
+    out, reads, final, st = run_exact(tabs, b, scheme=scheme)
     assert oracle.order_entry_invariants(tabs, final, b, np.ones(b.n_txns, bool)) == []
 
 
-def test_gacco_uneven_batch_shapes():
+@pytest.mark.parametrize("scheme", DETERMINISTIC)
+def test_cg_uneven_batch_shapes(scheme):
     # the batching workload's shape: 2..64 ops per transaction, Zipf 0.8
     tabs, b = wl.kv_workload(n_rows=100_000, n_fields=10, n_txns=16_384, ops=(2, 64), theta=0.8, seed=12)
     for lanes in (4, 16, 64):
-        run_exact(tabs, b, lanes_per_txn=lanes)
+        run_exact(tabs, b, lanes_per_txn=lanes, scheme=scheme)
 
 
-def test_gacco_strict_fences():
+@pytest.mark.parametrize("scheme", DETERMINISTIC)
+def test_cg_strict_fences(scheme):
     b_ = binding()
     tabs, b = wl.kv_workload(n_rows=20_000, n_fields=4, n_txns=20_000, ops=16, theta=0.99, seed=7)
-    run_exact(tabs, b, flags=b_.CC_RUN_STRICT_FENCES)
+    run_exact(tabs, b, flags=b_.CC_RUN_STRICT_FENCES, scheme=scheme)
 
 
-def test_gacco_repeated_runs_accumulate():
+@pytest.mark.parametrize("scheme", DETERMINISTIC)
+def test_cg_repeated_runs_accumulate(scheme):
     b_ = binding()
     tabs, b = wl.kv_workload(n_rows=5_000, n_fields=2, n_txns=3_000, ops=8, theta=0.9, seed=8)
     eng = b_.Engine(tabs)
     try:
-        bid = eng.submit(b, "gacco")
+        bid = eng.submit(b, scheme)
         eng.run(bid)
         eng.run(bid)
         out, reads = eng.outcomes(bid, b.n_txns, b.total_ops)
@@ -194,12 +216,13 @@ def test_gacco_repeated_runs_accumulate():
     assert np.array_equal(final[0], exp_fin[0])
 
 
-def test_gacco_run_rules():
+@pytest.mark.parametrize("scheme", DETERMINISTIC)
+def test_cg_run_rules(scheme):
     b_ = binding()
     tabs, b = wl.kv_workload(n_rows=1_000, n_fields=2, n_txns=500, ops=4, theta=0.5, seed=10)
     eng = b_.Engine(tabs)
     try:
-        bid = eng.submit(b, "gacco")
+        bid = eng.submit(b, scheme)
         with pytest.raises(b_.CCError) as e:
             eng.run(bid, mode=b_.CC_MODE_EPOCH)
         assert e.value.status == b_.CC_E_INVAL
@@ -215,8 +238,9 @@ def test_gacco_run_rules():
         eng.close()
 
 
-def test_gacco_full_size_kv_config():
+@pytest.mark.parametrize("scheme", DETERMINISTIC)
+def test_cg_full_size_kv_config(scheme):
     tabs, b = wl.kv_workload(seed=0)
-    out, reads, final, st = run_exact(tabs, b)
-    print(f"gacco full: run_ms={st['run_ns']/1e6:.1f} prep_ms={st['prep_ns']/1e6:.2f} "
+    out, reads, final, st = run_exact(tabs, b, scheme=scheme)
+    print(f"{scheme} full: run_ms={st['run_ns']/1e6:.1f} prep_ms={st['prep_ns']/1e6:.2f} "
           f"kernel_ms={st['kernel_ns']/1e6:.1f}")

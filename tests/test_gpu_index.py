@@ -16,7 +16,7 @@ from paper_2406_10158_amd import workload as wl
 
 pytestmark = pytest.mark.gpu
 
-ALL = SCHEMES + ["gacco"]
+ALL = SCHEMES + ["gacco", "gputx"]
 METHODS = {"bsearch": 0, "tree": None}  # None: CC_RUN_INDEX_TREE
 
 
@@ -52,7 +52,7 @@ def check_keyed(tabs, b, keys_by_table, scheme, method, **params):
     bad = np.nonzero(rows.astype(np.int64) != exp_rows)[0]
     assert len(bad) == 0, f"{len(bad)} lookups differ, first ops {bad[:5].tolist()}"
     rb = oracle.with_rows(b, exp_rows)
-    if scheme == "gacco":
+    if scheme in ("gacco", "gputx"):
         exp_fin, exp_reads = oracle.id_order_expected(tabs, rb)
         assert np.array_equal(reads, exp_reads)
         assert all(np.array_equal(g, e) for g, e in zip(final, exp_fin))
@@ -138,7 +138,7 @@ def test_keyed_submission_rules():
             eng.create_index(0, k2)
 
 
-@pytest.mark.parametrize("scheme", ["occ", "2pl_nw", "gacco"])
+@pytest.mark.parametrize("scheme", ["occ", "2pl_nw", "gacco", "gputx"])
 def test_keyed_order_entry_with_an_index_on_customers(scheme):
     tabs, b = wl.order_entry_workload(8, 3_000, seed=7)
     keys = [None] * len(tabs)
