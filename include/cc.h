@@ -66,7 +66,8 @@ enum cc_scheme {
                     a lock table; each row is then handed to its accessors in that order, reads
                     and writes alike.  Deterministic, no aborts.  Needs each transaction's ops
                     after the previous transaction's (first_op nondecreasing) and
-                    CC_MODE_PLAIN; accepts only CC_RUN_STRICT_FENCES and CC_RUN_INDEX_TREE. */
+                    CC_MODE_PLAIN; accepts only CC_RUN_STRICT_FENCES, CC_RUN_INDEX_TREE and
+                    CC_RUN_SHARED_READS. */
   CC_2PL_WD = 6, /* two-phase locking, wait-die (Section 2 "Two-Phase Locking", Section 3.5): a
                     transaction older than the exclusive holder of a lock it needs keeps its
                     locks and waits (a state of its team, at most 64 times per attempt); any
@@ -191,6 +192,9 @@ enum cc_mode { CC_MODE_PLAIN = 0, CC_MODE_EPOCH = 1, CC_MODE_SERVE = 2 };
                                      Exp-7): a 32-bit latch per row guards its control word, and every
                                      update of the word is a critical section [latch, load, store,
                                      unlatch] instead of one 64-bit atomic.  Not for CC_GACCO. */
+#define CC_RUN_SHARED_READS 0x80u /* CC_GACCO: reads of a row between two of its writes run together (a
+                                     write still waits for every earlier access, a read for every
+                                     earlier write); the paper's GaccO queues reads like writes */
 #define CC_RUN_INDEX_TREE 0x20u   /* keyed batches: look keys up by descending the index's 16-way tree
                                      (one 128-byte node per level) instead of by binary search of the
                                      sorted keys */

@@ -38,6 +38,7 @@ CC_RUN_PRECHECK = 0x8
 CC_RUN_NO_PRECHECK = 0x10
 CC_RUN_INDEX_TREE = 0x20
 CC_RUN_LATCH = 0x40
+CC_RUN_SHARED_READS = 0x80
 STAT_NAMES = ["committed", "attempts", "abort_lock", "abort_valid", "kernel_ns", "run_ns", "tickets",
               "max_attempts", "lat_p50_ns", "lat_p99_ns", "epochs", "passes", "deferred", "grid",
               "t_useful_ns", "t_abort_ns", "t_wait_ns", "gave_up", "admit_waits",

@@ -479,8 +479,8 @@ cc_status run_gacco(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes,
     return fail(c, CC_E_INVAL,
                 "CC_GACCO runs in CC_MODE_PLAIN only: it never aborts, so epochs have nothing to retry, and it "
                 "orders the whole batch before running it");
-  if (p.flags & ~(CC_RUN_STRICT_FENCES | CC_RUN_INDEX_TREE))
-    return fail(c, CC_E_INVAL, "CC_GACCO accepts only CC_RUN_STRICT_FENCES and CC_RUN_INDEX_TREE");
+  if (p.flags & ~(CC_RUN_STRICT_FENCES | CC_RUN_INDEX_TREE | CC_RUN_SHARED_READS))
+    return fail(c, CC_E_INVAL, "CC_GACCO accepts only CC_RUN_STRICT_FENCES, CC_RUN_INDEX_TREE and CC_RUN_SHARED_READS");
   GaccoArgs a{};
   a.ops = b.d_ops;
   a.txns = b.d_txns;
@@ -496,6 +496,7 @@ cc_status run_gacco(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes,
   a.poll_ticks = (uint32_t)std::max<uint64_t>(1, poll_ns * c->wallclock_khz / 1000000ull);
   a.ns_per_tick_q16 = (uint32_t)((1000000ull << 16) / c->wallclock_khz);
   a.has_slot = b.has_slot ? 1u : 0u;
+  a.shared = (p.flags & CC_RUN_SHARED_READS) ? 1u : 0u;
   const bool strict = (p.flags & CC_RUN_STRICT_FENCES) != 0;
 
   HIP_OR(c, hipEventRecord(c->ev[0], c->stream));
@@ -508,7 +509,7 @@ cc_status run_gacco(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes,
   }
   HIP_OR(c, hipEventRecord(c->ev[4], c->stream));
   HIP_OR(c, gacco_prepare(c->stream, b.d_ops, b.n_ops, (uint32_t)c->total_rows, c->d_words, b.d_rank, b.d_gscratch,
-                          c->d_ctl));
+                          c->d_ctl, a.shared != 0));
   HIP_OR(c, hipEventRecord(c->ev[5], c->stream));
   HIP_OR(c, hipEventRecord(c->ev[1], c->stream));
   int grid_used = 0;
@@ -592,7 +593,7 @@ cc_status run_gputx(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes,
   }
   HIP_OR(c, hipEventRecord(c->ev[4], c->stream));
   HIP_OR(c, gacco_prepare(c->stream, b.d_ops, b.n_ops, (uint32_t)c->total_rows, c->d_words, b.d_rank, b.d_gscratch,
-                          c->d_ctl));
+                          c->d_ctl, false));
   int grid_used = 0;
   if (n) {
     HIP_OR(c, gputx_init_state(c->stream, c->d_kstate, c->total_rows, iota, n));
@@ -879,8 +880,10 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   const uint32_t wpw = p.waves_per_wg ? p.waves_per_wg : 1;
   if (wpw < 1 || wpw > 16) return fail(c, CC_E_INVAL, "waves_per_wg must be 1..16");
   if (p.flags & ~(CC_RUN_STRICT_FENCES | CC_RUN_EAGER_INSTALL | CC_RUN_WAIT_UNLOCK | CC_RUN_PRECHECK |
-                  CC_RUN_NO_PRECHECK | CC_RUN_INDEX_TREE | CC_RUN_LATCH))
+                  CC_RUN_NO_PRECHECK | CC_RUN_INDEX_TREE | CC_RUN_LATCH | CC_RUN_SHARED_READS))
     return fail(c, CC_E_INVAL, "unknown run flag");
+  if ((p.flags & CC_RUN_SHARED_READS) && b.scheme != CC_GACCO)
+    return fail(c, CC_E_INVAL, "CC_RUN_SHARED_READS is a CC_GACCO option");
   if (p.flags & CC_RUN_WAIT_UNLOCK)
     // Switched off: two teams of one wavefront that block each other both see
     // the row free on their next loop iteration (each attempt releases its

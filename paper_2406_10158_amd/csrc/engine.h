@@ -153,7 +153,7 @@ struct GaccoArgs {
   uint32_t poll_ticks;        // sleep per access queued ahead of the team on a row, wall-clock ticks
   uint32_t ns_per_tick_q16;
   uint32_t has_slot;
-  uint32_t pad;
+  uint32_t shared;            // CC_RUN_SHARED_READS: counters instead of turns (see gacco_prepare)
 };
 
 // GaccO preprocessing (gacco.hip): clears ctl->stop, then builds the access
@@ -168,8 +168,11 @@ uint64_t gacco_scratch_words(uint64_t n_ops);
 uint64_t radix_sort_scratch_words(uint64_t n);
 hipError_t radix_sort_pairs(hipStream_t s, uint32_t *keys, uint32_t *vals, uint64_t n, int bits, uint32_t *scratch,
                             uint32_t **keys_out, uint32_t **vals_out);
+// With `shared`, the words hold (accesses done, writes done) counters and a
+// leader's rank is its threshold: accesses before it in its row for a write,
+// writes before it for a read (reads between two writes share the row).
 hipError_t gacco_prepare(hipStream_t s, const DevOp *ops, uint64_t n_ops, uint32_t sentinel, uint64_t *words,
-                         uint32_t *rank, uint32_t *scratch, Ctl *ctl);
+                         uint32_t *rank, uint32_t *scratch, Ctl *ctl, bool shared);
 // GaccO execution; hipErrorInvalidValue for an unsupported (lanes, ops per txn).
 hipError_t launch_gacco(hipStream_t s, int lanes, int max_ops, int waves_per_wg, int grid, bool strict,
                         const GaccoArgs &a, int n_cu, int *grid_used);

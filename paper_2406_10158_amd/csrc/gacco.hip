@@ -226,6 +226,56 @@ __global__ void __launch_bounds__(256) gacco_lock_table_kernel(const uint32_t *k
   rank[v] = (uint32_t)i;
 }
 
+
+// Shared reads (CC_RUN_SHARED_READS): each row's word holds two counters,
+// accesses done (high 32 bits) and writes done (low 32 bits).  A write waits
+// until every earlier access of its row is done, a read only until every
+// earlier write is; the reads between two writes run together.
+// First pass: write flags of the sorted accesses, and each row's start.
+__global__ void __launch_bounds__(256) gacco_shared_flags_kernel(const uint32_t *keys, const uint32_t *vals,
+                                                                 uint64_t n, uint32_t sentinel, const DevOp *ops,
+                                                                 uint64_t *words, uint32_t *wflag) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t k = keys[i], v = vals[i];
+  const bool real = k < sentinel && v < n;
+  wflag[i] = (real && op_written(ops[v].rowk)) ? 1u : 0u;
+  if (real && (i == 0 || keys[i - 1] != k)) words[k] = i;  // the row's first position, for the next pass
+}
+
+// Second pass (after an exclusive scan turned the flags into "writes before
+// position i"): each leader's threshold -- accesses before it in its row for
+// a write, writes before it in its row for a read.
+__global__ void __launch_bounds__(256) gacco_shared_rank_kernel(const uint32_t *keys, const uint32_t *vals,
+                                                                uint64_t n, uint32_t sentinel, const DevOp *ops,
+                                                                const uint64_t *words, const uint32_t *wbefore,
+                                                                uint32_t *rank) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t k = keys[i], v = vals[i];
+  if (k >= sentinel || v >= n) return;
+  const uint64_t start = words[k];
+  if (start > i) return;  // not reachable for a consistent table
+  rank[v] = op_written(ops[v].rowk) ? (uint32_t)(i - start) : wbefore[i] - wbefore[start];
+}
+
+// Third pass: both counters of every accessed row start at zero.
+__global__ void __launch_bounds__(256) gacco_shared_clear_kernel(const uint32_t *keys, uint64_t n, uint32_t sentinel,
+                                                                 uint64_t *words) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t k = keys[i];
+  if (k < sentinel && (i == 0 || keys[i - 1] != k)) words[k] = 0;
+}
+
+// Exclusive scan of m 32-bit values in place (partial: (m + 4095) / 4096 + 1 words).
+static void exclusive_scan_u32(hipStream_t s, uint32_t *data, uint64_t m, uint32_t *partial) {
+  const uint64_t chunks = (m + SCAN_CHUNK - 1) / SCAN_CHUNK;
+  hipLaunchKernelGGL(scan_sum_kernel, dim3((unsigned)chunks), dim3(RS_THREADS), 0, s, data, m, partial);
+  hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(RS_THREADS), 0, s, partial, (uint32_t)chunks);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)chunks), dim3(RS_THREADS), 0, s, data, m, partial);
+}
+
 __global__ void __launch_bounds__(64) gacco_reset_kernel(Ctl *ctl) {
   if (threadIdx.x == 0) ctl->stop = 0;
 }
@@ -264,18 +314,31 @@ uint64_t radix_sort_scratch_words(uint64_t n) {
 }
 
 hipError_t gacco_prepare(hipStream_t s, const DevOp *ops, uint64_t n_ops, uint32_t sentinel, uint64_t *words,
-                         uint32_t *rank, uint32_t *scratch, Ctl *ctl) {
+                         uint32_t *rank, uint32_t *scratch, Ctl *ctl, bool shared) {
   hipLaunchKernelGGL(gacco_reset_kernel, dim3(1), dim3(64), 0, s, ctl);
   if (n_ops == 0) return hipGetLastError();
-  uint32_t *ka = scratch, *va = ka + n_ops, *sorted_k = nullptr, *sorted_v = nullptr;
+  // scratch: [ka | va | radix scratch: kb | vb | histogram | partial sums]
+  uint32_t *ka = scratch, *va = ka + n_ops, *rs = va + n_ops, *sorted_k = nullptr, *sorted_v = nullptr;
   const unsigned blocks = (unsigned)((n_ops + 255) / 256);
   hipLaunchKernelGGL(gacco_keys_kernel, dim3(blocks), dim3(256), 0, s, ops, n_ops, sentinel, ka, va);
   int bits = 0;
   while (bits < 32 && (sentinel >> bits) != 0) ++bits;
-  hipError_t e = radix_sort_pairs(s, ka, va, n_ops, bits, va + n_ops, &sorted_k, &sorted_v);
+  hipError_t e = radix_sort_pairs(s, ka, va, n_ops, bits, rs, &sorted_k, &sorted_v);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(gacco_lock_table_kernel, dim3(blocks), dim3(256), 0, s, sorted_k, sorted_v, n_ops, sentinel,
-                     words, rank);
+  if (!shared) {
+    hipLaunchKernelGGL(gacco_lock_table_kernel, dim3(blocks), dim3(256), 0, s, sorted_k, sorted_v, n_ops, sentinel,
+                       words, rank);
+    return hipGetLastError();
+  }
+  // the key/value pair the sort did not end in is free, and so is the histogram
+  uint32_t *wflag = sorted_k == ka ? rs : ka;
+  uint32_t *partial = rs + 2 * n_ops;
+  hipLaunchKernelGGL(gacco_shared_flags_kernel, dim3(blocks), dim3(256), 0, s, sorted_k, sorted_v, n_ops, sentinel,
+                     ops, words, wflag);
+  exclusive_scan_u32(s, wflag, n_ops, partial);
+  hipLaunchKernelGGL(gacco_shared_rank_kernel, dim3(blocks), dim3(256), 0, s, sorted_k, sorted_v, n_ops, sentinel,
+                     ops, words, wflag, rank);
+  hipLaunchKernelGGL(gacco_shared_clear_kernel, dim3(blocks), dim3(256), 0, s, sorted_k, n_ops, sentinel, words);
   return hipGetLastError();
 }
 

@@ -87,10 +87,14 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) gacco_kernel(GaccoArgs a
       const uint32_t i = (uint32_t)t.tl + (uint32_t)(k * L);
       g[k] = false;
       if (act && lead.test(i) && !granted.test(i)) {
-        const uint64_t turn = ld_word(a.words + op_row(rowk[k]));
-        g[k] = turn == (uint64_t)rk[k];
-        if (!g[k] && (uint64_t)rk[k] > turn) {
-          const uint64_t d = (uint64_t)rk[k] - turn;
+        const uint64_t w = ld_word(a.words + op_row(rowk[k]));
+        // turn mode: the word is the position whose turn it is; shared
+        // reads: a write needs every earlier access done, a read every
+        // earlier write
+        const uint64_t have = !a.shared ? w : (op_written(rowk[k]) ? (w >> 32) : (w & 0xFFFFFFFFull));
+        g[k] = a.shared ? have >= (uint64_t)rk[k] : have == (uint64_t)rk[k];
+        if (!g[k] && (uint64_t)rk[k] > have) {
+          const uint64_t d = (uint64_t)rk[k] - have;
           ahead = d < ahead ? d : ahead;
         }
       }
@@ -160,8 +164,11 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) gacco_kernel(GaccoArgs a
     if (ballot(any_rl)) {
       order_point<STRICT>();  // the group's updates are performed before the row moves on
 #pragma unroll
-      for (int k = 0; k < K; ++k)
-        if (rl[k]) st_word(a.words + op_row(rowk[k]), (uint64_t)rk[k] + 1);
+      for (int k = 0; k < K; ++k) {
+        if (!rl[k]) continue;
+        if (a.shared) add_word(a.words + op_row(rowk[k]), (1ull << 32) | (op_written(rowk[k]) ? 1ull : 0ull));
+        else st_word(a.words + op_row(rowk[k]), (uint64_t)rk[k] + 1);
+      }
     }
     // read values leave after the releases, so that no release waits for them
 #pragma unroll

@@ -26,17 +26,27 @@ def _announce(request):
     print(f"\n[gpu] module {request.module.__name__}", flush=True)
 
 
-DETERMINISTIC = ["gacco", "gputx"]
+# "gacco_shared": GaccO with CC_RUN_SHARED_READS (reads between two writes run together)
+DETERMINISTIC = ["gacco", "gputx", "gacco_shared"]
+
+
+def _sch(scheme):
+    return "gacco" if scheme == "gacco_shared" else scheme
+
+
+def _fl(scheme):
+    return binding().CC_RUN_SHARED_READS if scheme == "gacco_shared" else 0
 
 
 def run_exact(tabs, b, scheme="gacco", **params):
-    out, reads, final, st = run_batch(tabs, b, scheme, **params)
+    params["flags"] = params.get("flags", 0) | _fl(scheme)
+    out, reads, final, st = run_batch(tabs, b, _sch(scheme), **params)
     assert "error" not in st, st["error"]
     exp_fin, exp_reads = oracle.id_order_expected(tabs, b)
     n = b.n_txns
     assert np.all(out["status"] == oracle.COMMITTED)
     assert np.all(out["attempts"] == 1)
-    if scheme == "gacco":
+    if _sch(scheme) == "gacco":
         assert np.all(out["serial_hi"] == 0)
     else:
         ranks = oracle.kset_ranks(b)
@@ -101,7 +111,7 @@ def test_cg_one_row_in_every_transaction(scheme):
 def test_cg_edge_sizes(scheme):
     tabs = [wl.kv_table(64, 2)]
     b0 = wl.kv_batch(64, 2, 0, ops=4, seed=0)
-    out, reads, final, st = run_batch(tabs, b0, scheme)
+    out, reads, final, st = run_batch(tabs, b0, _sch(scheme), flags=_fl(scheme))
     assert "error" not in st and st["committed"] == 0 and np.array_equal(final[0], tabs[0])
     run_exact(tabs, wl.kv_batch(64, 2, 1, ops=5, seed=1), scheme=scheme)
     b2 = wl.kv_batch(64, 2, 50, ops=(0, 3), seed=2)
@@ -160,8 +170,8 @@ def test_cg_unused_ops_stay_out_of_the_access_table(scheme):
         txns2["first_op"][t] = s + t
     eng = b_.Engine(tabs)
     try:
-        bid = b_.cc_submit_batch(eng.ctx, txns2, ops2, b_.SCHEMES[scheme])
-        st = eng.run(bid)
+        bid = b_.cc_submit_batch(eng.ctx, txns2, ops2, b_.SCHEMES[_sch(scheme)])
+        st = eng.run(bid, flags=_fl(scheme))
         out, reads = eng.outcomes(bid, b.n_txns, len(ops2))
         final = eng.tables()
     finally:
@@ -203,9 +213,9 @@ def test_cg_repeated_runs_accumulate(scheme):
     tabs, b = wl.kv_workload(n_rows=5_000, n_fields=2, n_txns=3_000, ops=8, theta=0.9, seed=8)
     eng = b_.Engine(tabs)
     try:
-        bid = eng.submit(b, scheme)
-        eng.run(bid)
-        eng.run(bid)
+        bid = eng.submit(b, _sch(scheme))
+        eng.run(bid, flags=_fl(scheme))
+        eng.run(bid, flags=_fl(scheme))
         out, reads = eng.outcomes(bid, b.n_txns, b.total_ops)
         final = eng.tables()
     finally:
@@ -222,7 +232,7 @@ def test_cg_run_rules(scheme):
     tabs, b = wl.kv_workload(n_rows=1_000, n_fields=2, n_txns=500, ops=4, theta=0.5, seed=10)
     eng = b_.Engine(tabs)
     try:
-        bid = eng.submit(b, scheme)
+        bid = eng.submit(b, _sch(scheme))
         with pytest.raises(b_.CCError) as e:
             eng.run(bid, mode=b_.CC_MODE_EPOCH)
         assert e.value.status == b_.CC_E_INVAL
@@ -232,7 +242,11 @@ def test_cg_run_rules(scheme):
         with pytest.raises(b_.CCError) as e:
             eng.run(bid, flags=b_.CC_RUN_LATCH)  # a deterministic scheme has no latch variant
         assert e.value.status == b_.CC_E_INVAL
-        st = eng.run(bid)  # the batch is still usable after the rejected runs
+        if _sch(scheme) == "gputx":
+            with pytest.raises(b_.CCError) as e:
+                eng.run(bid, flags=b_.CC_RUN_SHARED_READS)  # shared reads are a GaccO option
+            assert e.value.status == b_.CC_E_INVAL
+        st = eng.run(bid, flags=_fl(scheme))  # the batch is still usable after the rejected runs
         assert st["committed"] == b.n_txns
     finally:
         eng.close()
