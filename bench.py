@@ -137,6 +137,13 @@ def suite_schemes(args, binding, workload):
         tables, batch = workload.kv_workload(n_rows=args.rows, n_fields=args.fields, n_txns=args.txns,
                                              ops=args.ops, theta=theta, seed=args.seed)
         h = workload.hottest_row_writes(batch)[1]
+        # the oracle beside the GPU: its serial replay of the same batch on one host core
+        import oracle
+        t0 = time.perf_counter()
+        oracle.serial_execute(tables, batch)
+        dt = time.perf_counter() - t0
+        _emit({"suite": "schemes", "theta": theta, "scheme": "oracle (serial replay, 1 host core)",
+               "txn_per_s": round(batch.n_txns / dt, 1), "run_ms": round(dt * 1e3, 3)})
         eng = binding.Engine(tables)
         for scheme in ("occ", "2pl_nw", "2pl_wd", "to", "mvcc", "tictoc", "gacco", "gputx"):
             bid = eng.submit(batch, scheme)
@@ -179,6 +186,15 @@ def suite_order_entry(args, binding, workload):
 def suite_index(args, binding, workload):
     """Key-value batches that name rows by key: no index, binary search, 16-way tree (OCC and GaccO)."""
     keys = workload.index_keys(args.rows, seed=args.seed)
+    # the oracle beside the GPU: dictionary resolution of a sample of keys on one host core
+    import oracle
+    sample = workload.kv_batch(args.rows, args.fields, 20_000, ops=args.ops, theta=0.0, seed=args.seed)
+    sample_keys = workload.keyed_ops(sample, [keys])
+    t0 = time.perf_counter()
+    oracle.resolve_keys([keys], sample, sample_keys)
+    dt = time.perf_counter() - t0
+    _emit({"suite": "index", "lookup": "oracle (dictionary, 1 host core)", "keys": int(sample.total_ops),
+           "seconds": round(dt, 3), "note": "includes building the dictionary of all keys"})
     for theta in (0.0, 0.6, 0.9):
         tables, batch = workload.kv_workload(n_rows=args.rows, n_fields=args.fields, n_txns=args.txns,
                                              ops=args.ops, theta=theta, seed=args.seed)
