@@ -238,6 +238,30 @@ def suite_latch(args, binding, workload):
         eng.close()
 
 
+def suite_ycsb(args, binding, workload):
+    """The paper's YCSB presets (RO, MC, HC) and its two sweeps (Exp-1: theta at W=0.1; Exp-2: W at theta=0.6)."""
+    configs = [("RO", 0.0, 0.0), ("MC", 0.1, 0.6), ("HC", 0.5, 0.8)]
+    configs += [("exp1", 0.1, th) for th in (0.0, 0.3, 0.6, 0.8, 0.9)]
+    configs += [("exp2", w, 0.6) for w in (0.0, 0.3, 0.5, 0.7, 0.9)]
+    variants = [(s_, 0) for s_ in ("occ", "2pl_nw", "2pl_wd", "to", "mvcc", "tictoc", "gacco", "gputx")]
+    variants.append(("gacco", binding.CC_RUN_SHARED_READS))
+    for name, w, theta in configs:
+        tables, batch = workload.kv_workload(n_rows=args.rows, n_fields=args.fields, n_txns=args.txns,
+                                             ops=args.ops, read_ratio=1.0 - w, theta=theta, seed=args.seed)
+        eng = binding.Engine(tables)
+        for scheme, flags in variants:
+            bid = eng.submit(batch, scheme)
+            rec = {"suite": "ycsb", "set": name, "W": w, "theta": theta,
+                   "scheme": scheme + ("+shared_reads" if flags else "")}
+            try:
+                rec.update(_run_stats(eng, bid, batch.n_txns, steps=1, warmup=1, flags=flags))
+            except binding.CCError as e:
+                rec["error"] = str(e)
+            _emit(rec)
+            eng.release(bid)
+        eng.close()
+
+
 def suite_batching(args, binding, workload):
     """Uneven transactions (2-64 ops), Zipf 0.8: autotuned plain and epoch launches per batch size."""
     from paper_2406_10158_amd import autotune
@@ -317,7 +341,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probes", action="store_true", help="only run the memory micro-benchmarks")
-    ap.add_argument("--suite", choices=["schemes", "order_entry", "batching", "serving", "index", "latch"],
+    ap.add_argument("--suite", choices=["schemes", "order_entry", "batching", "serving", "index", "latch", "ycsb"],
                     help="run a measurement suite instead of the headline step (JSON line per point)")
     ap.add_argument("--oe-txns", type=int, default=100_000)
     ap.add_argument("--serve-arrivals", type=int, default=100_000)
@@ -339,7 +363,7 @@ def main():
         return
     if args.suite:
         {"schemes": suite_schemes, "order_entry": suite_order_entry, "batching": suite_batching, "index": suite_index,
-         "latch": suite_latch,
+         "latch": suite_latch, "ycsb": suite_ycsb,
          "serving": suite_serving}[args.suite](args, binding, workload)
         return
 
