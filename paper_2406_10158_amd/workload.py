@@ -303,6 +303,59 @@ def hottest_row_accesses(batch: Batch, table_id: int = 0) -> tuple[int, int]:
 # Order-entry (TPC-C-style NewOrder / Payment) workloads
 # ----------------------------------------------------------------------------
 
+def mixed_workload(shapes=((40, 3), (300, 5)), n_txns=2_000, ops=(1, 16), theta=0.8,
+                   kind_p=(0.35, 0.3, 0.2, 0.15), seed=0):
+    """Small, contended tables and a batch that mixes every operation kind.
+
+    ``shapes`` lists (rows, fields) per table; cells start uniform on [0, 60]
+    so that conditional adds cross their threshold often.  A transaction's
+    length is uniform on ``ops``; it is made of row groups: a (table, row) not
+    used earlier in the transaction, Zipf(theta) within its table, with 1-3
+    distinct fields whose operations are adjacent.  Kinds are drawn with
+    probabilities ``kind_p`` = (READ, ADD, COND_ADD, WRITE_SLOT); a slot write
+    takes its source uniformly among the transaction's earlier operations
+    (the first operation of a transaction is never one).
+    Returns (tables, batch).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    tables = [rng.integers(0, 61, size=(r, f), dtype=np.int64) for r, f in shapes]
+    kp = np.asarray(kind_p, dtype=np.float64)
+    kp = kp / kp.sum()
+    lengths, row, table, field, kind, arg = [], [], [], [], [], []
+    cap = sum(r * min(f, 3) for r, f in shapes)
+    for _ in range(n_txns):
+        want = int(rng.integers(int(ops[0]), int(ops[1]) + 1))
+        if want > cap:
+            raise ValueError("a transaction needs more cells than the tables offer")
+        used = set()
+        n = 0
+        while n < want:
+            t = int(rng.integers(0, len(shapes)))
+            r = int(draw_keys(rng, shapes[t][0], theta, 1)[0])
+            if (t, r) in used:
+                continue
+            used.add((t, r))
+            g = int(rng.integers(1, min(shapes[t][1], want - n, 3) + 1))
+            for f in rng.permutation(shapes[t][1])[:g]:
+                k = int(rng.choice(4, p=kp))
+                if k == WRITE_SLOT and n == 0:
+                    k = ADD
+                if k == READ:
+                    a = 0
+                elif k == ADD:
+                    a = int(rng.integers(-50, 51))
+                elif k == COND_ADD:
+                    a = int(rng.integers(-30, 6))
+                else:
+                    a = slot_arg(int(rng.integers(0, n)), int(rng.integers(-1, 3)), int(rng.integers(-100, 101)))
+                row.append(r); table.append(t); field.append(int(f)); kind.append(k); arg.append(a)
+                n += 1
+        lengths.append(n)
+    b = _pack(lengths, np.array(row, np.uint32), np.array(table, np.uint16), np.array(field, np.uint8),
+              np.array(kind, np.uint8), np.array(arg, np.int64), {})
+    return tables, b
+
+
 def slot_arg(src: int, mul: int, add: int) -> int:
     """Encode a WRITE_SLOT argument: value = read[src] * mul + add (see include/cc.h)."""
     if not (0 <= src < 256 and -(1 << 23) <= mul < (1 << 23) and -(1 << 31) <= add < (1 << 31)):

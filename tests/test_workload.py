@@ -103,3 +103,30 @@ def test_hottest_row_accesses_counts_transactions_not_ops():
     row, n = wl.hottest_row_accesses(b2)
     assert n >= wl.hottest_row_writes(b2)[1]
     assert n == len(set(np.repeat(np.arange(b2.n_txns), 16)[b2.row == row].tolist()))
+
+
+def test_mixed_workload_follows_the_batch_rules():
+    # row groups adjacent and never repeated, distinct fields per group, slot sources earlier in
+    # the transaction, every kind present, lengths within the asked range, cells in range
+    shapes = ((7, 2), (50, 4))
+    tabs, b = wl.mixed_workload(shapes=shapes, n_txns=400, ops=(1, 12), theta=0.9, seed=4)
+    assert [t.shape for t in tabs] == list(shapes)
+    assert all(t.min() >= 0 and t.max() <= 60 for t in tabs)
+    assert b.n_ops.min() >= 1 and b.n_ops.max() <= 12
+    assert set(np.unique(b.kind).tolist()) == {wl.READ, wl.ADD, wl.COND_ADD, wl.WRITE_SLOT}
+    for i in range(b.n_txns):
+        sl = b.txn_slice(i)
+        rows = list(zip(b.table[sl].tolist(), b.row[sl].tolist()))
+        fields = b.field[sl].tolist()
+        seen, prev = set(), None
+        for j, (key, f) in enumerate(zip(rows, fields)):
+            assert b.row[sl][j] < shapes[key[0]][0] and f < shapes[key[0]][1]
+            if key != prev:
+                assert key not in seen, (i, key)
+                seen.add(key)
+                group = set()
+            assert f not in group
+            group.add(f)
+            prev = key
+            if b.kind[sl][j] == wl.WRITE_SLOT:
+                assert 0 <= (int(b.arg[sl][j]) & 0xFF) < j
