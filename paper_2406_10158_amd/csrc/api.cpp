@@ -117,10 +117,20 @@ cc_status freeze(cc_ctx *c) {
   if (rows > CC_MAX_TOTAL_ROWS || cells > CC_MAX_TOTAL_CELLS) return fail(c, CC_E_RANGE, "tables too large");
   c->total_rows = rows;
   c->total_cells = cells;
-  HIP_OR(c, hipMalloc(&c->d_data, std::max<uint64_t>(cells, 1) * sizeof(int64_t)));
-  HIP_OR(c, hipMalloc(&c->d_words, std::max<uint64_t>(rows, 1) * sizeof(uint64_t)));
-  HIP_OR(c, hipMemsetAsync(c->d_data, 0, std::max<uint64_t>(cells, 1) * sizeof(int64_t), c->stream));
-  HIP_OR(c, hipStreamSynchronize(c->stream));
+  // all or nothing: a failed step frees what it allocated, so a later call can try again
+  int64_t *data = nullptr;
+  uint64_t *words = nullptr;
+  hipError_t e = hipMalloc(&data, std::max<uint64_t>(cells, 1) * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc(&words, std::max<uint64_t>(rows, 1) * sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMemsetAsync(data, 0, std::max<uint64_t>(cells, 1) * sizeof(int64_t), c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    if (data) (void)hipFree(data);
+    if (words) (void)hipFree(words);
+    return hip_fail(c, e, "table allocation");
+  }
+  c->d_data = data;
+  c->d_words = words;
   c->frozen = true;
   return CC_OK;
 }
@@ -823,28 +833,52 @@ cc_status cc_create_index(cc_ctx *c, uint32_t tid, const int64_t *keys, uint64_t
   d.row_base = t.row_base;
   d.elem_base = t.elem_base;
   d.n_fields = t.n_fields;
-  if (c->indexes.size() < c->tables.size()) c->indexes.resize(c->tables.size());
-  DevIndex &ix = c->indexes[tid];
-  if (ix.keys) (void)hipFree(ix.keys);
-  if (ix.rows) (void)hipFree(ix.rows);
-  if (ix.tree) (void)hipFree(ix.tree);
-  ix = DevIndex{};
-  HIP_OR(c, hipMalloc(&ix.keys, level0.size() * sizeof(int64_t)));
-  HIP_OR(c, hipMalloc(&ix.rows, rows.size() * sizeof(uint32_t)));
-  HIP_OR(c, hipMalloc(&ix.tree, std::max<size_t>(tree.size(), 1) * sizeof(int64_t)));
-  HIP_OR(c, hipMemcpyAsync(ix.keys, level0.data(), level0.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
-  HIP_OR(c, hipMemcpyAsync(ix.rows, rows.data(), rows.size() * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
-  if (!tree.empty())
-    HIP_OR(c, hipMemcpyAsync(ix.tree, tree.data(), tree.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
-  d.keys = ix.keys;
-  d.rows = ix.rows;
-  d.tree = ix.tree;
-  ix.desc = d;
+  // Build the new index in full before touching the old one: on any failure
+  // the table keeps its previous index (or none), on the host and on the
+  // device alike.
+  DevIndex nx{};
+  auto drop = [](DevIndex &x) {
+    if (x.keys) (void)hipFree(x.keys);
+    if (x.rows) (void)hipFree(x.rows);
+    if (x.tree) (void)hipFree(x.tree);
+    x = DevIndex{};
+  };
   if (!c->d_idx) HIP_OR(c, hipMalloc(&c->d_idx, CC_MAX_TABLES * sizeof(IndexDesc)));
+  hipError_t e = hipMalloc(&nx.keys, level0.size() * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc(&nx.rows, rows.size() * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(&nx.tree, std::max<size_t>(tree.size(), 1) * sizeof(int64_t));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(nx.keys, level0.data(), level0.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(nx.rows, rows.data(), rows.size() * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && !tree.empty())
+    e = hipMemcpyAsync(nx.tree, tree.data(), tree.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    drop(nx);
+    return hip_fail(c, e, "index upload");
+  }
+  d.keys = nx.keys;
+  d.rows = nx.rows;
+  d.tree = nx.tree;
+  nx.desc = d;
   std::vector<IndexDesc> all(CC_MAX_TABLES, IndexDesc{});
   for (size_t i = 0; i < c->indexes.size(); ++i) all[i] = c->indexes[i].desc;
-  HIP_OR(c, hipMemcpyAsync(c->d_idx, all.data(), all.size() * sizeof(IndexDesc), hipMemcpyHostToDevice, c->stream));
-  HIP_OR(c, hipStreamSynchronize(c->stream));
+  all[tid] = d;
+  e = hipMemcpyAsync(c->d_idx, all.data(), all.size() * sizeof(IndexDesc), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    // the device table may be partly written: put the old descriptors back
+    // (best effort) and keep the old index
+    for (size_t i = 0; i < c->indexes.size(); ++i) all[i] = c->indexes[i].desc;
+    if (tid >= c->indexes.size()) all[tid] = IndexDesc{};
+    (void)hipMemcpy(c->d_idx, all.data(), all.size() * sizeof(IndexDesc), hipMemcpyHostToDevice);
+    drop(nx);
+    return hip_fail(c, e, "index descriptor upload");
+  }
+  if (c->indexes.size() < c->tables.size()) c->indexes.resize(c->tables.size());
+  drop(c->indexes[tid]);
+  c->indexes[tid] = nx;
   return CC_OK;
 }
 
