@@ -138,12 +138,10 @@ def test_check_batch_accepts_generated_workloads(b):
 
 
 def test_init_without_a_gpu_fails_cleanly(b):
-    try:
-        import torch
-        if torch.cuda.is_available():
-            pytest.skip("a GPU is present")
-    except ImportError:
-        pass
+    # the kernel driver's device node, not torch: in a process that loaded the library first,
+    # torch's own HIP runtime can report no device while the library's sees one
+    if os.path.exists("/dev/kfd"):
+        pytest.skip("a GPU is present")
     with pytest.raises(b.CCError) as e:
         b.cc_init(0)
     assert e.value.status == b.CC_E_NODEV
