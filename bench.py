@@ -423,7 +423,8 @@ def main():
             traffic = t["total_bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
-                "kernel": "gacco_kernel" if args.scheme == "gacco" else "txn_kernel", "launches_per_step": launches,
+                "kernel": {"gacco": "gacco_kernel", "gputx": "gputx_exec_kernel"}.get(args.scheme, "txn_kernel"),
+                "launches_per_step": launches,
                 "algorithmic_bytes_per_launch": int(alg / launches),
                 "avg_launch_ms": round(k_step_s * 1e3 / launches, 4)}
 
@@ -436,10 +437,17 @@ def main():
     if args.scheme == "gacco":
         # every access of the hottest row (reads too) is one turn of its word;
         # the bound takes the plain store-to-load hand-off per turn
-        hot_row, h = workload.hottest_row_accesses(batch)
+        _, h = workload.hottest_row_accesses(batch)
         t_h, h_key = probes["handoff_ns"], "hot_row_accesses_H"
+    elif args.scheme == "gputx":
+        # the rank pass hands the hottest row along its accesses, one turn
+        # each; then the K-sets run one after another, each released by the
+        # done counter: at least one store-to-load hand-off per turn and per K-set
+        _, h = workload.hottest_row_accesses(batch)
+        h += int(st["ksets"])
+        t_h, h_key = probes["handoff_ns"], "hot_row_accesses_plus_ksets_H"
     else:
-        hot_row, h = workload.hottest_row_writes(batch)
+        _, h = workload.hottest_row_writes(batch)
         t_h, h_key = probes["commit_handoff_ns"], "hot_row_writes_H"
     x_cont = batch.n_txns / (h * t_h * 1e-9) if h else float("inf")
     eff = min(x_roof, x_cont)

@@ -209,10 +209,14 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) gputx_exec_kernel(GputxA
   uint64_t ready_at = 0, progress_at = 0, began = 0, waited = 0;
   uint32_t idle_polls = 0;
   uint64_t n_commit = 0, t_useful = 0, t_wait = 0;
+  uint32_t first = 0, n = 0;  // the claimed transaction's operations, staged while it waits
+  uint32_t rowk[K], elem[K];
+  int64_t arg[K];
 
   for (;;) {
     const bool claim = pos < 0 && !finished;
     const uint64_t q = t.claim(&a.ctl->queue, claim, 1);
+    bool fresh = false;
     if (claim) {
       if (q < a.n_txns && ld_word(&a.ctl->stop) == 0) {
         pos = (int64_t)q;
@@ -222,11 +226,37 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) gputx_exec_kernel(GputxA
         began = progress_at = wall_clock64();
         waited = 0;
         idle_polls = 0;
+        fresh = true;
       } else {
         finished = true;
       }
     }
     if (ballot(pos >= 0) == 0) break;
+    if (ballot(fresh)) {
+      // Stage the operations as soon as the position is taken: they do not
+      // change during the run, so these loads overlap the wait for lower
+      // K-sets instead of following it.
+      if (fresh) {
+        const DevTxn d = a.txns[txn];
+        first = d.first;
+        n = d.n;
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const uint32_t idx = (uint32_t)t.tl + (uint32_t)(k * L);
+        if (fresh) {
+          rowk[k] = 0;
+          elem[k] = 0;
+          arg[k] = 0;
+          if (idx < n) {
+            const DevOp op = a.ops[first + idx];
+            rowk[k] = op.rowk;
+            elem[k] = op.elem;
+            arg[k] = op.arg;
+          }
+        }
+      }
+    }
     const uint64_t now = wall_clock64();
     bool go = false;
     uint64_t behind = 0;
@@ -241,29 +271,13 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) gputx_exec_kernel(GputxA
     if (ballot(go)) {
       if (STRICT) order_point<STRICT>();
       else asm volatile("" ::: "memory");
-      uint32_t first = 0, n = 0;
-      if (go) {
-        const DevTxn d = a.txns[txn];
-        first = d.first;
-        n = d.n;
-      }
-      uint32_t rowk[K], elem[K];
-      int64_t arg[K], x[K];
+      int64_t x[K];
       bool v[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const uint32_t idx = (uint32_t)t.tl + (uint32_t)(k * L);
         v[k] = go && idx < n;
-        rowk[k] = 0;
-        elem[k] = 0;
-        arg[k] = 0;
         x[k] = 0;
-        if (v[k]) {
-          const DevOp op = a.ops[first + idx];
-          rowk[k] = op.rowk;
-          elem[k] = op.elem;
-          arg[k] = op.arg;
-        }
       }
 #pragma unroll
       for (int k = 0; k < K; ++k)
