@@ -131,6 +131,12 @@ def _run_stats(eng, bid, n_txns, steps=2, warmup=1, reset=None, **params):
             "breakdown": {k: round(st[f"t_{k}_ns"] / busy, 3) if busy else 0 for k in ("useful", "abort", "wait")}}
 
 
+def _pick(args, names):
+    """The suite's schemes, narrowed to --only when it is given."""
+    only = [x for x in (args.only or "").split(",") if x]
+    return tuple(n for n in names if not only or n in only)
+
+
 def suite_schemes(args, binding, workload):
     """Every scheme on the key-value config at each contention level."""
     for theta in (0.0, 0.6, 0.9, 0.99):
@@ -145,7 +151,7 @@ def suite_schemes(args, binding, workload):
         _emit({"suite": "schemes", "theta": theta, "scheme": "oracle (serial replay, 1 host core)",
                "txn_per_s": round(batch.n_txns / dt, 1), "run_ms": round(dt * 1e3, 3)})
         eng = binding.Engine(tables)
-        for scheme in ("occ", "2pl_nw", "2pl_wd", "to", "mvcc", "tictoc", "gacco", "gputx"):
+        for scheme in _pick(args, ("occ", "2pl_nw", "2pl_wd", "to", "mvcc", "tictoc", "gacco", "gputx")):
             bid = eng.submit(batch, scheme)
             rec = {"suite": "schemes", "theta": theta, "scheme": scheme, "hot_row_writes": h}
             try:
@@ -165,7 +171,7 @@ def suite_order_entry(args, binding, workload):
     for w in (1, 8, 64):
         tables, batch = workload.order_entry_workload(w, args.oe_txns, seed=args.seed)
         eng = binding.Engine(tables)
-        for scheme in ("occ", "2pl_nw", "2pl_wd", "to", "mvcc", "tictoc", "gacco", "gputx"):
+        for scheme in _pick(args, ("occ", "2pl_nw", "2pl_wd", "to", "mvcc", "tictoc", "gacco", "gputx")):
             bid = eng.submit(batch, scheme)
             rec = {"suite": "order_entry", "warehouses": w, "txns": batch.n_txns, "scheme": scheme}
             try:
@@ -224,7 +230,7 @@ def suite_latch(args, binding, workload):
         tables, batch = workload.kv_workload(n_rows=args.rows, n_fields=args.fields, n_txns=args.txns,
                                              ops=args.ops, theta=theta, seed=args.seed)
         eng = binding.Engine(tables)
-        for scheme in ("occ", "2pl_nw", "2pl_wd", "to", "mvcc", "tictoc"):
+        for scheme in _pick(args, ("occ", "2pl_nw", "2pl_wd", "to", "mvcc", "tictoc")):
             bid = eng.submit(batch, scheme)
             for latch in (False, True):
                 rec = {"suite": "latch", "theta": theta, "scheme": scheme, "latch": latch}
@@ -243,8 +249,9 @@ def suite_ycsb(args, binding, workload):
     configs = [("RO", 0.0, 0.0), ("MC", 0.1, 0.6), ("HC", 0.5, 0.8)]
     configs += [("exp1", 0.1, th) for th in (0.0, 0.3, 0.6, 0.8, 0.9)]
     configs += [("exp2", w, 0.6) for w in (0.0, 0.3, 0.5, 0.7, 0.9)]
-    variants = [(s_, 0) for s_ in ("occ", "2pl_nw", "2pl_wd", "to", "mvcc", "tictoc", "gacco", "gputx")]
-    variants.append(("gacco", binding.CC_RUN_SHARED_READS))
+    variants = [(s_, 0) for s_ in _pick(args, ("occ", "2pl_nw", "2pl_wd", "to", "mvcc", "tictoc", "gacco", "gputx"))]
+    if _pick(args, ("gacco+shared_reads",)):
+        variants.append(("gacco", binding.CC_RUN_SHARED_READS))
     for name, w, theta in configs:
         tables, batch = workload.kv_workload(n_rows=args.rows, n_fields=args.fields, n_txns=args.txns,
                                              ops=args.ops, read_ratio=1.0 - w, theta=theta, seed=args.seed)
@@ -344,6 +351,7 @@ def main():
     ap.add_argument("--probes", action="store_true", help="only run the memory micro-benchmarks")
     ap.add_argument("--suite", choices=["schemes", "order_entry", "batching", "serving", "index", "latch", "ycsb"],
                     help="run a measurement suite instead of the headline step (JSON line per point)")
+    ap.add_argument("--only", default="", help="comma-separated schemes a suite runs (default: all of its schemes)")
     ap.add_argument("--oe-txns", type=int, default=100_000)
     ap.add_argument("--serve-arrivals", type=int, default=100_000)
     ap.add_argument("--serve-cap", type=int, default=4 << 30)

@@ -209,14 +209,14 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) gputx_exec_kernel(GputxA
   uint64_t ready_at = 0, progress_at = 0, began = 0, waited = 0;
   uint32_t idle_polls = 0;
   uint64_t n_commit = 0, t_useful = 0, t_wait = 0;
-  uint32_t first = 0, n = 0;  // the claimed transaction's operations, staged while it waits
+  bool staged = false;        // the claimed transaction's operations are in registers
+  uint32_t first = 0, n = 0;
   uint32_t rowk[K], elem[K];
   int64_t arg[K];
 
   for (;;) {
     const bool claim = pos < 0 && !finished;
     const uint64_t q = t.claim(&a.ctl->queue, claim, 1);
-    bool fresh = false;
     if (claim) {
       if (q < a.n_txns && ld_word(&a.ctl->stop) == 0) {
         pos = (int64_t)q;
@@ -226,17 +226,29 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) gputx_exec_kernel(GputxA
         began = progress_at = wall_clock64();
         waited = 0;
         idle_polls = 0;
-        fresh = true;
+        staged = false;
       } else {
         finished = true;
       }
     }
     if (ballot(pos >= 0) == 0) break;
-    if (ballot(fresh)) {
-      // Stage the operations as soon as the position is taken: they do not
-      // change during the run, so these loads overlap the wait for lower
-      // K-sets instead of following it.
-      if (fresh) {
+    const uint64_t now = wall_clock64();
+    bool go = false;
+    uint64_t behind = 0;
+    if (pos >= 0 && now >= ready_at) {
+      uint64_t d = 0;
+      if (t.tl == 0) d = ld_word(&a.ctl->ticket);  // transactions done so far
+      d = (uint64_t)__shfl((long long)d, t.tb, 64);
+      go = d >= need;
+      behind = go ? 0 : need - d;
+    }
+    // Stage the operations (they do not change during the run).  A team whose
+    // K-set cannot start yet does it now, so that the loads overlap its wait;
+    // a team that can start does it on its way, after the gate's load, which
+    // then never queues behind them.
+    const bool stage = pos >= 0 && !staged;
+    if (ballot(stage)) {
+      if (stage) {
         const DevTxn d = a.txns[txn];
         first = d.first;
         n = d.n;
@@ -244,7 +256,7 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) gputx_exec_kernel(GputxA
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const uint32_t idx = (uint32_t)t.tl + (uint32_t)(k * L);
-        if (fresh) {
+        if (stage) {
           rowk[k] = 0;
           elem[k] = 0;
           arg[k] = 0;
@@ -256,16 +268,7 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) gputx_exec_kernel(GputxA
           }
         }
       }
-    }
-    const uint64_t now = wall_clock64();
-    bool go = false;
-    uint64_t behind = 0;
-    if (pos >= 0 && now >= ready_at) {
-      uint64_t d = 0;
-      if (t.tl == 0) d = ld_word(&a.ctl->ticket);  // transactions done so far
-      d = (uint64_t)__shfl((long long)d, t.tb, 64);
-      go = d >= need;
-      behind = go ? 0 : need - d;
+      staged = staged || stage;
     }
     bool done_now = false;
     if (ballot(go)) {
