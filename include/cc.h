@@ -218,6 +218,10 @@ typedef struct {
   uint64_t ts_start;      /* first value of the run's ticket / timestamp counter (0 for normal runs; a
                              large value forces the 31-bit TO/MVCC timestamp-overflow path) */
   uint64_t hbm_cap_bytes; /* CC_MODE_SERVE: admission budget for uncommitted work; 0 = no cap */
+  uint64_t wait_limit_us; /* CC_GACCO, CC_GPUTX: a team that sees no progress on its waits for this long
+                             stops every team and the run fails with CC_E_LIVELOCK; 0 = 4 s.  It cannot
+                             trigger while the lock table is consistent (the smallest unfinished
+                             transaction can always proceed); a tiny value exercises the stop path */
 } cc_run_params;
 
 /* Counters reported by cc_stats (index: meaning). */

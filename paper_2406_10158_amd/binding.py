@@ -60,7 +60,7 @@ class cc_run_params(ctypes.Structure):
     _fields_ = [("lanes_per_txn", ctypes.c_uint32), ("waves_per_wg", ctypes.c_uint32), ("grid", ctypes.c_uint32),
                 ("mode", ctypes.c_uint32), ("max_attempts", ctypes.c_uint64), ("max_epochs", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("backoff_ns", ctypes.c_uint32), ("defer_after", ctypes.c_uint32),
-                ("ts_start", ctypes.c_uint64), ("hbm_cap_bytes", ctypes.c_uint64)]
+                ("ts_start", ctypes.c_uint64), ("hbm_cap_bytes", ctypes.c_uint64), ("wait_limit_us", ctypes.c_uint64)]
 
 
 _P = ctypes.c_void_p
@@ -226,9 +226,9 @@ def cc_fetch_rows(ctx, batch_id: int, n_ops: int) -> np.ndarray:
 
 
 def run_params(lanes_per_txn=0, waves_per_wg=0, grid=0, mode=CC_MODE_PLAIN, max_attempts=0, max_epochs=0,
-               flags=0, backoff_ns=0, defer_after=0, ts_start=0, hbm_cap_bytes=0) -> cc_run_params:
+               flags=0, backoff_ns=0, defer_after=0, ts_start=0, hbm_cap_bytes=0, wait_limit_us=0) -> cc_run_params:
     return cc_run_params(lanes_per_txn, waves_per_wg, grid, mode, max_attempts, max_epochs, flags, backoff_ns,
-                         defer_after, ts_start, hbm_cap_bytes)
+                         defer_after, ts_start, hbm_cap_bytes, wait_limit_us)
 
 
 def cc_run(ctx, batch_id: int, params: cc_run_params | None = None) -> None:

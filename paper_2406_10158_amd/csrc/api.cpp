@@ -484,6 +484,13 @@ std::vector<Table> layout_tables(uint32_t n_tables, const uint64_t *n_rows, cons
 // table), one execution pass.  Every transaction runs exactly once.
 constexpr uint64_t GACCO_WAIT_LIMIT_MS = 4000;
 
+// Wall-clock ticks a waiting team may go without progress before it stops
+// the run (cc_run_params.wait_limit_us; 0 = GACCO_WAIT_LIMIT_MS).
+uint64_t wait_limit_ticks(const cc_ctx *c, const cc_run_params &p) {
+  if (p.wait_limit_us == 0) return (uint64_t)c->wallclock_khz * GACCO_WAIT_LIMIT_MS;
+  return std::max<uint64_t>(1, p.wait_limit_us * c->wallclock_khz / 1000ull);
+}
+
 cc_status run_gacco(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes, uint32_t wpw) {
   if (p.mode != CC_MODE_PLAIN)
     return fail(c, CC_E_INVAL,
@@ -501,7 +508,7 @@ cc_status run_gacco(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes,
   a.out = b.d_out;
   a.reads = b.d_reads;
   a.ctl = c->d_ctl;
-  a.wait_limit_ticks = (uint64_t)c->wallclock_khz * GACCO_WAIT_LIMIT_MS;
+  a.wait_limit_ticks = wait_limit_ticks(c, p);
   const uint64_t poll_ns = p.backoff_ns ? p.backoff_ns : 200;
   a.poll_ticks = (uint32_t)std::max<uint64_t>(1, poll_ns * c->wallclock_khz / 1000000ull);
   a.ns_per_tick_q16 = (uint32_t)((1000000ull << 16) / c->wallclock_khz);
@@ -587,7 +594,7 @@ cc_status run_gputx(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes,
   a.out = b.d_out;
   a.reads = b.d_reads;
   a.ctl = c->d_ctl;
-  a.wait_limit_ticks = (uint64_t)c->wallclock_khz * GACCO_WAIT_LIMIT_MS;
+  a.wait_limit_ticks = wait_limit_ticks(c, p);
   const uint64_t poll_ns = p.backoff_ns ? p.backoff_ns : 200;
   a.poll_ticks = (uint32_t)std::max<uint64_t>(1, poll_ns * c->wallclock_khz / 1000000ull);
   a.ns_per_tick_q16 = (uint32_t)((1000000ull << 16) / c->wallclock_khz);

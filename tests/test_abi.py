@@ -3,6 +3,7 @@ host-only validation rejects malformed batches with the documented status codes.
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -48,9 +49,33 @@ def test_strerror_and_version(b):
     assert b.cc_version().startswith("cc-gfx950")
 
 
-def test_struct_layouts_match_header(b):
-    assert b.OP_DTYPE.itemsize == 16 and b.TXN_DTYPE.itemsize == 16 and b.OUTCOME_DTYPE.itemsize == 32
-    assert ctypes.sizeof(b.cc_run_params) == 56
+def test_struct_layouts_match_header(b, tmp_path):
+    # compile the header with the host C compiler and compare every size and field offset
+    # with the binding's numpy dtypes and ctypes structures
+    layouts = [("cc_op", b.OP_DTYPE.names, None), ("cc_txn", b.TXN_DTYPE.names, None),
+               ("cc_outcome", b.OUTCOME_DTYPE.names, None),
+               ("cc_run_params", [f[0] for f in b.cc_run_params._fields_], None),
+               ("cc_config", [f[0] for f in b.cc_config._fields_], None)]
+    lines = []
+    for name, fields, _ in layouts:
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for f in fields:
+            lines.append(f'  printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"cc.h\"\nint main(void) {\n"
+                   + "\n".join(lines) + "\n  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for name, dt in (("cc_op", b.OP_DTYPE), ("cc_txn", b.TXN_DTYPE), ("cc_outcome", b.OUTCOME_DTYPE)):
+        assert dt.itemsize == int(got[name]), name
+        for f in dt.names:
+            assert dt.fields[f][1] == int(got[f"{name}.{f}"]), (name, f)
+    for name, st in (("cc_run_params", b.cc_run_params), ("cc_config", b.cc_config)):
+        assert ctypes.sizeof(st) == int(got[name]), name
+        for f, _ in st._fields_:
+            assert getattr(st, f).offset == int(got[f"{name}.{f}"]), (name, f)
 
 
 def _batch(rows, tables=None, fields=None, kinds=None, args=None, txn_lens=None):

@@ -258,3 +258,27 @@ def test_cg_full_size_kv_config(scheme):
     out, reads, final, st = run_exact(tabs, b, scheme=scheme)
     print(f"{scheme} full: run_ms={st['run_ns']/1e6:.1f} prep_ms={st['prep_ns']/1e6:.2f} "
           f"kernel_ms={st['kernel_ns']/1e6:.1f}")
+
+
+@pytest.mark.parametrize("scheme", DETERMINISTIC)
+def test_wait_limit_stops_the_run_and_the_context_recovers(scheme):
+    # The bounded wait's stop path, forced from the host: with a 1 us limit a contended run
+    # stops (every team leaves its wait and every kernel exits), the run reports
+    # CC_E_LIVELOCK, and the next run of the same batch on reloaded tables matches the
+    # id-order execution exactly.
+    bb = binding()
+    tabs, b = wl.kv_workload(n_rows=2_000, n_fields=2, n_txns=20_000, ops=8, theta=0.99, seed=77)
+    print(f"[gpu] wait limit {scheme}", flush=True)
+    with bb.Engine(tabs) as eng:
+        bid = eng.submit(b, _sch(scheme))
+        with pytest.raises(bb.CCError) as e:
+            eng.run(bid, flags=_fl(scheme), wait_limit_us=1)
+        assert e.value.status == bb.CC_E_LIVELOCK
+        eng.load(tabs)
+        st = eng.run(bid, flags=_fl(scheme))
+        assert st["committed"] == b.n_txns
+        out, reads = eng.outcomes(bid, b.n_txns, b.total_ops)
+        final = eng.tables()
+    exp_fin, exp_reads = oracle.id_order_expected(tabs, b)
+    assert np.array_equal(np.asarray(reads, np.int64), exp_reads)
+    assert all(np.array_equal(np.asarray(g, np.int64), x) for g, x in zip(final, exp_fin))
