@@ -221,7 +221,8 @@ typedef struct {
   uint64_t wait_limit_us; /* CC_GACCO, CC_GPUTX: a team that sees no progress on its waits for this long
                              stops every team and the run fails with CC_E_LIVELOCK; 0 = 4 s.  It cannot
                              trigger while the lock table is consistent (the smallest unfinished
-                             transaction can always proceed); a tiny value exercises the stop path */
+                             transaction can always proceed); a tiny value exercises the stop path.
+                             Nonzero for another scheme: CC_E_INVAL */
 } cc_run_params;
 
 /* Counters reported by cc_stats (index: meaning). */

@@ -925,6 +925,8 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
     return fail(c, CC_E_INVAL, "unknown run flag");
   if ((p.flags & CC_RUN_SHARED_READS) && b.scheme != CC_GACCO)
     return fail(c, CC_E_INVAL, "CC_RUN_SHARED_READS is a CC_GACCO option");
+  if (p.wait_limit_us && b.scheme != CC_GACCO && b.scheme != CC_GPUTX)
+    return fail(c, CC_E_INVAL, "wait_limit_us applies to CC_GACCO and CC_GPUTX only");
   if (p.flags & CC_RUN_WAIT_UNLOCK)
     // Switched off: two teams of one wavefront that block each other both see
     // the row free on their next loop iteration (each attempt releases its

@@ -282,3 +282,14 @@ def test_wait_limit_stops_the_run_and_the_context_recovers(scheme):
     exp_fin, exp_reads = oracle.id_order_expected(tabs, b)
     assert np.array_equal(np.asarray(reads, np.int64), exp_reads)
     assert all(np.array_equal(np.asarray(g, np.int64), x) for g, x in zip(final, exp_fin))
+
+
+def test_wait_limit_is_rejected_for_the_other_schemes():
+    bb = binding()
+    tabs, b = wl.kv_workload(n_rows=1_000, n_fields=2, n_txns=100, ops=4, seed=78)
+    with bb.Engine(tabs) as eng:
+        bid = eng.submit(b, "occ")
+        with pytest.raises(bb.CCError) as e:
+            eng.run(bid, wait_limit_us=10)
+        assert e.value.status == bb.CC_E_INVAL
+        assert np.array_equal(eng.tables()[0], tabs[0])
