@@ -255,6 +255,8 @@ enum cc_stat {
   CC_STAT_INDEX_NS = 24,   /* keyed batches: the index lookups, HIP events; part of CC_STAT_RUN_NS */
   CC_STAT_WD_WAITS = 25,   /* CC_2PL_WD: times a transaction kept its locks and waited */
   CC_STAT_KSETS = 26,      /* CC_GPUTX: K-sets (largest rank + 1) */
+  CC_STAT_PACKED_STATE = 27, /* CC_GPUTX: 1 if the rank pass kept each row's rank state in its turn word
+                                (fewer than 2^20 transactions and 2^24 operations), else 0 */
   CC_N_STATS = 32
 };
 

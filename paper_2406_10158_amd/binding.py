@@ -42,7 +42,8 @@ CC_RUN_SHARED_READS = 0x80
 STAT_NAMES = ["committed", "attempts", "abort_lock", "abort_valid", "kernel_ns", "run_ns", "tickets",
               "max_attempts", "lat_p50_ns", "lat_p99_ns", "epochs", "passes", "deferred", "grid",
               "t_useful_ns", "t_abort_ns", "t_wait_ns", "gave_up", "admit_waits",
-              "occ_r1_ns", "occ_r2_ns", "occ_r3_ns", "occ_r4_ns", "prep_ns", "index_ns", "wd_waits", "ksets"]
+              "occ_r1_ns", "occ_r2_ns", "occ_r3_ns", "occ_r4_ns", "prep_ns", "index_ns", "wd_waits", "ksets",
+              "packed_state"]
 CC_N_STATS = 32
 
 OP_DTYPE = np.dtype([("row", "<u4"), ("table", "<u2"), ("field", "u1"), ("kind", "u1"), ("arg", "<i8")])

@@ -526,7 +526,7 @@ cc_status run_gacco(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes,
   }
   HIP_OR(c, hipEventRecord(c->ev[4], c->stream));
   HIP_OR(c, gacco_prepare(c->stream, b.d_ops, b.n_ops, (uint32_t)c->total_rows, c->d_words, b.d_rank, b.d_gscratch,
-                          c->d_ctl, a.shared != 0));
+                          c->d_ctl, a.shared ? PREP_SHARED : PREP_TURNS));
   HIP_OR(c, hipEventRecord(c->ev[5], c->stream));
   HIP_OR(c, hipEventRecord(c->ev[1], c->stream));
   int grid_used = 0;
@@ -599,6 +599,10 @@ cc_status run_gputx(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes,
   a.poll_ticks = (uint32_t)std::max<uint64_t>(1, poll_ns * c->wallclock_khz / 1000000ull);
   a.ns_per_tick_q16 = (uint32_t)((1000000ull << 16) / c->wallclock_khz);
   a.has_slot = b.has_slot ? 1u : 0u;
+  // the rank pass keeps each row's rank state in its turn word when both fit
+  // (rank + 1 in 20 bits, a row's place in its list in 24)
+  const bool packed = n < (1ull << 20) && b.n_ops < (1ull << 24);
+  a.packed = packed ? 1u : 0u;
   const bool strict = (p.flags & CC_RUN_STRICT_FENCES) != 0;
 
   HIP_OR(c, hipEventRecord(c->ev[0], c->stream));
@@ -610,10 +614,10 @@ cc_status run_gputx(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes,
   }
   HIP_OR(c, hipEventRecord(c->ev[4], c->stream));
   HIP_OR(c, gacco_prepare(c->stream, b.d_ops, b.n_ops, (uint32_t)c->total_rows, c->d_words, b.d_rank, b.d_gscratch,
-                          c->d_ctl, false));
+                          c->d_ctl, packed ? PREP_LOCAL : PREP_TURNS));
   int grid_used = 0;
   if (n) {
-    HIP_OR(c, gputx_init_state(c->stream, c->d_kstate, c->total_rows, iota, n));
+    HIP_OR(c, gputx_init_state(c->stream, c->d_kstate, packed ? 0 : c->total_rows, iota, n));
     HIP_OR(c, gputx_reset(c->stream, c->d_ctl));
     hipError_t e = launch_gputx_pass(c->stream, false, (int)lanes, (int)b.max_ops, (int)wpw, (int)p.grid, strict, a,
                                      c->n_cu, &grid_used);
@@ -651,6 +655,7 @@ cc_status run_gputx(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes,
   b.stats[CC_STAT_MAX_ATTEMPTS] = h.stats[DS_MAX_ATTEMPTS];
   b.stats[CC_STAT_PASSES] = n ? 1 : 0;
   b.stats[CC_STAT_GRID] = (uint64_t)grid_used;
+  b.stats[CC_STAT_PACKED_STATE] = packed ? 1 : 0;
   const double ns_per_tick = 1e6 / (double)c->wallclock_khz;
   b.stats[CC_STAT_T_USEFUL_NS] = (uint64_t)((double)h.stats[DS_T_USEFUL] * ns_per_tick);
   b.stats[CC_STAT_T_WAIT_NS] = (uint64_t)((double)h.stats[DS_T_WAIT] * ns_per_tick);

@@ -168,11 +168,19 @@ uint64_t gacco_scratch_words(uint64_t n_ops);
 uint64_t radix_sort_scratch_words(uint64_t n);
 hipError_t radix_sort_pairs(hipStream_t s, uint32_t *keys, uint32_t *vals, uint64_t n, int bits, uint32_t *scratch,
                             uint32_t **keys_out, uint32_t **vals_out);
-// With `shared`, the words hold (accesses done, writes done) counters and a
-// leader's rank is its threshold: accesses before it in its row for a write,
-// writes before it for a read (reads between two writes share the row).
+// Modes:
+//  PREP_TURNS   each accessed row's word is the sorted position of its first
+//               access, and a leader's rank is its own sorted position (the
+//               turn it waits for);
+//  PREP_SHARED  the words hold (accesses done, writes done) counters and a
+//               leader's rank is its threshold: accesses before it in its row
+//               for a write, writes before it for a read (reads between two
+//               writes share the row);
+//  PREP_LOCAL   every accessed row's word is 0 and a leader's rank is its
+//               place in its row's list (GPUTx's packed rank state).
+enum PrepMode { PREP_TURNS = 0, PREP_SHARED = 1, PREP_LOCAL = 2 };
 hipError_t gacco_prepare(hipStream_t s, const DevOp *ops, uint64_t n_ops, uint32_t sentinel, uint64_t *words,
-                         uint32_t *rank, uint32_t *scratch, Ctl *ctl, bool shared);
+                         uint32_t *rank, uint32_t *scratch, Ctl *ctl, int mode);
 // GaccO execution; hipErrorInvalidValue for an unsupported (lanes, ops per txn).
 hipError_t launch_gacco(hipStream_t s, int lanes, int max_ops, int waves_per_wg, int grid, bool strict,
                         const GaccoArgs &a, int n_cu, int *grid_used);
@@ -197,7 +205,7 @@ struct GputxArgs {
   uint32_t poll_ticks;
   uint32_t ns_per_tick_q16;
   uint32_t has_slot;
-  uint32_t pad;
+  uint32_t packed;            // rank pass: turn and rank state share the row's word (see gputx.hip)
 };
 hipError_t launch_gputx_pass(hipStream_t s, bool exec, int lanes, int max_ops, int waves_per_wg, int grid,
                              bool strict, const GputxArgs &a, int n_cu, int *grid_used);

@@ -259,6 +259,21 @@ __global__ void __launch_bounds__(256) gacco_shared_rank_kernel(const uint32_t *
   rank[v] = op_written(ops[v].rowk) ? (uint32_t)(i - start) : wbefore[i] - wbefore[start];
 }
 
+// Per-row positions (PREP_LOCAL, GPUTx's packed rank state): after the lock
+// table has put each row's first position in its word, every leader's place
+// in its row's list becomes its position minus that start.
+__global__ void __launch_bounds__(256) gacco_local_rank_kernel(const uint32_t *keys, const uint32_t *vals, uint64_t n,
+                                                               uint32_t sentinel, const uint64_t *words,
+                                                               uint32_t *rank) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t k = keys[i], v = vals[i];
+  if (k >= sentinel || v >= n) return;
+  const uint64_t start = words[k];
+  if (start > i) return;  // not reachable for a consistent table
+  rank[v] = (uint32_t)(i - start);
+}
+
 // Third pass: both counters of every accessed row start at zero.
 __global__ void __launch_bounds__(256) gacco_shared_clear_kernel(const uint32_t *keys, uint64_t n, uint32_t sentinel,
                                                                  uint64_t *words) {
@@ -314,7 +329,7 @@ uint64_t radix_sort_scratch_words(uint64_t n) {
 }
 
 hipError_t gacco_prepare(hipStream_t s, const DevOp *ops, uint64_t n_ops, uint32_t sentinel, uint64_t *words,
-                         uint32_t *rank, uint32_t *scratch, Ctl *ctl, bool shared) {
+                         uint32_t *rank, uint32_t *scratch, Ctl *ctl, int mode) {
   hipLaunchKernelGGL(gacco_reset_kernel, dim3(1), dim3(64), 0, s, ctl);
   if (n_ops == 0) return hipGetLastError();
   // scratch: [ka | va | radix scratch: kb | vb | histogram | partial sums]
@@ -325,9 +340,15 @@ hipError_t gacco_prepare(hipStream_t s, const DevOp *ops, uint64_t n_ops, uint32
   while (bits < 32 && (sentinel >> bits) != 0) ++bits;
   hipError_t e = radix_sort_pairs(s, ka, va, n_ops, bits, rs, &sorted_k, &sorted_v);
   if (e != hipSuccess) return e;
-  if (!shared) {
+  if (mode != PREP_SHARED) {
     hipLaunchKernelGGL(gacco_lock_table_kernel, dim3(blocks), dim3(256), 0, s, sorted_k, sorted_v, n_ops, sentinel,
                        words, rank);
+    if (mode == PREP_LOCAL) {
+      // places within each row, and every accessed row's word starts at zero
+      hipLaunchKernelGGL(gacco_local_rank_kernel, dim3(blocks), dim3(256), 0, s, sorted_k, sorted_v, n_ops, sentinel,
+                         words, rank);
+      hipLaunchKernelGGL(gacco_shared_clear_kernel, dim3(blocks), dim3(256), 0, s, sorted_k, n_ops, sentinel, words);
+    }
     return hipGetLastError();
   }
   // the key/value pair the sort did not end in is free, and so is the histogram

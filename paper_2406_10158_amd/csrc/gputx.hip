@@ -49,7 +49,17 @@ __global__ void __launch_bounds__(256) gputx_fill_kernel(uint64_t *p, uint64_t n
 // ---------------------------------------------------------------------------
 // rank pass
 // ---------------------------------------------------------------------------
-template <int L, int K, bool STRICT>
+// Packed state (PACKED, batches of fewer than 2^20 transactions and 2^24
+// operations): a row's word holds its turn and its state together --
+// [63:40] place in the row's list whose turn it is, [39:20] largest rank + 1
+// of its accessors so far, [19:0] rank + 1 of its last writer.  The look that
+// finds the turn brings the state with it, and one store passes the row on
+// with its new state, so neither a separate load of the state nor an
+// ordering point before the release is needed.  Otherwise the state lives in
+// its own word (kstate) and the turn word holds sorted positions.
+constexpr uint64_t GX_M20 = (1ull << 20) - 1;
+
+template <int L, int K, bool STRICT, bool PACKED>
 __global__ void __launch_bounds__(MaxThreads<K>::value) gputx_rank_kernel(GputxArgs a) {
   constexpr int NW = L == 64 ? K : 1;
   static_assert(L == 64 || L * K <= 64, "operation sets of one word");
@@ -58,6 +68,7 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) gputx_rank_kernel(GputxA
   int64_t txn = -1;
   bool finished = false;
   uint32_t rowk[K], rk[K];
+  uint64_t gst[K];  // PACKED: the row's word as seen when its turn came
   Set lead = Set::zero(), granted = Set::zero();
   uint64_t ready_at = 0, progress_at = 0;
   uint32_t idle_polls = 0;
@@ -114,8 +125,10 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) gputx_rank_kernel(GputxA
       const uint32_t i = (uint32_t)t.tl + (uint32_t)(k * L);
       g[k] = false;
       if (act && lead.test(i) && !granted.test(i)) {
-        const uint64_t turn = ld_word(a.words + op_row(rowk[k]));
+        const uint64_t w = ld_word(a.words + op_row(rowk[k]));
+        const uint64_t turn = PACKED ? (w >> 40) : w;
         g[k] = turn == (uint64_t)rk[k];
+        if (PACKED && g[k]) gst[k] = w;
         if (!g[k] && (uint64_t)rk[k] > turn) {
           const uint64_t d = (uint64_t)rk[k] - turn;
           ahead = d < ahead ? d : ahead;
@@ -127,7 +140,29 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) gputx_rank_kernel(GputxA
     // every row has come to the transaction: its rank, the rows' new states,
     // then the rows move on
     const bool ready = act && granted == lead;
-    if (ballot(ready)) {
+    if (PACKED && ballot(ready)) {
+      uint64_t r1 = 1;  // the transaction's rank + 1: at least 1, else the largest of these
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (ready && lead.test((uint32_t)t.tl + (uint32_t)(k * L))) {
+          const uint64_t any1 = (gst[k] >> 20) & GX_M20, w1 = gst[k] & GX_M20;
+          const uint64_t c = op_written(rowk[k]) ? any1 + 1 : w1 + 1;
+          r1 = c > r1 ? c : r1;
+        }
+      }
+      r1 = t.max(r1);
+      if (STRICT) order_point<STRICT>();
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (ready && lead.test((uint32_t)t.tl + (uint32_t)(k * L))) {
+          const uint64_t any1 = (gst[k] >> 20) & GX_M20, w1 = gst[k] & GX_M20;
+          const uint64_t nany = any1 > r1 ? any1 : r1;
+          const uint64_t nw1 = op_written(rowk[k]) ? r1 : w1;
+          st_word(a.words + op_row(rowk[k]), (((uint64_t)rk[k] + 1) << 40) | (nany << 20) | nw1);
+        }
+      }
+      if (ready && t.tl == 0) a.txn_rank[txn] = (uint32_t)(r1 - 1);
+    } else if (!PACKED && ballot(ready)) {
       if (STRICT) order_point<STRICT>();
       else asm volatile("" ::: "memory");
       uint64_t st[K];
@@ -364,8 +399,10 @@ static hipError_t gputx_launch_one(hipStream_t s, int waves_per_wg, int grid, co
   *grid_used = grid;
   if (exec)
     hipLaunchKernelGGL((gputx_exec_kernel<L, K, STRICT>), dim3(grid), dim3(block), 0, s, a);
+  else if (a.packed)
+    hipLaunchKernelGGL((gputx_rank_kernel<L, K, STRICT, true>), dim3(grid), dim3(block), 0, s, a);
   else
-    hipLaunchKernelGGL((gputx_rank_kernel<L, K, STRICT>), dim3(grid), dim3(block), 0, s, a);
+    hipLaunchKernelGGL((gputx_rank_kernel<L, K, STRICT, false>), dim3(grid), dim3(block), 0, s, a);
   return hipGetLastError();
 }
 

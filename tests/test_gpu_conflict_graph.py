@@ -52,6 +52,8 @@ def run_exact(tabs, b, scheme="gacco", **params):
         ranks = oracle.kset_ranks(b)
         assert np.array_equal(out["serial_hi"].astype(np.int64), ranks)
         assert st["ksets"] == (int(ranks.max()) + 1 if n else 0)
+        # the rank state shares the turn word below 2^20 transactions and 2^24 operations
+        assert st["packed_state"] == int(n < (1 << 20) and b.total_ops < (1 << 24))
     assert np.array_equal(out["serial_lo"].astype(np.int64), np.arange(n))
     bad = np.nonzero(np.asarray(reads, np.int64) != exp_reads)[0]
     assert len(bad) == 0, f"{len(bad)} read values differ, first ops {bad[:5].tolist()}"
@@ -258,6 +260,14 @@ def test_cg_full_size_kv_config(scheme):
     out, reads, final, st = run_exact(tabs, b, scheme=scheme)
     print(f"{scheme} full: run_ms={st['run_ns']/1e6:.1f} prep_ms={st['prep_ns']/1e6:.2f} "
           f"kernel_ms={st['kernel_ns']/1e6:.1f}")
+
+
+def test_gputx_rank_state_in_its_own_word_for_large_batches():
+    # 2^20 + 1000 transactions: too many for the packed rank state, so the rank pass keeps
+    # the state in its own word next to a turn word of sorted positions
+    tabs, b = wl.kv_workload(n_rows=200_000, n_fields=2, n_txns=(1 << 20) + 1000, ops=2, theta=0.8, seed=79)
+    *_, st = run_exact(tabs, b, "gputx")
+    assert st["packed_state"] == 0 and st["ksets"] > 10
 
 
 @pytest.mark.parametrize("scheme", DETERMINISTIC)
