@@ -133,6 +133,39 @@ def test_edge_sizes(scheme):
     run_and_check(tabs3, b3, scheme, lanes_per_txn=64, waves_per_wg=2)
 
 
+@pytest.mark.parametrize("scheme", ["occ", "mvcc", "gacco", "gputx"])
+def test_maximum_total_rows(scheme):
+    # 2^28 rows in all (the limit): one table of 2^28 - 16 rows and one of 16. Row indices
+    # share a 32-bit word with the operation kind and flag bits, so the highest rows of both
+    # tables are hit on purpose (MVCC's version words and GPUTx's state words span them too).
+    n0 = (1 << 28) - 16
+    tabs = [np.arange(n0, dtype=np.int64).reshape(n0, 1), np.arange(32, dtype=np.int64).reshape(16, 2)]
+    rng = np.random.Generator(np.random.PCG64(90))
+    lengths, row, table, field, kind, arg = [], [], [], [], [], []
+    for _ in range(3_000):
+        picks = set()
+        while len(picks) < 4:
+            picks.add((0, n0 - 1 - int(rng.integers(0, 600))) if rng.random() < 0.7 else (1, int(rng.integers(0, 16))))
+        for t_, r_ in sorted(picks):
+            row.append(r_); table.append(t_); field.append(int(rng.integers(0, 2)) if t_ == 1 else 0)
+            k = int(rng.integers(0, 2)); kind.append(k); arg.append(int(rng.integers(-9, 10)) if k else 0)
+        lengths.append(4)
+    b = wl._pack(lengths, np.array(row, np.uint32), np.array(table, np.uint16), np.array(field, np.uint8),
+                 np.array(kind, np.uint8), np.array(arg, np.int64), {})
+    print(f"[gpu] maximum total rows {scheme}", flush=True)
+    out, reads, final, st = run_batch(tabs, b, scheme)
+    assert "error" not in st, st["error"]
+    assert np.all(out["status"] == oracle.COMMITTED)
+    if scheme in ("gacco", "gputx"):
+        exp_fin, exp_reads = oracle.id_order_expected(tabs, b)
+        assert np.array_equal(np.asarray(reads, np.int64), exp_reads)
+        assert all(np.array_equal(g, x) for g, x in zip(final, exp_fin))
+    else:
+        assert check(tabs, b, out, reads, final).ok
+    # the rows no transaction touched still hold their initial values (spot check of the low end)
+    assert np.array_equal(final[0][:1000, 0], np.arange(1000))
+
+
 @pytest.mark.parametrize("scheme", IMPLEMENTED)
 def test_strict_fences(scheme):
     b_ = binding()
