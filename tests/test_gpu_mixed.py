@@ -66,3 +66,25 @@ def test_mixed_kinds_latch_and_strict(scheme):
 def test_mixed_kinds_more_seeds(scheme):
     for seed in range(3000, 3004):
         _run(scheme, 16, seed=seed)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES + DETERMINISTIC)
+def test_mixed_kinds_sixteen_tables_and_256_fields(scheme):
+    # the table and field limits: 16 tables, one of them 256 fields wide
+    shapes = tuple((int(r), int(f)) for r, f in zip((5, 9, 17, 33, 64, 100, 7, 300, 50, 2, 400, 13, 80, 3, 256, 60),
+                                                   (1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 1, 2, 3, 256, 4, 5)))
+    tabs, b = wl.mixed_workload(shapes=shapes, n_txns=1_000, ops=(1, 16), theta=0.8, seed=4000)
+    assert len(tabs) == 16 and int(b.table.max()) == 15
+    wide = b.table == 13
+    assert wide.any() and int(b.field[wide].max()) > 200
+    print(f"[gpu] mixed 16 tables {scheme}", flush=True)
+    if scheme in DETERMINISTIC:
+        b_ = binding()
+        flags = b_.CC_RUN_SHARED_READS if scheme == "gacco_shared" else 0
+        out, reads, final, st = run_batch(tabs, b, "gputx" if scheme == "gputx" else "gacco", flags=flags)
+        assert "error" not in st, st["error"]
+        exp_fin, exp_reads = oracle.id_order_expected(tabs, b)
+        assert np.array_equal(np.asarray(reads, np.int64), exp_reads)
+        assert all(np.array_equal(np.asarray(g, np.int64), x) for g, x in zip(final, exp_fin))
+    else:
+        run_and_check(tabs, b, scheme)
