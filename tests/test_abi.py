@@ -170,3 +170,33 @@ def test_init_without_a_gpu_fails_cleanly(b):
     with pytest.raises(b.CCError) as e:
         b.cc_init(0)
     assert e.value.status == b.CC_E_NODEV
+
+
+def test_every_entry_point_rejects_a_null_context(b):
+    # no GPU needed: each call returns CC_E_INVAL before touching the device (cc_destroy(NULL) is a no-op)
+    lib = b.lib
+    u64 = ctypes.c_uint64()
+    u32 = ctypes.c_uint32()
+    buf = (ctypes.c_int64 * 8)()
+    params = b.run_params()
+    calls = {
+        "cc_create_table": lambda: lib.cc_create_table(None, 4, 1, ctypes.byref(u32)),
+        "cc_load": lambda: lib.cc_load(None, 0, ctypes.addressof(buf), 4, 0),
+        "cc_read_table": lambda: lib.cc_read_table(None, 0, ctypes.addressof(buf), 0),
+        "cc_submit_batch": lambda: lib.cc_submit_batch(None, None, 0, None, 0, 0, 0, ctypes.byref(u64)),
+        "cc_submit_batch_keyed": lambda: lib.cc_submit_batch_keyed(None, None, 0, None, 0, None, 0, 0, ctypes.byref(u64)),
+        "cc_create_index": lambda: lib.cc_create_index(None, 0, None, 0),
+        "cc_run": lambda: lib.cc_run(None, 1, ctypes.byref(params)),
+        "cc_fetch_outcomes": lambda: lib.cc_fetch_outcomes(None, 1, None, None, 0),
+        "cc_fetch_rows": lambda: lib.cc_fetch_rows(None, 1, ctypes.addressof(buf)),
+        "cc_set_arrivals": lambda: lib.cc_set_arrivals(None, 1, None, 0),
+        "cc_stats": lambda: lib.cc_stats(None, 1, None, 0),
+        "cc_release_batch": lambda: lib.cc_release_batch(None, 1),
+        "cc_device_info": lambda: lib.cc_device_info(None, None, None),
+        "cc_probe": lambda: lib.cc_probe(None, 0, 1 << 20, 1, 1, None),
+        "cc_init": lambda: lib.cc_init(None, None),
+    }
+    for name, call in calls.items():
+        assert call() == b.CC_E_INVAL, name
+    assert lib.cc_destroy(None) == b.CC_OK
+    assert isinstance(lib.cc_last_error(None), bytes)
