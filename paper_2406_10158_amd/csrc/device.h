@@ -156,6 +156,13 @@ __device__ __forceinline__ int64_t apply_op(uint32_t kind, int64_t pre, int64_t 
   }
 }
 
+// Largest workgroup a (lanes, ops-per-lane) variant is compiled for: more
+// register slots per lane leave room for fewer wavefronts.
+template <int K>
+struct MaxThreads {
+  static constexpr int value = K <= 1 ? 1024 : (K <= 4 ? 512 : 256);
+};
+
 // Per-lane operation slots of the transaction the team executes: lane j of
 // the team holds operations j, j+L, ..., j+(K-1)L.
 template <int K>
@@ -195,16 +202,49 @@ __device__ __forceinline__ int64_t slot_source(const Team<L> &t, const Slots<K> 
   return r;
 }
 
+// The same for every slot at once, through LDS: each lane writes its read
+// values slot-major (row k holds every thread's slot k), then reads each
+// WRITE_SLOT source from its lane and slot.  Used at 16 slots per lane, where
+// the K x K shuffles of slot_source need more registers than there are.
+// Only this wavefront reads what it wrote, and a wavefront's LDS operations
+// are performed in order, so wavefront-scope fences suffice.
+template <int L, int K>
+__device__ __forceinline__ void slot_sources_lds(const Team<L> &t, const Slots<K> &s, int64_t (&src_val)[K]) {
+  constexpr int T = MaxThreads<K>::value;
+  __shared__ int64_t xs[K * T];
+  const int me = (int)threadIdx.x;
+  const int team0 = me - t.lane + t.tb;  // thread index of the team's first lane
+#pragma unroll
+  for (int k = 0; k < K; ++k) xs[k * T + me] = s.x[k];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const bool slot = s.valid[k] && op_kind(s.rowk[k]) == CC_WRITE_SLOT;
+    // a source is an earlier operation of the transaction, so src < L * K
+    const uint32_t src = slot ? (uint32_t)(s.arg[k] & 0xFF) : 0u;
+    src_val[k] = slot ? xs[(int)(src / L) * T + team0 + (int)(src & (L - 1))] : 0;
+  }
+  // the next call's writes come after these reads
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Store the new values of a committing team's write operations.  Every lane
 // of the wavefront must call it (WRITE_SLOT sources move between lanes).
 template <int L, int K>
 __device__ __forceinline__ void install_values(const Team<L> &t, const Slots<K> &s, bool commit, const RunArgs &a) {
   if (a.has_slot) {
     int64_t src_val[K];
+    if constexpr (K >= 16) {
+      slot_sources_lds<L, K>(t, s, src_val);
+    } else {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      uint32_t src = (s.valid[k] && op_kind(s.rowk[k]) == CC_WRITE_SLOT) ? (uint32_t)(s.arg[k] & 0xFF) : 0u;
-      src_val[k] = slot_source<L, K>(t, s, src);
+      for (int k = 0; k < K; ++k) {
+        uint32_t src = (s.valid[k] && op_kind(s.rowk[k]) == CC_WRITE_SLOT) ? (uint32_t)(s.arg[k] & 0xFF) : 0u;
+        src_val[k] = slot_source<L, K>(t, s, src);
+      }
     }
 #pragma unroll
     for (int k = 0; k < K; ++k)

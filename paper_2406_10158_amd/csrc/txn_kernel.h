@@ -7,13 +7,6 @@
 
 namespace cce {
 
-// Largest workgroup a (lanes, ops-per-lane) variant is compiled for: more
-// register slots per lane leave room for fewer wavefronts.
-template <int K>
-struct MaxThreads {
-  static constexpr int value = K <= 1 ? 1024 : (K <= 4 ? 512 : 256);
-};
-
 template <int L, int K, int SCHEME, bool STRICT, bool LATCH>
 __device__ __forceinline__ int attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a, uint32_t txn,
                                        bool retry, bool resume, bool may_wait, uint64_t *hi, uint64_t *lo) {
