@@ -346,6 +346,7 @@ def main():
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--defer-after", type=int, default=0, help="attempts before a transaction is deferred to the next pass (0: the library default)")
+    ap.add_argument("--backoff-ns", type=int, default=0, help="back-off base (OCC family) or poll interval per queued access (GaccO, GPUTx); 0: the library default, 200 ns")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probes", action="store_true", help="only run the memory micro-benchmarks")
@@ -387,7 +388,7 @@ def main():
     eng = binding.Engine(tables, device=0, stream=stream.cuda_stream)
     bid = eng.submit(batch, args.scheme)
     params = dict(lanes_per_txn=args.lanes, waves_per_wg=args.waves, grid=args.grid, flags=args.flags,
-                  defer_after=args.defer_after)
+                  defer_after=args.defer_after, backoff_ns=args.backoff_ns)
     for _ in range(args.warmup):
         eng.run(bid, **params)
     torch.cuda.synchronize()
@@ -488,7 +489,7 @@ def main():
         "config": {"workload": wl_name, "rows": args.rows, "fields": args.fields, "txns": args.txns,
                    "ops_per_txn": args.ops, "theta": args.theta, "read_ratio": 0.5, "scheme": args.scheme,
                    "lanes_per_txn": args.lanes, "waves_per_wg": args.waves, "grid": args.grid,
-                   "defer_after": args.defer_after, "global_batch": args.txns, "parallelism": "single GPU"},
+                   "defer_after": args.defer_after, "backoff_ns": args.backoff_ns, "global_batch": args.txns, "parallelism": "single GPU"},
         "p50_commit_latency_ms": round(float(np.median(p50)) / 1e6, 4),
         "p99_commit_latency_ms": round(float(np.median(p99)) / 1e6, 4),
         "abort_rate": round((float(np.mean(attempts)) - batch.n_txns) / batch.n_txns, 4),
