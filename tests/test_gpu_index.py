@@ -159,3 +159,31 @@ def test_keyed_full_size_kv_config():
         rep = check(tabs, b, out, reads, final)
         assert rep.ok, rep
         print(f"keyed full size {method}: index_ms={st['index_ns']/1e6:.3f} run_ms={st['run_ns']/1e6:.1f}")
+
+
+@pytest.mark.parametrize("scheme", ["occ", "tictoc", "2pl_nw"])
+def test_keyed_batches_in_epoch_and_serve_modes(scheme):
+    # lookups run once per run before either mode's kernels; the resolved batch is then
+    # checked like any other
+    b_ = binding()
+    tabs, b = wl.kv_workload(n_rows=30_000, n_fields=2, n_txns=8_000, ops=(2, 24), theta=0.8, seed=41)
+    keys = wl.index_keys(30_000, seed=41)
+    op_keys = wl.keyed_ops(b, [keys])
+    exp_rows = oracle.resolve_keys([keys], b, op_keys)
+    rb = oracle.with_rows(b, exp_rows)
+    arrivals = np.sort(np.random.Generator(np.random.PCG64(42)).integers(0, 2_000_000, b.n_txns)).astype(np.int64)
+    for mode in ("epoch", "serve"):
+        with b_.Engine(tabs) as eng:
+            eng.create_index(0, keys)
+            bid = eng.submit_keyed(b, op_keys, scheme)
+            if mode == "serve":
+                b_.cc_set_arrivals(eng.ctx, bid, arrivals)
+            st = eng.run(bid, mode=b_.CC_MODE_EPOCH if mode == "epoch" else b_.CC_MODE_SERVE,
+                         flags=b_.CC_RUN_INDEX_TREE)
+            out, reads = eng.outcomes(bid, b.n_txns, b.total_ops)
+            rows = eng.rows(bid, b.total_ops)
+            final = eng.tables()
+        assert np.array_equal(rows.astype(np.int64), exp_rows), mode
+        rep = check(tabs, rb, out, reads, final)
+        assert rep.ok, (mode, rep)
+        assert st["committed"] == b.n_txns and st["index_ns"] > 0

@@ -89,3 +89,13 @@ def test_serve_needs_arrivals():
         assert e.value.status == bb.CC_E_STATE
         with pytest.raises(bb.CCError):
             bb.cc_set_arrivals(eng.ctx, bid, arr[::-1].copy() if len(arr) > 1 else np.array([-1]))
+
+
+@pytest.mark.parametrize("scheme", ["occ", "tictoc", "2pl_wd"])
+def test_serve_stream_with_latched_control_words(scheme):
+    # the latch variants under continuous admission
+    bb = binding()
+    tabs, b, arr, m = wl.serve_stream(4_000, 2e6, kv_rows=100_000, seed=33)
+    out, reads, final, st = serve(tabs, b, arr, scheme, flags=bb.CC_RUN_LATCH)
+    assert check(tabs, b, out, reads, final).ok
+    assert np.all(out["commit_ns"] + 10 >= arr)
