@@ -113,14 +113,13 @@ __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool a
   uint32_t blk = ~0u;
   bool pre_fail = false;
   if (ballot(active && precheck)) {
-    // R0, by default from a transaction's third attempt on: load every row's
-    // word and give up before taking any lock if one is held, so that
+    // R0, by default from a transaction's second attempt on: load every
+    // row's word and give up before taking any lock if one is held, so that
     // failing attempts never hold rows (or write their lines) while they
     // fail elsewhere.  Read-only rows keep the word loaded here, exactly as
-    // R1 would load it.  Early attempts skip it: until a transaction has
-    // failed repeatedly there is little sign of contention, and at low
-    // contention the extra round (which its whole wavefront waits for) costs
-    // more than it saves.
+    // R1 would load it.  First attempts skip it: until a transaction has
+    // failed there is no sign of contention, and at low contention the extra
+    // round (which its whole wavefront waits for) costs more than it saves.
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (active && precheck && s.valid[k] && op_leader(s.rowk[k])) {

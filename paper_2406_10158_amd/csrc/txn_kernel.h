@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
     }
     uint64_t key_hi = 0, key_lo = 0;
     s.block = ~0u;
-    const int r = attempt<L, K, SCHEME, STRICT, LATCH>(t, s, active, a, (uint32_t)(txn < 0 ? 0 : txn), attempts >= 2,
+    const int r = attempt<L, K, SCHEME, STRICT, LATCH>(t, s, active, a, (uint32_t)(txn < 0 ? 0 : txn), attempts >= 1,
                                                 keep, waits < a.wd_wait_limit, &key_hi, &key_lo);
     if (t.tl == 0 && txn >= 0) {
       const uint64_t dt = wall_clock64() - now;
