@@ -572,13 +572,31 @@ __device__ __forceinline__ uint64_t tt_rts(uint64_t w) { return tt_wts(w) + ((w 
 
 template <int L, int K, bool STRICT, bool LATCH>
 __device__ __forceinline__ int tictoc_attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a,
-                                              uint64_t *hi, uint64_t *lo) {
+                                              bool precheck, uint64_t *hi, uint64_t *lo) {
   bool fail = false;
   uint32_t blk = ~0u;
+  bool pre_fail = false;
+  if (ballot(active && precheck)) {
+    // R0 (as OCC's, by default from a transaction's second attempt on): load
+    // every row's word and give up before locking if one is held; read-only
+    // rows keep the word loaded here, exactly as R1 would load it
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (active && precheck && s.valid[k] && op_leader(s.rowk[k])) {
+        const uint64_t o = ld_word(a.words + op_row(s.rowk[k]));
+        s.v[k] = o;
+        if ((o & TT_LOCK) && blk == ~0u) blk = op_row(s.rowk[k]);
+        fail |= (o & TT_LOCK) != 0;
+      }
+    }
+    order_point<STRICT>();
+    pre_fail = t.any(fail);
+  }
+  const bool go = active && !pre_fail;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     s.got[k] = false;
-    if (active && s.valid[k] && op_leader(s.rowk[k])) {
+    if (go && s.valid[k] && op_leader(s.rowk[k]) && (!precheck || op_written(s.rowk[k]))) {
       uint64_t *w = a.words + op_row(s.rowk[k]);
       if (op_written(s.rowk[k])) {
         const uint64_t old = w_or<LATCH, STRICT>(a, w, TT_LOCK);

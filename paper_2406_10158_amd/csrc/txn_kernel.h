@@ -10,16 +10,14 @@ namespace cce {
 template <int L, int K, int SCHEME, bool STRICT, bool LATCH>
 __device__ __forceinline__ int attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a, uint32_t txn,
                                        bool retry, bool resume, bool may_wait, uint64_t *hi, uint64_t *lo) {
-  if constexpr (SCHEME == CC_OCC) {
-    const bool precheck = a.precheck == 2 || (a.precheck == 1 && retry);
-    return occ_attempt<L, K, STRICT, LATCH>(t, s, active, a, precheck, hi, lo);
-  }
+  const bool precheck = a.precheck == 2 || (a.precheck == 1 && retry);
+  if constexpr (SCHEME == CC_OCC) return occ_attempt<L, K, STRICT, LATCH>(t, s, active, a, precheck, hi, lo);
   else if constexpr (SCHEME == CC_2PL_NW) return tpl_attempt<L, K, STRICT, LATCH>(t, s, active, a, txn, hi, lo);
   else if constexpr (SCHEME == CC_2PL_WD)
     return tplwd_attempt<L, K, STRICT, LATCH>(t, s, active, a, txn, resume, may_wait, hi, lo);
   else if constexpr (SCHEME == CC_TO) return to_attempt<L, K, STRICT, false, LATCH>(t, s, active, a, hi, lo);
   else if constexpr (SCHEME == CC_MVCC) return to_attempt<L, K, STRICT, true, LATCH>(t, s, active, a, hi, lo);
-  else return tictoc_attempt<L, K, STRICT, LATCH>(t, s, active, a, hi, lo);
+  else return tictoc_attempt<L, K, STRICT, LATCH>(t, s, active, a, precheck, hi, lo);
 }
 
 // ---------------------------------------------------------------------------
