@@ -183,11 +183,11 @@ enum cc_mode { CC_MODE_PLAIN = 0, CC_MODE_EPOCH = 1, CC_MODE_SERVE = 2 };
                                      transaction holds, look at that row's word between attempts and
                                      retry once it is free.  Disabled: teams of one wavefront that block
                                      each other retry in lockstep and can livelock in the final pass. */
-#define CC_RUN_PRECHECK 0x8u      /* OCC and TicToc: an extra first round loads every row's word and aborts before
+#define CC_RUN_PRECHECK 0x8u      /* OCC, TicToc, TO and MVCC: an extra first round loads every row's word and aborts before
                                      taking any lock if one is held -- on every attempt.  By default it
                                      runs from a transaction's second attempt on (a failure is the
                                      sign of contention) */
-#define CC_RUN_NO_PRECHECK 0x10u  /* OCC and TicToc: never run the pre-check round */
+#define CC_RUN_NO_PRECHECK 0x10u  /* OCC, TicToc, TO and MVCC: never run the pre-check round */
 #define CC_RUN_LATCH 0x40u        /* latch variants of the non-deterministic schemes (paper Section 4.2,
                                      Exp-7): a 32-bit latch per row guards its control word, and every
                                      update of the word is a critical section [latch, load, store,

@@ -412,11 +412,29 @@ constexpr int MVCC_MAX_WALK = 1 << 16;
 
 template <int L, int K, bool STRICT, bool MV, bool LATCH>
 __device__ __forceinline__ int to_attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a,
-                                          uint64_t *hi, uint64_t *lo) {
-  const uint64_t ts = t.claim(&a.ctl->ticket, active, 1) + 1;
-  const bool overflow = active && ts > TO_MASK31;
-  bool fail = overflow;
+                                          bool precheck, uint64_t *hi, uint64_t *lo) {
   uint32_t blk = ~0u;
+  bool pre_fail = false;
+  if (ballot(active && precheck)) {
+    // R0 (as OCC's, by default from a transaction's second attempt on): give
+    // up before taking a timestamp or marking any row if a row is dirty (an
+    // uncommitted write holds it), which R1 would abort on anyway
+    bool busy = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (active && precheck && s.valid[k] && op_leader(s.rowk[k])) {
+        const uint64_t o = ld_word(a.words + op_row(s.rowk[k]));
+        if ((o & TO_DIRTY) && blk == ~0u) blk = op_row(s.rowk[k]);
+        busy |= (o & TO_DIRTY) != 0;
+      }
+    }
+    order_point<STRICT>();
+    pre_fail = t.any(busy);
+  }
+  const bool go = active && !pre_fail;
+  const uint64_t ts = t.claim(&a.ctl->ticket, go, 1) + 1;
+  const bool overflow = go && ts > TO_MASK31;
+  bool fail = overflow || (active && pre_fail);
   bool old_ver[K];  // MVCC: this op reads a version older than the current one
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -425,7 +443,7 @@ __device__ __forceinline__ int to_attempt(const Team<L> &t, Slots<K> &s, bool ac
     const bool lead = op_leader(s.rowk[k]);
     // MVCC followers of read rows also look at the word, to pick the version
     const bool look = lead || (MV && !op_written(s.rowk[k]));
-    if (active && !overflow && s.valid[k] && look) {
+    if (go && !overflow && s.valid[k] && look) {
       uint64_t *wp = a.words + op_row(s.rowk[k]);
       uint64_t w = ld_word(wp);
       bool done = false, bad = false;

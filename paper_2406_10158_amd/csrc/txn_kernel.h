@@ -15,8 +15,8 @@ __device__ __forceinline__ int attempt(const Team<L> &t, Slots<K> &s, bool activ
   else if constexpr (SCHEME == CC_2PL_NW) return tpl_attempt<L, K, STRICT, LATCH>(t, s, active, a, txn, hi, lo);
   else if constexpr (SCHEME == CC_2PL_WD)
     return tplwd_attempt<L, K, STRICT, LATCH>(t, s, active, a, txn, resume, may_wait, hi, lo);
-  else if constexpr (SCHEME == CC_TO) return to_attempt<L, K, STRICT, false, LATCH>(t, s, active, a, hi, lo);
-  else if constexpr (SCHEME == CC_MVCC) return to_attempt<L, K, STRICT, true, LATCH>(t, s, active, a, hi, lo);
+  else if constexpr (SCHEME == CC_TO) return to_attempt<L, K, STRICT, false, LATCH>(t, s, active, a, precheck, hi, lo);
+  else if constexpr (SCHEME == CC_MVCC) return to_attempt<L, K, STRICT, true, LATCH>(t, s, active, a, precheck, hi, lo);
   else return tictoc_attempt<L, K, STRICT, LATCH>(t, s, active, a, precheck, hi, lo);
 }
 
