@@ -313,13 +313,30 @@ def check_run(init_tables, batch, status, serial_hi, serial_lo, got_reads, got_f
     return rep
 
 
+OE_WAREHOUSE_YTD = "warehouse ytd != sum of district ytd"
+OE_CONSERVED = "customer balance + warehouse ytd not conserved"
+OE_NEXT_O_ID = "district next_o_id growth != committed new-orders"
+OE_ORDER_CNT = "stock order_cnt growth != committed order lines"
+OE_SLOTS = "order slots: committed order ids of a district are not exactly its counter's range"
+OE_SLOTS_UNTOUCHED = "order slots: a slot of an uncommitted new-order (or of no transaction) was written"
+
+
 def order_entry_invariants(init_tables, final_tables, batch, committed) -> list:
     """Closed-form invariants of the order-entry workload; returns a list of violations.
+
+    Each holds for every serial order of the committed transactions, so none
+    needs the run's reported order (TPC-C's consistency conditions for the two
+    transactions the paper runs, Section 4.1 "Benchmark Selection"):
 
     * warehouse ytd == sum of its districts' ytd (payments add the same amount to both);
     * sum(customer balance) + sum(warehouse ytd) is unchanged (payments move money);
     * district next-order-id growth == committed new-orders of that district;
-    * total stock order-count growth == committed order lines.
+    * total stock order-count growth == committed order lines;
+    * the order slots of a district's k committed new-orders hold exactly the
+      counter values init .. init+k-1, each once, because each new-order's
+      order id is the pre-image of its district counter; slots of new-orders
+      that did not commit keep their initial values.
+    Every violation is reported with its own message (the OE_* constants).
     """
     from paper_2406_10158_amd import workload as wl  # table/field numbering only
     committed = np.asarray(committed, bool)
@@ -331,19 +348,37 @@ def order_entry_invariants(init_tables, final_tables, batch, committed) -> list:
     W = wh.shape[0]
     dsum = di[:, wl.D_YTD].reshape(W, wl.DISTRICTS_PER_W).sum(axis=1)
     if not np.array_equal(wh[:, wl.W_YTD], dsum):
-        out.append("warehouse ytd != sum of district ytd")
+        out.append(OE_WAREHOUSE_YTD)
     if cu[:, wl.C_BALANCE].sum() + wh[:, wl.W_YTD].sum() != cu0[:, wl.C_BALANCE].sum() + wh0[:, wl.W_YTD].sum():
-        out.append("customer balance + warehouse ytd not conserved")
-    is_no = np.asarray(batch.meta["is_new_order"], bool)
+        out.append(OE_CONSERVED)
     txn_of_op = np.repeat(np.arange(batch.n_txns), batch.n_ops.astype(np.int64))
     dop = (batch.table == wl.T_DISTRICT) & (batch.field == wl.D_NEXT_O_ID) & committed[txn_of_op]
     per_d = np.bincount(batch.row[dop].astype(np.int64), minlength=di.shape[0])
     if not np.array_equal(di[:, wl.D_NEXT_O_ID] - di0[:, wl.D_NEXT_O_ID], per_d):
-        out.append("district next_o_id growth != committed new-orders")
+        out.append(OE_NEXT_O_ID)
     lines = int(((batch.table == wl.T_ORDER_LINE) & (batch.field == wl.OL_AMOUNT) & committed[txn_of_op]).sum())
     if int(st[:, wl.S_ORDER_CNT].sum() - st0[:, wl.S_ORDER_CNT].sum()) != lines:
-        out.append("stock order_cnt growth != committed order lines")
-    if int(committed[is_no].sum()) != int(((batch.table == wl.T_ORDER) & (batch.field == wl.O_ID)
-                                           & committed[txn_of_op]).sum()):
-        out.append("order slot count != committed new-orders")
+        out.append(OE_ORDER_CNT)
+    # order slots: the transaction's district (its next-order-id op) and its slot row (its O_ID op)
+    od0, od = init_tables[wl.T_ORDER], np.asarray(final_tables[wl.T_ORDER], np.int64)
+    d_of = np.full(batch.n_txns, -1, np.int64)
+    m = (batch.table == wl.T_DISTRICT) & (batch.field == wl.D_NEXT_O_ID)
+    d_of[txn_of_op[m]] = batch.row[m]
+    slot_of = np.full(batch.n_txns, -1, np.int64)
+    m = (batch.table == wl.T_ORDER) & (batch.field == wl.O_ID)
+    slot_of[txn_of_op[m]] = batch.row[m]
+    owner = (slot_of >= 0) & (d_of >= 0)
+    ok = True
+    for d in np.unique(d_of[owner & committed]).tolist():
+        got = np.sort(od[slot_of[owner & committed & (d_of == d)], wl.O_ID])
+        want = np.arange(di0[d, wl.D_NEXT_O_ID], di0[d, wl.D_NEXT_O_ID] + len(got), dtype=np.int64)
+        if not np.array_equal(got, want):
+            ok = False
+            break
+    if not ok:
+        out.append(OE_SLOTS)
+    written = np.zeros(od.shape[0], bool)
+    written[slot_of[owner & committed]] = True
+    if not np.array_equal(od[~written], od0[~written]):
+        out.append(OE_SLOTS_UNTOUCHED)
     return out

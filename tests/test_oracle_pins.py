@@ -174,12 +174,65 @@ def test_order_entry_invariants_on_serial_execution():
     fin, _ = oracle.serial_execute(tabs, b)
     committed = np.ones(b.n_txns, bool)
     assert oracle.order_entry_invariants(tabs, fin, b, committed) == []
+    # any other serial order satisfies them too (they need no order)
+    fin2, _ = oracle.replay(tabs, b, np.random.default_rng(1).permutation(b.n_txns))
+    assert oracle.order_entry_invariants(tabs, fin2, b, committed) == []
+
+
+def _oe_committed_new_order(b, seed=0):
+    """A committed new-order transaction's district row and order-slot row."""
+    t = int(np.nonzero(b.meta["is_new_order"])[0][seed])
+    s = b.txn_slice(t)
+    d = int(b.row[s][(b.table[s] == wl.T_DISTRICT) & (b.field[s] == wl.D_NEXT_O_ID)][0])
+    slot = int(b.row[s][(b.table[s] == wl.T_ORDER) & (b.field[s] == wl.O_ID)][0])
+    return t, d, slot
+
+
+def _plant(fin, table, row, field, delta=None, value=None):
     bad = [t.copy() for t in fin]
-    bad[wl.T_WAREHOUSE][0, wl.W_YTD] += 1
-    assert oracle.order_entry_invariants(tabs, bad, b, committed)
-    bad = [t.copy() for t in fin]
-    bad[wl.T_STOCK][0, wl.S_ORDER_CNT] += 1
-    assert oracle.order_entry_invariants(tabs, bad, b, committed)
+    if value is not None:
+        bad[table][row, field] = value
+    else:
+        bad[table][row, field] += delta
+    return bad
+
+
+def test_order_entry_invariants_flag_each_planted_error_alone():
+    # each planted error changes exactly one quantity, and exactly that invariant's message comes back
+    tabs, b = wl.order_entry_workload(2, 400, seed=6)
+    fin, _ = oracle.serial_execute(tabs, b)
+    ok = np.ones(b.n_txns, bool)
+    inv = lambda tables, committed=ok: oracle.order_entry_invariants(tabs, tables, b, committed)
+    assert inv(fin) == []
+    # a district's ytd off by one: warehouse ytd no longer equals its districts' sum (money is still conserved)
+    assert inv(_plant(fin, wl.T_DISTRICT, 3, wl.D_YTD, 1)) == [oracle.OE_WAREHOUSE_YTD]
+    # a customer's balance off by one: the conservation sum moves, nothing else does
+    assert inv(_plant(fin, wl.T_CUSTOMER, 17, wl.C_BALANCE, -1)) == [oracle.OE_CONSERVED]
+    # a warehouse ytd and one of its districts both off by one: both sums move together
+    both = _plant(_plant(fin, wl.T_WAREHOUSE, 1, wl.W_YTD, 5), wl.T_DISTRICT, 12, wl.D_YTD, 5)
+    assert inv(both) == [oracle.OE_CONSERVED]
+    # a district counter one too high
+    t, d, slot = _oe_committed_new_order(b)
+    assert inv(_plant(fin, wl.T_DISTRICT, d, wl.D_NEXT_O_ID, 1)) == [oracle.OE_NEXT_O_ID]
+    # a stock order count one too high
+    assert inv(_plant(fin, wl.T_STOCK, 999, wl.S_ORDER_CNT, 1)) == [oracle.OE_ORDER_CNT]
+    # a committed order slot holding another order's id (a duplicate in its district)
+    _, d2, slot2 = _oe_committed_new_order(b, 1)
+    twins = [i for i in range(1, 40) if _oe_committed_new_order(b, i)[1] == d]
+    assert twins, "the generator put a second new-order in this district"
+    _, _, slot_b = _oe_committed_new_order(b, twins[0])
+    dup = _plant(fin, wl.T_ORDER, slot_b, wl.O_ID, value=int(fin[wl.T_ORDER][slot, wl.O_ID]))
+    assert inv(dup) == [oracle.OE_SLOTS]
+    # an order slot written although its transaction did not commit: mark one new-order uncommitted
+    # and undo its other effects by replaying the rest, then write its slot anyway
+    keep = np.ones(b.n_txns, bool)
+    keep[t] = False
+    fin_k, _ = oracle.replay(tabs, b, np.nonzero(keep)[0])
+    assert inv(fin_k, keep) == []
+    stray = _plant(fin_k, wl.T_ORDER, slot, wl.O_C_ID, value=12345)
+    assert inv(stray, keep) == [oracle.OE_SLOTS_UNTOUCHED]
+    # an order id one too high in a committed slot: the district's ids are no longer its counter's range
+    assert inv(_plant(fin, wl.T_ORDER, slot, wl.O_ID, 1)) == [oracle.OE_SLOTS]
 
 
 def test_order_entry_slot_values_follow_district_counter():
