@@ -34,6 +34,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "perkey.c")]
 _SO = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -45,11 +46,11 @@ _P = ctypes.c_void_p
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc into oracle/liboracle.so."""
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+    """Compile the oracle with gcc (OpenMP for the per-key checker) into oracle/liboracle.so."""
+    if force or not os.path.exists(_SO) or any(os.path.getmtime(_SO) < os.path.getmtime(f) for f in _SRCS):
         tmp = _SO + ".tmp"
-        subprocess.run(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC", _SRC, "-o", tmp],
-                       check=True)
+        subprocess.run(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fopenmp", "-shared", "-fPIC", *_SRCS,
+                        "-o", tmp], check=True)
         os.replace(tmp, _SO)
     return _SO
 
@@ -65,6 +66,9 @@ def _load():
         lib.oracle_bruteforce.restype = ctypes.c_int64
         lib.oracle_bruteforce.argtypes = [ctypes.c_uint32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                           ctypes.c_uint64, _P, ctypes.c_int, _P, ctypes.c_uint64]
+        lib.oracle_perkey_check.restype = ctypes.c_int
+        lib.oracle_perkey_check.argtypes = [ctypes.c_uint32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                            ctypes.c_uint64, ctypes.c_uint64, _P, _P, _P, _P, ctypes.c_int, _P]
         _lib = lib
     return _lib
 
@@ -89,7 +93,7 @@ def _table_args(tables):
 
 
 _ERR = {-2: "row/field/table out of range", -3: "unknown op kind", -4: "WRITE_SLOT source not earlier",
-        -5: "out of memory", -6: "bad argument"}
+        -5: "out of memory", -6: "bad argument", -7: "duplicate serial keys among committed transactions"}
 
 
 def replay(tables, batch, order):
@@ -260,6 +264,7 @@ class CheckReport:
     table_mismatches: int = 0
     closed_form_ok: bool | None = None
     problems: list = field(default_factory=list)
+    threads: int = 1
 
     def __str__(self):
         return (f"ok={self.ok} committed={self.n_committed} read_mismatch={self.read_mismatches} "
@@ -382,3 +387,48 @@ def order_entry_invariants(init_tables, final_tables, batch, committed) -> list:
     if not np.array_equal(od[~written], od0[~written]):
         out.append(OE_SLOTS_UNTOUCHED)
     return out
+
+
+def check_run_perkey(init_tables, batch, status, serial_hi, serial_lo, got_reads, got_final,
+                     require_all_committed=True, threads=0) -> CheckReport:
+    """``check_run``'s question answered cell by cell on all host threads (C + OpenMP, ``perkey.c``).
+
+    Every operation changes one cell as a function of that cell's previous
+    value (a WRITE_SLOT also of the value its source operation reported, which
+    is checked on the source's own cell), so the history of each cell can be
+    replayed on its own, in serial-key order, and the cells in parallel.  A
+    run passes here exactly when the serial replay of ``check_run`` accepts
+    it.  ``threads`` <= 0: OpenMP's default (OMP_NUM_THREADS, else all cores).
+    The report's ``problems`` name the lowest mismatching op and cell.
+    """
+    lib = _load()
+    status = np.ascontiguousarray(status, np.uint32)
+    committed = status == COMMITTED
+    rep = CheckReport(ok=True, n_committed=int(committed.sum()))
+    if require_all_committed and not committed.all():
+        rep.ok = False
+        rep.problems.append(f"{int((~committed).sum())} transactions did not commit")
+    init, n_rows, n_fields, ptrs = _table_args(init_tables)
+    fin, _, _, fptrs = _table_args(got_final)
+    arrs = _batch_arrays(batch)
+    hi = np.ascontiguousarray(serial_hi, np.uint64)
+    lo = np.ascontiguousarray(serial_lo, np.uint64)
+    reads = np.ascontiguousarray(got_reads, np.int64)
+    res = np.zeros(6, np.int64)
+    rc = lib.oracle_perkey_check(len(init), _ptr(n_rows), _ptr(n_fields), ptrs, fptrs, *[_ptr(a) for a in arrs],
+                                 batch.n_txns, batch.total_ops, _ptr(status), _ptr(hi), _ptr(lo), _ptr(reads),
+                                 int(threads), _ptr(res))
+    if rc == -7:
+        rep.ok = False
+        rep.problems.append(_ERR[-7])
+        return rep
+    if rc != 0:
+        raise ValueError(f"oracle_perkey_check: {_ERR.get(rc, rc)}")
+    rep.read_mismatches, rep.table_mismatches = int(res[0]), int(res[1])
+    rep.threads = int(res[5])
+    if res[2] >= 0:
+        rep.problems.append(f"op {int(res[2])}: read value differs from its cell's replay")
+    if res[1]:
+        rep.problems.append(f"{int(res[1])} cells differ from their replay (lowest touched: {int(res[3])})")
+    rep.ok = rep.ok and rep.read_mismatches == 0 and rep.table_mismatches == 0
+    return rep

@@ -6,7 +6,8 @@
 * brute force: a set of mutually disjoint transactions matches all k! orders, classic
   non-serializable outcomes (lost update, write skew) match none;
 * planted errors in a run's outcome are detected by ``check_run``;
-* order-entry invariants hold on a serial execution and catch a perturbed table.
+* order-entry invariants hold on a serial execution, and each one flags a planted error of its own;
+* the per-key parallel checker accepts and rejects exactly what the serial replay does.
 """
 import json
 import math
@@ -459,3 +460,93 @@ def test_literal_per_item_rank_rule_can_merge_conflicting_transactions():
             seen[item] = seen.get(item, 0) + 1
         lit.append(r)
     assert lit[4] == lit[5] == 2 and _conflict(_accesses(b, 4), _accesses(b, 5))
+
+
+# ---------------------------------------------------------------------------
+# Per-key parallel checker (oracle/perkey.c): each cell's history replayed on
+# its own, cells in parallel.  It must accept and reject exactly the runs the
+# serial replay accepts and rejects, at any thread count.
+# ---------------------------------------------------------------------------
+def _both(tabs, b, status, hi, lo, reads, fin, threads=0, **kw):
+    a = oracle.check_run(tabs, b, status, hi, lo, reads, fin, **kw)
+    p = oracle.check_run_perkey(tabs, b, status, hi, lo, reads, fin, threads=threads, **kw)
+    return a, p
+
+
+@pytest.mark.parametrize("which", ["tiny", "kv_hot", "order_entry", "mixed"])
+def test_perkey_checker_accepts_valid_runs_like_the_serial_replay(which):
+    tabs, b = {"tiny": lambda: wl.tiny_workload(seed=3),
+               "kv_hot": lambda: wl.kv_workload(n_rows=3_000, n_fields=4, n_txns=20_000, ops=16, theta=0.9, seed=4),
+               "order_entry": lambda: wl.order_entry_workload(2, 800, seed=7),
+               "mixed": lambda: wl.mixed_workload(seed=5)}[which]()
+    order = np.random.default_rng(11).permutation(b.n_txns)
+    status, hi, lo, reads, fin = _fake_run(tabs, b, order)
+    for threads in (1, 3, 8):
+        a, p = _both(tabs, b, status, hi, lo, reads, fin, threads=threads)
+        assert a.ok and p.ok, (a, p)
+        assert p.threads == threads
+
+
+def test_perkey_checker_flags_planted_errors_with_exact_counts():
+    # READ / ADD batches: a planted read error is one read mismatch, a changed cell one cell mismatch
+    tabs, b = wl.kv_workload(n_rows=2_000, n_fields=3, n_txns=5_000, ops=8, theta=0.9, seed=8)
+    order = np.random.default_rng(2).permutation(b.n_txns)
+    status, hi, lo, reads, fin = _fake_run(tabs, b, order)
+    r2 = reads.copy(); r2[777] += 1
+    a, p = _both(tabs, b, status, hi, lo, r2, fin)
+    assert (a.read_mismatches, a.table_mismatches) == (1, 0) == (p.read_mismatches, p.table_mismatches)
+    touched = (int(b.row[10]), int(b.field[10]))
+    f2 = [fin[0].copy()]; f2[0][touched] += 5
+    a, p = _both(tabs, b, status, hi, lo, reads, f2)
+    assert a.table_mismatches == 1 == p.table_mismatches and a.read_mismatches == 0 == p.read_mismatches
+    used = np.zeros((2_000, 3), bool); used[b.row, b.field] = True
+    r, f = map(int, np.argwhere(~used)[0])
+    f3 = [fin[0].copy()]; f3[0][r, f] -= 1  # a cell no transaction touched
+    a, p = _both(tabs, b, status, hi, lo, reads, f3)
+    assert a.table_mismatches == 1 == p.table_mismatches
+    # duplicate serial keys, a swapped order, an uncommitted transaction
+    lo2 = lo.copy(); lo2[order[1]] = lo2[order[0]]
+    a, p = _both(tabs, b, status, hi, lo2, reads, fin)
+    assert not a.ok and not p.ok
+    lo3 = lo.copy(); lo3[order[0]], lo3[order[-1]] = lo[order[-1]], lo[order[0]]
+    a, p = _both(tabs, b, status, hi, lo3, reads, fin)
+    assert not a.ok and not p.ok
+    s2 = status.copy(); s2[3] = 0
+    a, p = _both(tabs, b, s2, hi, lo, reads, fin)
+    assert not a.ok and not p.ok
+
+
+def test_perkey_checker_agrees_with_the_serial_replay_on_random_corruptions():
+    tabs, b = wl.order_entry_workload(1, 400, seed=12)
+    order = np.random.default_rng(3).permutation(b.n_txns)
+    status, hi, lo, reads, fin = _fake_run(tabs, b, order)
+    rng = np.random.default_rng(4)
+    for _ in range(40):
+        r2, f2 = reads.copy(), [t.copy() for t in fin]
+        if rng.random() < 0.5:
+            r2[int(rng.integers(0, b.total_ops))] += int(rng.integers(1, 5))
+        else:
+            t = int(rng.integers(0, len(f2)))
+            f2[t][int(rng.integers(0, f2[t].shape[0])), int(rng.integers(0, f2[t].shape[1]))] += 1
+        a, p = _both(tabs, b, status, hi, lo, r2, f2)
+        assert a.ok == p.ok is False
+    # a corrupted WRITE_SLOT source: the serial replay recomputes the slot from its own read, the per-key
+    # check from the reported one; both reject
+    src = int(np.nonzero((b.table == wl.T_DISTRICT) & (b.field == wl.D_NEXT_O_ID))[0][0])
+    r2 = reads.copy(); r2[src] += 1
+    a, p = _both(tabs, b, status, hi, lo, r2, fin)
+    assert not a.ok and not p.ok and p.table_mismatches >= 1
+
+
+def test_perkey_checker_on_a_committed_subset():
+    tabs, b = wl.kv_workload(n_rows=500, n_fields=2, n_txns=3_000, ops=4, theta=0.8, seed=13)
+    keep = np.random.default_rng(5).random(b.n_txns) < 0.7
+    order = np.random.default_rng(6).permutation(np.nonzero(keep)[0])
+    fin, reads = oracle.replay(tabs, b, order)
+    status = keep.astype(np.uint32)
+    lo = np.zeros(b.n_txns, np.uint64); lo[order] = np.arange(1, len(order) + 1, dtype=np.uint64)
+    hi = np.zeros(b.n_txns, np.uint64)
+    a, p = _both(tabs, b, status, hi, lo, reads, fin, require_all_committed=False)
+    assert a.ok and p.ok
+    a, p = _both(tabs, b, status, hi, lo, reads, fin)
+    assert not a.ok and not p.ok
