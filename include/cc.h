@@ -150,7 +150,8 @@ typedef struct {
 typedef struct {
   int32_t device;  /* HIP device ordinal */
   uint32_t flags;  /* must be 0 */
-  void *stream;    /* hipStream_t to issue work on (NULL: the null stream) */
+  void *stream;    /* hipStream_t to issue work on (e.g. a torch stream); NULL: the context creates a
+                      stream of its own with the default priority (so that its runs can be captured) */
 } cc_config;
 
 /*
@@ -179,28 +180,33 @@ enum cc_mode { CC_MODE_PLAIN = 0, CC_MODE_EPOCH = 1, CC_MODE_SERVE = 2 };
 /* Run flags. */
 #define CC_RUN_STRICT_FENCES 0x1u /* agent-scope acquire/release fences (cache invalidate/write-back) at
                                      every ordering point instead of wait-for-completion only */
-#define CC_RUN_WAIT_UNLOCK 0x4u   /* (currently rejected with CC_E_INVAL) after failing on a row another
-                                     transaction holds, look at that row's word between attempts and
-                                     retry once it is free.  Disabled: teams of one wavefront that block
-                                     each other retry in lockstep and can livelock in the final pass. */
+#define CC_RUN_WAIT_UNLOCK 0x4u   /* reserved; always rejected with CC_E_INVAL (a retry-when-free policy
+                                     whose teams of one wavefront could retry in lockstep and livelock
+                                     in the final single-wavefront pass; the code path is removed) */
 #define CC_RUN_PRECHECK 0x8u      /* OCC, TicToc, TO and MVCC: an extra first round loads every row's word and aborts before
                                      taking any lock if one is held -- on every attempt.  By default it
                                      runs from a transaction's second attempt on (a failure is the
-                                     sign of contention) */
-#define CC_RUN_NO_PRECHECK 0x10u  /* OCC, TicToc, TO and MVCC: never run the pre-check round */
+                                     sign of contention).  CC_E_INVAL for another scheme, or together
+                                     with CC_RUN_NO_PRECHECK */
+#define CC_RUN_NO_PRECHECK 0x10u  /* OCC, TicToc, TO and MVCC: never run the pre-check round (CC_E_INVAL for
+                                     another scheme) */
 #define CC_RUN_LATCH 0x40u        /* latch variants of the non-deterministic schemes (paper Section 4.2,
                                      Exp-7): a 32-bit latch per row guards its control word, and every
                                      update of the word is a critical section [latch, load, store,
-                                     unlatch] instead of one 64-bit atomic.  Not for CC_GACCO. */
+                                     unlatch] instead of one 64-bit atomic.  Not for CC_GACCO or CC_GPUTX.
+                                     A latch not obtained within 2^22 tries fails the run: every team
+                                     stops, cc_run returns CC_E_LIVELOCK, and the table contents are
+                                     undefined (reload them before the next run) */
 #define CC_RUN_SHARED_READS 0x80u /* CC_GACCO: reads of a row between two of its writes run together (a
                                      write still waits for every earlier access, a read for every
                                      earlier write); the paper's GaccO queues reads like writes */
 #define CC_RUN_INDEX_TREE 0x20u   /* keyed batches: look keys up by descending the index's 16-way tree
                                      (one 128-byte node per level) instead of by binary search of the
                                      sorted keys */
-#define CC_RUN_EAGER_INSTALL 0x2u /* OCC: store new values in the validation round (undo on abort) instead
-                                     of after validation succeeds; measured ~3% slower on the key-value
-                                     workload, kept for comparison */
+#define CC_RUN_EAGER_INSTALL 0x2u /* OCC only (CC_E_INVAL for another scheme): store new values in the
+                                     validation round (undo on abort) instead of after validation
+                                     succeeds; measured ~3% slower on the key-value workload, kept for
+                                     comparison */
 
 typedef struct {
   uint32_t lanes_per_txn; /* lanes cooperating on one transaction: 1, 4, 16, 64; 0 = smallest >= longest txn */
@@ -260,18 +266,28 @@ enum cc_stat {
   CC_N_STATS = 32
 };
 
-/* Library version and self-description. */
+/* Library version and self-description (no device work). */
 const char *cc_version(void);
 const char *cc_strerror(cc_status status);
 const char *cc_last_error(const cc_ctx *ctx);
 
 /*
  * Create a context on cfg->device (which must be a gfx950 GPU) issuing work
- * on cfg->stream.  *out receives the context, or NULL on error.
+ * on cfg->stream (cfg NULL: device 0, own stream).  The context holds the
+ * device state of one database (paper Section 3.3, "An Overview": tables,
+ * control words and batches live in device memory, and the host only
+ * launches work): its control block is allocated here.  *out receives the
+ * context, or NULL on error.  Errors: CC_E_INVAL (out NULL, flags not 0),
+ * CC_E_NODEV (no device, ordinal out of range, not gfx950), CC_E_NOMEM,
+ * CC_E_HIP; cc_last_error(NULL) gives the message.
  */
 cc_status cc_init(cc_ctx **out, const cc_config *cfg);
 
-/* Free every device and host resource of the context.  NULL is accepted. */
+/*
+ * Wait for the context's stream, then free every device and host resource
+ * of the context (tables, indexes, batches, the stream it created).  The
+ * caller's stream and buffers are not touched.  NULL is accepted.
+ */
 cc_status cc_destroy(cc_ctx *ctx);
 
 /*
@@ -284,24 +300,47 @@ cc_status cc_destroy(cc_ctx *ctx);
 cc_status cc_create_table(cc_ctx *ctx, uint64_t n_rows, uint32_t n_fields, uint32_t *table_id);
 
 /*
- * Copy n_rows x n_fields values (row-major) into a table.  n_rows must equal
- * the table's row count.  rows is a host pointer, or a device pointer when
- * rows_on_device is non-zero (device-to-device copy, e.g. a pristine copy
- * kept in a torch tensor).  The first cc_load freezes the set of tables.
+ * Copy n_rows x n_fields values (row-major) into a table: the data is
+ * resident in device memory before any transaction runs (paper Section 4.1,
+ * "Constraints").  n_rows must equal the table's row count.  rows is a host
+ * pointer, or a device pointer when rows_on_device is non-zero
+ * (device-to-device copy, e.g. a pristine copy kept in a torch tensor); the
+ * caller keeps ownership and the call returns after the copy.  The first
+ * cc_load lays out and allocates every declared table (one value arena, one
+ * control word per row, Section 3.4) and freezes the set of tables.  Errors:
+ * CC_E_INVAL (NULL, wrong row count), CC_E_RANGE (unknown table, tables
+ * above CC_MAX_TOTAL_ROWS / CC_MAX_TOTAL_CELLS), CC_E_NOMEM, CC_E_HIP.
  */
 cc_status cc_load(cc_ctx *ctx, uint32_t table_id, const int64_t *rows, uint64_t n_rows, int rows_on_device);
 
-/* Copy a table's current contents out (row-major), to host or device memory. */
+/*
+ * Copy a table's current contents out (row-major) into out: n_rows x
+ * n_fields int64 values, host memory, or device memory when out_on_device is
+ * non-zero.  The final-state snapshot that verification compares (paper
+ * Section 3.4, "Measurements and Verification").  Errors: CC_E_INVAL,
+ * CC_E_RANGE (unknown table), CC_E_STATE (not loaded), CC_E_HIP.
+ */
 cc_status cc_read_table(cc_ctx *ctx, uint32_t table_id, int64_t *out, int out_on_device);
 
 /*
  * Validate a batch of n_txns transactions over n_ops operations and stage it
- * in device memory for `scheme`.  txns/ops are host arrays (on_device = 0).
- * Errors: CC_E_INVAL (bad scheme/kind, op ranges outside the ops array,
- * WRITE_SLOT source not earlier, too many ops in a txn; for CC_GACCO and
- * CC_GPUTX, a transaction whose first_op is below the previous one's), CC_E_RANGE,
- * CC_E_DUPROW.  *batch_id receives a handle valid until cc_release_batch or
- * cc_destroy.  Zero transactions is a valid (empty) batch.
+ * in device memory for `scheme`: a batch whose read and write sets are fixed
+ * before execution, over existing rows only (paper Section 4.1,
+ * "Constraints"; the batch model of Section 3.3).  txns / ops are host
+ * arrays (on_device = 0: validated on the host, packed and copied), or
+ * device pointers on the context's device (on_device != 0, e.g. torch
+ * tensors' data_ptr(): an ingest kernel validates them with the same rules
+ * and the same status codes and packs them into the engine's layout, on the
+ * context's stream).  Either way the arrays are read during the call only;
+ * the caller keeps ownership and may reuse them once it returns.  Errors:
+ * CC_E_INVAL (bad scheme/kind, op ranges outside the ops array, two
+ * transactions sharing an op, WRITE_SLOT source not earlier, too many ops in
+ * a txn, reserved not 0; for CC_GACCO and CC_GPUTX, a transaction whose
+ * first_op is below the previous one's), CC_E_RANGE, CC_E_DUPROW,
+ * CC_E_NOMEM.  When several transactions are malformed, the status is that
+ * of the lowest-numbered one.  *batch_id receives a handle valid until
+ * cc_release_batch or cc_destroy.  Zero transactions is a valid (empty)
+ * batch.
  */
 cc_status cc_submit_batch(cc_ctx *ctx, const cc_txn *txns, uint64_t n_txns, const cc_op *ops, uint64_t n_ops,
                           int scheme, int on_device, uint64_t *batch_id);
@@ -366,9 +405,23 @@ cc_status cc_check_batch(uint32_t n_tables, const uint64_t *n_rows, const uint32
 cc_status cc_run(cc_ctx *ctx, uint64_t batch_id, const cc_run_params *params);
 
 /*
+ * Host-only check of run parameters for a scheme: returns CC_OK, or the
+ * status cc_run would return for these parameters before touching the
+ * device (unknown mode or flag, lanes_per_txn not 1/4/16/64, waves_per_wg
+ * above 16, a flag the scheme does not implement, CC_RUN_PRECHECK with
+ * CC_RUN_NO_PRECHECK, wait_limit_us for a scheme without waits, a mode
+ * GaccO / GPUTx do not run).  params may be NULL (defaults).  Usable without
+ * a GPU.
+ */
+cc_status cc_check_run_params(int scheme, const cc_run_params *params);
+
+/*
  * Copy the last run's per-transaction outcomes (n_txns entries) and per-op
- * read values (n_ops entries, indexed like the submitted ops array) out.
- * Either pointer may be NULL.  dst_on_device selects device destinations.
+ * read values (n_ops entries, indexed like the submitted ops array) out:
+ * what the paper's verification consumes (Section 3.4, "Measurements and
+ * Verification"), with the serial key in place of its event log.  Either
+ * pointer may be NULL.  dst_on_device selects device destinations.  Errors:
+ * CC_E_NOBATCH, CC_E_STATE (batch not run), CC_E_HIP.
  */
 cc_status cc_fetch_outcomes(cc_ctx *ctx, uint64_t batch_id, cc_outcome *per_txn, int64_t *per_op_read,
                             int dst_on_device);
@@ -381,7 +434,14 @@ cc_status cc_fetch_outcomes(cc_ctx *ctx, uint64_t batch_id, cc_outcome *per_txn,
  */
 cc_status cc_set_arrivals(cc_ctx *ctx, uint64_t batch_id, const int64_t *arrival_ns, uint64_t n);
 
-/* Copy up to n counters (enum cc_stat order) of the batch's last run. */
+/*
+ * Copy up to n counters (enum cc_stat order) of the batch's last run: the
+ * paper's metrics (Section 4.1, "Metric Selection": throughput over the
+ * window from CC initialisation to the last commit, abort rate) and its
+ * breakdown of time into useful work, aborts and waiting (Section 3.4,
+ * "Measurements and Verification").  Host memory.  Errors: CC_E_INVAL,
+ * CC_E_NOBATCH.
+ */
 cc_status cc_stats(cc_ctx *ctx, uint64_t batch_id, uint64_t *counters, uint32_t n);
 
 /* Free a batch's device buffers. */

@@ -83,6 +83,7 @@ _SIGS = {
     "cc_create_index": (_S, [_P, ctypes.c_uint32, _P, ctypes.c_uint64]),
     "cc_fetch_rows": (_S, [_P, ctypes.c_uint64, _P]),
     "cc_run": (_S, [_P, ctypes.c_uint64, ctypes.POINTER(cc_run_params)]),
+    "cc_check_run_params": (_S, [ctypes.c_int, ctypes.POINTER(cc_run_params)]),
     "cc_fetch_outcomes": (_S, [_P, ctypes.c_uint64, _P, _P, ctypes.c_int]),
     "cc_stats": (_S, [_P, ctypes.c_uint64, _P, ctypes.c_uint32]),
     "cc_set_arrivals": (_S, [_P, ctypes.c_uint64, _P, ctypes.c_uint64]),
@@ -196,23 +197,46 @@ def cc_check_batch(table_shapes, txns: np.ndarray, ops: np.ndarray, scheme: int)
                                   scheme))
 
 
-def cc_submit_batch(ctx, txns: np.ndarray, ops: np.ndarray, scheme: int) -> int:
-    txns = _host(txns, TXN_DTYPE)
-    ops = _host(ops, OP_DTYPE)
+def _count(a, itemsize: int) -> int:
+    """Records in a host array (its length) or a device tensor (its bytes / the record size)."""
+    if hasattr(a, "data_ptr"):
+        nbytes = a.numel() * a.element_size()
+        assert nbytes % itemsize == 0, "device array is not a whole number of records"
+        return nbytes // itemsize
+    return len(a)
+
+
+def cc_submit_batch(ctx, txns, ops, scheme: int) -> int:
+    """Submit host arrays (numpy, TXN_DTYPE / OP_DTYPE) or device tensors holding the same records."""
+    on_dev = hasattr(txns, "data_ptr")
+    assert on_dev == hasattr(ops, "data_ptr"), "txns and ops must both be host arrays or both device tensors"
+    if not on_dev:
+        txns = _host(txns, TXN_DTYPE)
+        ops = _host(ops, OP_DTYPE)
     bid = ctypes.c_uint64()
-    _check(lib.cc_submit_batch(ctx, _ptr(txns), len(txns), _ptr(ops), len(ops), scheme, 0, ctypes.byref(bid)), ctx)
+    _check(lib.cc_submit_batch(ctx, _ptr(txns), _count(txns, 16), _ptr(ops), _count(ops, 16), scheme, int(on_dev),
+                               ctypes.byref(bid)), ctx)
     return int(bid.value)
 
 
-def cc_submit_batch_keyed(ctx, txns: np.ndarray, ops: np.ndarray, op_keys: np.ndarray, scheme: int) -> int:
-    txns = _host(txns, TXN_DTYPE)
-    ops = _host(ops, OP_DTYPE)
-    keys = _host(op_keys, np.int64)
-    assert len(keys) == len(ops)
+def cc_submit_batch_keyed(ctx, txns, ops, op_keys, scheme: int) -> int:
+    on_dev = hasattr(txns, "data_ptr")
+    assert on_dev == hasattr(ops, "data_ptr") == hasattr(op_keys, "data_ptr")
+    if not on_dev:
+        txns = _host(txns, TXN_DTYPE)
+        ops = _host(ops, OP_DTYPE)
+        op_keys = _host(op_keys, np.int64)
+    assert _count(op_keys, 8) == _count(ops, 16)
     bid = ctypes.c_uint64()
-    _check(lib.cc_submit_batch_keyed(ctx, _ptr(txns), len(txns), _ptr(ops), len(ops), _ptr(keys), scheme, 0,
-                                     ctypes.byref(bid)), ctx)
+    _check(lib.cc_submit_batch_keyed(ctx, _ptr(txns), _count(txns, 16), _ptr(ops), _count(ops, 16), _ptr(op_keys),
+                                     scheme, int(on_dev), ctypes.byref(bid)), ctx)
     return int(bid.value)
+
+
+def cc_check_run_params(scheme: int, params: cc_run_params | None = None) -> int:
+    """Host-only check of run parameters; returns the cc_status cc_run would give before any device work."""
+    p = params if params is not None else run_params()
+    return int(lib.cc_check_run_params(scheme, ctypes.byref(p)))
 
 
 def cc_create_index(ctx, table_id: int, keys: np.ndarray) -> None:
@@ -304,6 +328,21 @@ class Engine:
             scheme = SCHEMES[scheme]
         txns, ops = pack_batch(batch)
         return cc_submit_batch(self.ctx, txns, ops, scheme)
+
+    def submit_device(self, batch, scheme, device="cuda", keys=None) -> int:
+        """Submit through device memory: the ABI arrays are copied into torch tensors on the GPU first
+        and the library validates and packs them there (on_device = 1)."""
+        import torch
+        if isinstance(scheme, str):
+            scheme = SCHEMES[scheme]
+        txns, ops = pack_batch(batch)
+        if keys is not None:
+            ops["row"][np.isin(ops["table"], sorted(self.indexed))] = 0
+        as_dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.uint8)).to(device)
+        dt, do = as_dev(txns), as_dev(ops)
+        if keys is None:
+            return cc_submit_batch(self.ctx, dt, do, scheme)
+        return cc_submit_batch_keyed(self.ctx, dt, do, as_dev(np.asarray(keys, np.int64)), scheme)
 
     def create_index(self, table_id, keys):
         cc_create_index(self.ctx, self.ids[table_id], keys)

@@ -75,6 +75,7 @@ struct cc_ctx {
   IndexDesc *d_idx = nullptr;         // device copy of every table's IndexDesc
   uint32_t *d_latch = nullptr;        // CC_RUN_LATCH: one latch per global row
   uint64_t *d_kstate = nullptr;       // GPUTx: per-row rank state
+  uint64_t *d_ingest = nullptr;       // device-side batch ingest: reduced results
   std::map<uint64_t, Batch> batches;
   uint64_t next_batch = 1;
   hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -310,6 +311,7 @@ cc_status cc_destroy(cc_ctx *c) {
   if (c->d_idx) (void)hipFree(c->d_idx);
   if (c->d_latch) (void)hipFree(c->d_latch);
   if (c->d_kstate) (void)hipFree(c->d_kstate);
+  if (c->d_ingest) (void)hipFree(c->d_ingest);
   if (c->d_data) (void)hipFree(c->d_data);
   if (c->d_words) (void)hipFree(c->d_words);
   if (c->d_aux) (void)hipFree(c->d_aux);
@@ -491,13 +493,8 @@ uint64_t wait_limit_ticks(const cc_ctx *c, const cc_run_params &p) {
   return std::max<uint64_t>(1, p.wait_limit_us * c->wallclock_khz / 1000ull);
 }
 
+// (mode and flags were checked by check_run_params)
 cc_status run_gacco(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes, uint32_t wpw) {
-  if (p.mode != CC_MODE_PLAIN)
-    return fail(c, CC_E_INVAL,
-                "CC_GACCO runs in CC_MODE_PLAIN only: it never aborts, so epochs have nothing to retry, and it "
-                "orders the whole batch before running it");
-  if (p.flags & ~(CC_RUN_STRICT_FENCES | CC_RUN_INDEX_TREE | CC_RUN_SHARED_READS))
-    return fail(c, CC_E_INVAL, "CC_GACCO accepts only CC_RUN_STRICT_FENCES, CC_RUN_INDEX_TREE and CC_RUN_SHARED_READS");
   GaccoArgs a{};
   a.ops = b.d_ops;
   a.txns = b.d_txns;
@@ -573,11 +570,8 @@ uint64_t gputx_scratch_words(uint64_t n_txns) { return 3 * n_txns + 1 + radix_so
 // GPUTx run: CC initialisation, [index lookups], preprocessing shared with
 // GaccO, the rank pass, the sort into K-sets, and the K-set-ordered
 // execution.  Every transaction runs exactly once.
+// (mode and flags were checked by check_run_params)
 cc_status run_gputx(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes, uint32_t wpw) {
-  if (p.mode != CC_MODE_PLAIN)
-    return fail(c, CC_E_INVAL, "CC_GPUTX runs in CC_MODE_PLAIN only: it orders the whole batch before running it");
-  if (p.flags & ~(CC_RUN_STRICT_FENCES | CC_RUN_INDEX_TREE))
-    return fail(c, CC_E_INVAL, "CC_GPUTX accepts only CC_RUN_STRICT_FENCES and CC_RUN_INDEX_TREE");
   if (!c->d_kstate) HIP_OR(c, hipMalloc(&c->d_kstate, std::max<uint64_t>(c->total_rows, 1) * sizeof(uint64_t)));
   const uint64_t n = b.n_txns;
   uint32_t *txn_rank = b.d_tscratch, *iota = txn_rank + n, *kstart = iota + n, *sort_scratch = kstart + n + 1;
@@ -674,6 +668,54 @@ cc_status run_gputx(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes,
   return CC_OK;
 }
 
+// Run parameters against the scheme, before anything touches the device
+// (cc_check_run_params and cc_run).  c may be NULL (no message kept).
+cc_status check_run_params(cc_ctx *c, int scheme, const cc_run_params &p) {
+  if (scheme < 0 || scheme >= CC_N_SCHEMES) return fail(c, CC_E_INVAL, "unknown scheme");
+  if (p.mode != CC_MODE_PLAIN && p.mode != CC_MODE_EPOCH && p.mode != CC_MODE_SERVE)
+    return fail(c, CC_E_INVAL, "unknown mode");
+  const uint32_t lanes = p.lanes_per_txn;
+  if (lanes != 0 && lanes != 1 && lanes != 4 && lanes != 16 && lanes != 64)
+    return fail(c, CC_E_INVAL, "lanes_per_txn must be 1, 4, 16 or 64");
+  if (p.waves_per_wg > 16) return fail(c, CC_E_INVAL, "waves_per_wg must be 1..16");
+  if (p.flags & ~(CC_RUN_STRICT_FENCES | CC_RUN_EAGER_INSTALL | CC_RUN_WAIT_UNLOCK | CC_RUN_PRECHECK |
+                  CC_RUN_NO_PRECHECK | CC_RUN_INDEX_TREE | CC_RUN_LATCH | CC_RUN_SHARED_READS))
+    return fail(c, CC_E_INVAL, "unknown run flag");
+  if ((p.flags & CC_RUN_SHARED_READS) && scheme != CC_GACCO)
+    return fail(c, CC_E_INVAL, "CC_RUN_SHARED_READS is a CC_GACCO option");
+  if (p.wait_limit_us && scheme != CC_GACCO && scheme != CC_GPUTX)
+    return fail(c, CC_E_INVAL, "wait_limit_us applies to CC_GACCO and CC_GPUTX only");
+  if (p.flags & CC_RUN_WAIT_UNLOCK)
+    // Switched off: two teams of one wavefront that block each other both see
+    // the row free on their next loop iteration (each attempt releases its
+    // locks before returning) and retry together, so in the final
+    // single-wavefront pass, which never defers, they can conflict forever.
+    return fail(c, CC_E_INVAL, "CC_RUN_WAIT_UNLOCK is disabled (same-wavefront retries can livelock)");
+  if (scheme == CC_GACCO) {
+    if (p.mode != CC_MODE_PLAIN)
+      return fail(c, CC_E_INVAL,
+                  "CC_GACCO runs in CC_MODE_PLAIN only: it never aborts, so epochs have nothing to retry, and it "
+                  "orders the whole batch before running it");
+    if (p.flags & ~(CC_RUN_STRICT_FENCES | CC_RUN_INDEX_TREE | CC_RUN_SHARED_READS))
+      return fail(c, CC_E_INVAL, "CC_GACCO accepts only CC_RUN_STRICT_FENCES, CC_RUN_INDEX_TREE and CC_RUN_SHARED_READS");
+    return CC_OK;
+  }
+  if (scheme == CC_GPUTX) {
+    if (p.mode != CC_MODE_PLAIN)
+      return fail(c, CC_E_INVAL, "CC_GPUTX runs in CC_MODE_PLAIN only: it orders the whole batch before running it");
+    if (p.flags & ~(CC_RUN_STRICT_FENCES | CC_RUN_INDEX_TREE))
+      return fail(c, CC_E_INVAL, "CC_GPUTX accepts only CC_RUN_STRICT_FENCES and CC_RUN_INDEX_TREE");
+    return CC_OK;
+  }
+  const uint32_t pre = CC_RUN_PRECHECK | CC_RUN_NO_PRECHECK;
+  if ((p.flags & pre) == pre) return fail(c, CC_E_INVAL, "CC_RUN_PRECHECK and CC_RUN_NO_PRECHECK exclude each other");
+  if ((p.flags & pre) && scheme != CC_OCC && scheme != CC_TICTOC && scheme != CC_TO && scheme != CC_MVCC)
+    return fail(c, CC_E_INVAL, "the pre-check round exists for CC_OCC, CC_TICTOC, CC_TO and CC_MVCC only");
+  if ((p.flags & CC_RUN_EAGER_INSTALL) && scheme != CC_OCC)
+    return fail(c, CC_E_INVAL, "CC_RUN_EAGER_INSTALL is a CC_OCC option");
+  return CC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -696,16 +738,160 @@ cc_status cc_check_batch(uint32_t n_tables, const uint64_t *n_rows, const uint32
   return st;
 }
 
+// Device buffers of a batch: descriptors, outcomes, read values, pending
+// list, and the scheme's extras.  All or nothing.
+static hipError_t alloc_batch(Batch &b, int scheme, bool keyed) {
+  const bool ordered_scheme = scheme == CC_GACCO || scheme == CC_GPUTX;
+  const uint64_t n_ops = b.n_ops, n_txns = b.n_txns;
+  auto alloc = [&](void **p, size_t bytes) -> hipError_t { return hipMalloc(p, bytes ? bytes : 16); };
+  hipError_t e;
+  if ((e = alloc((void **)&b.d_ops, n_ops * sizeof(DevOp))) != hipSuccess ||
+      (e = alloc((void **)&b.d_txns, n_txns * sizeof(DevTxn))) != hipSuccess ||
+      (e = alloc((void **)&b.d_out, n_txns * sizeof(DevOutcome))) != hipSuccess ||
+      (e = alloc((void **)&b.d_reads, n_ops * sizeof(int64_t))) != hipSuccess ||
+      (e = alloc((void **)&b.d_list, n_txns * sizeof(uint32_t))) != hipSuccess ||
+      (scheme == CC_MVCC && (e = alloc((void **)&b.d_nodes, n_ops * 3 * sizeof(uint64_t))) != hipSuccess) ||
+      (ordered_scheme && (e = alloc((void **)&b.d_rank, n_ops * sizeof(uint32_t))) != hipSuccess) ||
+      (ordered_scheme &&
+       (e = alloc((void **)&b.d_gscratch, gacco_scratch_words(n_ops) * sizeof(uint32_t))) != hipSuccess) ||
+      (scheme == CC_GPUTX &&
+       (e = alloc((void **)&b.d_tscratch, gputx_scratch_words(n_txns) * sizeof(uint32_t))) != hipSuccess) ||
+      (keyed && (e = alloc((void **)&b.d_opkeys, n_ops * sizeof(int64_t))) != hipSuccess) ||
+      (keyed && (e = alloc((void **)&b.d_meta, n_ops * sizeof(uint32_t))) != hipSuccess) ||
+      (keyed && (e = alloc((void **)&b.d_rows, n_ops * sizeof(uint32_t))) != hipSuccess)) {
+    free_batch(b);
+    return e;
+  }
+  return hipSuccess;
+}
+
+// True if [p, p + bytes) lies inside one allocation of the context's device.
+static bool device_range(const cc_ctx *c, const void *p, uint64_t bytes) {
+  if (bytes == 0) return true;
+  if (!p) return false;
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  if (at.type != hipMemoryTypeDevice || at.device != c->device) return false;
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  const uintptr_t lo = (uintptr_t)base, q = (uintptr_t)p;
+  return q >= lo && bytes <= size && q - lo <= size - bytes;
+}
+
+static const char *ingest_message(uint32_t m) {
+  switch (m) {
+    case INGEST_MSG_RESERVED: return "cc_txn.reserved must be 0";
+    case INGEST_MSG_TOO_MANY: return "transaction has too many ops";
+    case INGEST_MSG_OP_RANGE: return "op range outside ops";
+    case INGEST_MSG_SHARED: return "transactions share operations";
+    case INGEST_MSG_TABLE: return "op table out of range";
+    case INGEST_MSG_KEYED_ROW: return "an op on an indexed table names its row by key; row must be 0";
+    case INGEST_MSG_ROW_FIELD: return "op row/field out of range";
+    case INGEST_MSG_KIND: return "unknown op kind";
+    case INGEST_MSG_SLOT_SRC: return "WRITE_SLOT source is not an earlier op";
+    case INGEST_MSG_DUP_FIELD: return "field repeated within a txn";
+    case INGEST_MSG_DUP_ROW: return "row accessed twice (non-adjacent) within a txn";
+    default: return "malformed batch";
+  }
+}
+
 static cc_status submit_impl(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, const cc_op *ops, uint64_t n_ops,
                              const int64_t *op_keys, int scheme, int on_device, uint64_t *batch_id) {
   if (!c || !batch_id) return CC_E_INVAL;
   *batch_id = 0;
   if (scheme < 0 || scheme >= CC_N_SCHEMES) return fail(c, CC_E_INVAL, "unknown scheme");
-  if (on_device) return fail(c, CC_E_INVAL, "device-resident batch submission is not supported; pass host arrays");
   if (!c->frozen) return fail(c, CC_E_STATE, "load the tables before submitting a batch");
   if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
   std::vector<bool> indexed(c->tables.size(), false);
   for (size_t t = 0; t < c->indexes.size() && t < indexed.size(); ++t) indexed[t] = c->indexes[t].keys != nullptr;
+  const bool ordered_scheme = scheme == CC_GACCO || scheme == CC_GPUTX;
+  Batch b;
+  b.scheme = scheme;
+  b.n_txns = n_txns;
+  b.n_ops = n_ops;
+
+  if (on_device) {
+    // the caller's arrays are in device memory: validate and pack them there
+    if ((n_txns && !txns) || (n_ops && !ops)) return fail(c, CC_E_INVAL, "null array");
+    if (n_txns > 0xFFFFFFFFull || n_ops > 0xFFFFFFFFull) return fail(c, CC_E_RANGE, "batch too large");
+    if (!device_range(c, txns, n_txns * sizeof(cc_txn)) || !device_range(c, ops, n_ops * sizeof(cc_op)) ||
+        (op_keys && !device_range(c, op_keys, n_ops * sizeof(int64_t))))
+      return fail(c, CC_E_INVAL, "on_device arrays must lie in device memory of the context's device");
+    bool any_index = false;
+    for (bool x : indexed) any_index |= x;
+    const bool maybe_keyed = op_keys && any_index;
+    hipError_t e = alloc_batch(b, scheme, maybe_keyed);
+    if (e != hipSuccess) return hip_fail(c, e, "batch allocation");
+    if (!c->d_ingest && (e = hipMalloc(&c->d_ingest, INGEST_N * sizeof(uint64_t))) != hipSuccess) {
+      free_batch(b);
+      return hip_fail(c, e, "ingest buffer allocation");
+    }
+    IngestArgs ia{};
+    ia.txns = txns;
+    ia.ops = ops;
+    ia.op_keys = maybe_keyed ? op_keys : nullptr;
+    ia.n_txns = n_txns;
+    ia.n_ops = n_ops;
+    ia.n_tables = (uint32_t)c->tables.size();
+    for (uint32_t t = 0; t < ia.n_tables; ++t) {
+      const Table &tb = c->tables[t];
+      ia.tab[t] = IngestTable{tb.n_rows, tb.row_base, tb.elem_base, tb.n_fields, (uint32_t)(indexed[t] ? 1 : 0)};
+    }
+    ia.dops = b.d_ops;
+    ia.dtx = b.d_txns;
+    ia.owner = (uint32_t *)b.d_reads;  // n_ops x 8 bytes, cleared below before any run
+    ia.meta = maybe_keyed ? b.d_meta : nullptr;
+    ia.rows0 = maybe_keyed ? b.d_rows : nullptr;
+    ia.out = c->d_ingest;
+    uint64_t res[INGEST_N] = {};
+    e = launch_ingest(c->stream, ia);
+    if (e == hipSuccess && maybe_keyed && n_ops)
+      e = hipMemcpyAsync(b.d_opkeys, op_keys, n_ops * sizeof(int64_t), hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess && n_ops) e = hipMemsetAsync(b.d_reads, 0, n_ops * sizeof(int64_t), c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(res, c->d_ingest, sizeof res, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      free_batch(b);
+      return hip_fail(c, e, "batch ingest");
+    }
+    if (res[INGEST_ERR] != ~0ull) {
+      free_batch(b);
+      const uint64_t w = res[INGEST_ERR];
+      const cc_status code = -(cc_status)(w & 15u);
+      return fail(c, code, std::string(ingest_message((uint32_t)((w >> 4) & 0xFFFu))) + " (transaction " +
+                               std::to_string(w >> 16) + ")");
+    }
+    if (ordered_scheme && res[INGEST_UNORDERED]) {
+      free_batch(b);
+      return fail(c, CC_E_INVAL,
+                  "CC_GACCO and CC_GPUTX need each transaction's ops after the previous transaction's (first_op "
+                  "nondecreasing)");
+    }
+    b.max_ops = (uint32_t)res[INGEST_MAX_OPS];
+    b.has_slot = res[INGEST_HAS_SLOT] != 0;
+    b.keyed = res[INGEST_KEYED] != 0;
+    if (maybe_keyed && !b.keyed) {
+      (void)hipFree(b.d_opkeys);
+      (void)hipFree(b.d_meta);
+      (void)hipFree(b.d_rows);
+      b.d_opkeys = nullptr;
+      b.d_meta = nullptr;
+      b.d_rows = nullptr;
+    }
+    const uint64_t id = c->next_batch++;
+    c->batches[id] = b;
+    *batch_id = id;
+    return CC_OK;
+  }
+
   std::vector<DevOp> dops;
   std::vector<DevTxn> dtx;
   uint32_t max_ops = 0;
@@ -713,7 +899,6 @@ static cc_status submit_impl(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, con
   cc_status st = validate_and_pack(c, c->tables, txns, n_txns, ops, n_ops, &dops, &dtx, &max_ops, &has_slot, &ordered,
                                    op_keys, op_keys ? &indexed : nullptr);
   if (st) return st;
-  const bool ordered_scheme = scheme == CC_GACCO || scheme == CC_GPUTX;
   if (ordered_scheme && !ordered)
     return fail(c, CC_E_INVAL,
                 "CC_GACCO and CC_GPUTX need each transaction's ops after the previous transaction's (first_op nondecreasing)");
@@ -734,33 +919,11 @@ static cc_status submit_impl(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, con
         }
       }
   }
-
-  Batch b;
-  b.scheme = scheme;
-  b.n_txns = n_txns;
-  b.n_ops = n_ops;
   b.max_ops = max_ops;
   b.has_slot = has_slot;
   b.keyed = keyed;
-  auto alloc = [&](void **p, size_t bytes) -> hipError_t { return hipMalloc(p, bytes ? bytes : 16); };
-  hipError_t e;
-  if ((e = alloc((void **)&b.d_ops, n_ops * sizeof(DevOp))) != hipSuccess ||
-      (e = alloc((void **)&b.d_txns, n_txns * sizeof(DevTxn))) != hipSuccess ||
-      (e = alloc((void **)&b.d_out, n_txns * sizeof(DevOutcome))) != hipSuccess ||
-      (e = alloc((void **)&b.d_reads, n_ops * sizeof(int64_t))) != hipSuccess ||
-      (e = alloc((void **)&b.d_list, n_txns * sizeof(uint32_t))) != hipSuccess ||
-      (scheme == CC_MVCC && (e = alloc((void **)&b.d_nodes, n_ops * 3 * sizeof(uint64_t))) != hipSuccess) ||
-      (ordered_scheme && (e = alloc((void **)&b.d_rank, n_ops * sizeof(uint32_t))) != hipSuccess) ||
-      (ordered_scheme &&
-       (e = alloc((void **)&b.d_gscratch, gacco_scratch_words(n_ops) * sizeof(uint32_t))) != hipSuccess) ||
-      (scheme == CC_GPUTX &&
-       (e = alloc((void **)&b.d_tscratch, gputx_scratch_words(n_txns) * sizeof(uint32_t))) != hipSuccess) ||
-      (keyed && (e = alloc((void **)&b.d_opkeys, n_ops * sizeof(int64_t))) != hipSuccess) ||
-      (keyed && (e = alloc((void **)&b.d_meta, n_ops * sizeof(uint32_t))) != hipSuccess) ||
-      (keyed && (e = alloc((void **)&b.d_rows, n_ops * sizeof(uint32_t))) != hipSuccess)) {
-    free_batch(b);
-    return hip_fail(c, e, "batch allocation");
-  }
+  hipError_t e = alloc_batch(b, scheme, keyed);
+  if (e != hipSuccess) return hip_fail(c, e, "batch allocation");
   auto copy_in = [&]() -> hipError_t {
     hipError_t r = hipSuccess;
     if (n_ops) r = hipMemcpyAsync(b.d_ops, dops.data(), n_ops * sizeof(DevOp), hipMemcpyHostToDevice, c->stream);
@@ -906,6 +1069,10 @@ cc_status cc_fetch_rows(cc_ctx *c, uint64_t batch_id, uint32_t *rows) {
   return CC_OK;
 }
 
+cc_status cc_check_run_params(int scheme, const cc_run_params *pp) {
+  return check_run_params(nullptr, scheme, pp ? *pp : cc_run_params{});
+}
+
 cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   if (!c) return CC_E_INVAL;
   auto it = c->batches.find(batch_id);
@@ -913,8 +1080,8 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   Batch &b = it->second;
   cc_run_params p{};
   if (pp) p = *pp;
-  if (p.mode != CC_MODE_PLAIN && p.mode != CC_MODE_EPOCH && p.mode != CC_MODE_SERVE)
-    return fail(c, CC_E_INVAL, "unknown mode");
+  const cc_status pst = check_run_params(c, b.scheme, p);
+  if (pst) return pst;
   if (p.mode == CC_MODE_SERVE && b.n_txns && !b.d_arrival)
     return fail(c, CC_E_STATE, "CC_MODE_SERVE needs cc_set_arrivals first");
   uint32_t lanes = p.lanes_per_txn;
@@ -922,22 +1089,7 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
     lanes = 1;
     while (lanes < 64 && lanes < b.max_ops) lanes *= 4;
   }
-  if (lanes != 1 && lanes != 4 && lanes != 16 && lanes != 64) return fail(c, CC_E_INVAL, "lanes_per_txn must be 1, 4, 16 or 64");
   const uint32_t wpw = p.waves_per_wg ? p.waves_per_wg : 1;
-  if (wpw < 1 || wpw > 16) return fail(c, CC_E_INVAL, "waves_per_wg must be 1..16");
-  if (p.flags & ~(CC_RUN_STRICT_FENCES | CC_RUN_EAGER_INSTALL | CC_RUN_WAIT_UNLOCK | CC_RUN_PRECHECK |
-                  CC_RUN_NO_PRECHECK | CC_RUN_INDEX_TREE | CC_RUN_LATCH | CC_RUN_SHARED_READS))
-    return fail(c, CC_E_INVAL, "unknown run flag");
-  if ((p.flags & CC_RUN_SHARED_READS) && b.scheme != CC_GACCO)
-    return fail(c, CC_E_INVAL, "CC_RUN_SHARED_READS is a CC_GACCO option");
-  if (p.wait_limit_us && b.scheme != CC_GACCO && b.scheme != CC_GPUTX)
-    return fail(c, CC_E_INVAL, "wait_limit_us applies to CC_GACCO and CC_GPUTX only");
-  if (p.flags & CC_RUN_WAIT_UNLOCK)
-    // Switched off: two teams of one wavefront that block each other both see
-    // the row free on their next loop iteration (each attempt releases its
-    // locks before returning) and retry together, so in the final
-    // single-wavefront pass, which never defers, they can conflict forever.
-    return fail(c, CC_E_INVAL, "CC_RUN_WAIT_UNLOCK is disabled (same-wavefront retries can livelock)");
   if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
   if (b.scheme == CC_GACCO) return run_gacco(c, b, p, lanes, wpw);
   if (b.scheme == CC_GPUTX) return run_gputx(c, b, p, lanes, wpw);
@@ -963,7 +1115,6 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
   a.ns_per_tick_q16 = (uint32_t)((1000000ull << 16) / c->wallclock_khz);
   a.has_slot = b.has_slot ? 1u : 0u;
   a.eager_install = (p.flags & CC_RUN_EAGER_INSTALL) ? 1u : 0u;
-  a.wait_unlock = (p.flags & CC_RUN_WAIT_UNLOCK) ? 1u : 0u;
   a.precheck = (p.flags & CC_RUN_PRECHECK) ? 2u : ((p.flags & CC_RUN_NO_PRECHECK) ? 0u : 1u);
   a.wd_wait_limit = 64;
   if (p.flags & CC_RUN_LATCH) {
@@ -1033,7 +1184,8 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
       ++passes;
       all = false;
       HIP_OR(c, hipMemcpy(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
-      if (h.stats[DS_COMMITTED] + h.stats[DS_GAVE_UP] >= b.n_txns || last) return CC_OK;
+      // a stuck latch stopped the run (reported below)
+      if (h.stats[DS_COMMITTED] + h.stats[DS_GAVE_UP] >= b.n_txns || last || h.stop) return CC_OK;
       grid = std::max(1, grid_used / 8);
       if (grid == 1) waves = 1;
     }
@@ -1099,7 +1251,7 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
       epochs += EPOCHS_PER_GRAPH;
       HIP_OR(c, hipMemcpy(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
       const uint64_t done = h.stats[DS_COMMITTED] + h.stats[DS_GAVE_UP];
-      if (done >= b.n_txns) break;
+      if (done >= b.n_txns || h.stop) break;
       if (epochs >= max_epochs) {
         epoch_limit = true;
         break;
@@ -1155,7 +1307,8 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
       for (uint64_t t = 0; t < b.n_txns; ++t) o[t].commit_ns -= b.arrival_ns[t];
     latency_percentiles(o, &b.stats[CC_STAT_LAT_P50_NS], &b.stats[CC_STAT_LAT_P99_NS]);
   }
-  if (h.stats[DS_LATCH_STUCK]) return fail(c, CC_E_LIVELOCK, "a row latch was not obtained within the spin limit");
+  if (h.stats[DS_LATCH_STUCK] || h.stop)
+    return fail(c, CC_E_LIVELOCK, "a row latch was not obtained within the spin limit; table contents are undefined");
   if (h.stats[DS_TS_OVERFLOW]) return fail(c, CC_E_TS_OVERFLOW, "timestamp overflow during the run");
   if (epoch_limit) return fail(c, CC_E_LIVELOCK, "max_epochs reached with transactions pending");
   if (h.stats[DS_COMMITTED] != b.n_txns) {

@@ -75,7 +75,8 @@ struct Ctl {
   uint64_t budget_reserved;  // serving: bytes ever reserved (a FIFO position counter)
   uint64_t budget_released;  // serving: bytes ever released
   uint64_t stats[DS_N];
-  uint64_t stop;             // GaccO: set by a team whose wait exceeded its limit; every team then exits
+  uint64_t stop;             // set by a team whose wait exceeded its limit (GaccO, GPUTx) or whose latch
+                             // was stuck (CC_RUN_LATCH); every team then exits
 };
 
 // Kernel arguments for a transaction run.
@@ -103,8 +104,8 @@ struct RunArgs {
   uint64_t budget_cap;     // serving: admission cap on reserved bytes (0: no cap)
   uint32_t bytes_per_op;   // serving: log / version bytes one operation reserves
   uint32_t eager_install;  // OCC: store values in the validation round (undo on abort)
-  uint32_t wait_unlock;    // after a lock failure, poll the held row until it is free
-  uint32_t precheck;       // OCC load-only round before any lock: 0 never, 1 on retries, 2 always
+  uint32_t pad4;
+  uint32_t precheck;       // OCC, TicToc, TO, MVCC: load-only round before any lock: 0 never, 1 on retries, 2 always
   uint32_t wd_wait_limit;  // 2PL wait-die: waits of one attempt before it dies anyway
   uint32_t pad5;
   uint32_t *latch;         // CC_RUN_LATCH: one 32-bit latch per global row (else unused)
@@ -212,6 +213,49 @@ hipError_t launch_gputx_pass(hipStream_t s, bool exec, int lanes, int max_ops, i
 hipError_t gputx_init_state(hipStream_t s, uint64_t *kstate, uint64_t n_rows, uint32_t *iota, uint64_t n_txns);
 hipError_t gputx_reset(hipStream_t s, Ctl *ctl);
 hipError_t gputx_kstart(hipStream_t s, const uint32_t *rank_sorted, uint64_t n, uint32_t *kstart);
+
+// Device-side ingest of a batch already in device memory (ingest.hip).
+struct IngestTable {
+  uint64_t n_rows;
+  uint64_t row_base;   // first global row
+  uint64_t elem_base;  // first cell
+  uint32_t n_fields;
+  uint32_t indexed;    // keyed batches: the table has an index (its ops name rows by key)
+};
+// reduced results in IngestArgs::out
+enum IngestOut { INGEST_ERR = 0, INGEST_MAX_OPS = 1, INGEST_HAS_SLOT = 2, INGEST_UNORDERED = 3, INGEST_KEYED = 4,
+                 INGEST_N = 5 };
+// what failed (bits 4-15 of the error word); the host turns it into a message
+enum IngestMsg {
+  INGEST_MSG_RESERVED = 1,
+  INGEST_MSG_TOO_MANY,
+  INGEST_MSG_OP_RANGE,
+  INGEST_MSG_SHARED,
+  INGEST_MSG_TABLE,
+  INGEST_MSG_KEYED_ROW,
+  INGEST_MSG_ROW_FIELD,
+  INGEST_MSG_KIND,
+  INGEST_MSG_SLOT_SRC,
+  INGEST_MSG_DUP_FIELD,
+  INGEST_MSG_DUP_ROW
+};
+struct IngestArgs {
+  const cc_txn *txns;     // caller's device arrays
+  const cc_op *ops;
+  const int64_t *op_keys; // keyed batches (else nullptr)
+  uint64_t n_txns, n_ops;
+  IngestTable tab[CC_MAX_TABLES];
+  uint32_t n_tables;
+  uint32_t pad;
+  DevOp *dops;            // packed descriptors (the batch's own buffers)
+  DevTxn *dtx;
+  uint32_t *owner;        // n_ops scratch words: lowest transaction naming each op
+  uint32_t *meta;         // keyed batches: per-op keyed flag, table, field (else nullptr)
+  uint32_t *rows0;        // keyed batches: per-op row as submitted
+  uint64_t *out;          // INGEST_N words
+};
+// Resets out, then validates and packs; the host reads `out` afterwards.
+hipError_t launch_ingest(hipStream_t s, const IngestArgs &a);
 
 // Host-side launchers (kernels.hip).
 hipError_t launch_init(hipStream_t s, uint64_t *words, uint64_t n_words, uint64_t *aux, uint64_t n_aux,

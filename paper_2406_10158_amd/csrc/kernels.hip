@@ -92,6 +92,7 @@ __global__ void __launch_bounds__(256) init_kernel(uint64_t *words, uint64_t n_w
     ctl->budget_reserved = 0;
     ctl->budget_released = 0;
     for (int i = 0; i < DS_N; ++i) ctl->stats[i] = 0;
+    ctl->stop = 0;
     ctl->start_clock = wall_clock64();
   }
 }

@@ -27,10 +27,20 @@ namespace cce {
 // ---------------------------------------------------------------------------
 constexpr uint32_t LATCH_SPINS = 1u << 22;
 
+// A latch that is not obtained within LATCH_SPINS tries fails the run: the
+// first team to give up sets the stop word, every later latched update gives
+// up at once (it checks the word every 1024 tries), and the persistent loop
+// of every team exits at its next iteration.  An update that gave up is not
+// applied; it returns the word with bit 63 set, which every scheme reads as
+// "held" (OCC / TicToc lock, 2PL exclusive, TO dirty), so acquisitions and
+// compare-and-swaps fail and their attempts abort.  A lost release leaves its
+// row held, and cc_run reports CC_E_LIVELOCK with the table contents
+// undefined.
 template <bool STRICT, class F>
 __device__ __forceinline__ uint64_t latched(const RunArgs &a, uint64_t *w, F f) {
   uint32_t *lt = a.latch + (w - a.words);
   for (uint32_t it = 0; it < LATCH_SPINS; ++it) {
+    if (it && (it & 1023u) == 0 && ld_word(&a.ctl->stop)) return ld_word(w) | (1ull << 63);
     uint32_t e = 0;
     if (__hip_atomic_compare_exchange_strong(lt, &e, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT)) {
@@ -43,9 +53,10 @@ __device__ __forceinline__ uint64_t latched(const RunArgs &a, uint64_t *w, F f) 
     }
     __builtin_amdgcn_s_sleep(1);
   }
-  // a latch no one released in 2^22 tries: cc_run reports the run as failed
+  // a latch no one released in 2^22 tries: the run fails
   add_word(&a.ctl->stats[DS_LATCH_STUCK], 1ull);
-  return ld_word(w);
+  st_word(&a.ctl->stop, 1ull);
+  return ld_word(w) | (1ull << 63);
 }
 
 template <bool LATCH, bool STRICT>

@@ -42,14 +42,17 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
   uint64_t res_pos = 0;     // serving: the reservation's position in the byte queue
   bool admitted = false;    // serving: the reservation has been granted
   uint64_t t_round[4] = {0, 0, 0, 0};  // OCC committed attempts: per-round ticks
-  uint32_t wait_row = ~0u;  // row whose release the team waits for (~0u: none)
-  uint32_t polls = 0;
   uint64_t n_admit_wait = 0;
   bool resume = false;      // 2PL wait-die: the team waits holding locks; its next attempt continues this one
   uint32_t waits = 0;       // 2PL wait-die: waits of the current attempt
   uint64_t n_waits = 0;
 
   for (;;) {
+    if constexpr (LATCH) {
+      // a stuck latch failed the run (see latched): every team leaves its
+      // transaction pending and exits
+      if (__shfl((int)(ld_word(&a.ctl->stop) != 0), 0, 64)) break;
+    }
     const bool need = txn < 0 && !done;
     const uint64_t q = t.claim(&a.ctl->queue, need, 1);
     if (need) {
@@ -61,7 +64,6 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
         ready_at = a.arrival ? start_clock + (uint64_t)a.arrival[txn] : 0;
         reserved = 0;
         admitted = false;
-        wait_row = ~0u;
         resume = false;
         waits = 0;
       } else {
@@ -93,26 +95,6 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
       res_pos = (uint64_t)__shfl((long long)pos, t.tb, 64);
       admitted = __shfl((int)ok, t.tb, 64) != 0;
       if (!admitted) ready_at = now + 1 + (mix64(((uint64_t)txn << 20) ^ now) % (4ull * a.backoff_ticks));
-    }
-    if (wait_row != ~0u && txn >= 0 && now >= ready_at) {
-      // waiting for a row another transaction holds: look at its word (a
-      // load, not an atomic) and retry once it is free.  The gaps between
-      // looks grow exponentially (randomised), so that however many teams
-      // wait on one hot row, their loads cannot queue up on that address
-      // ahead of the holder's own release.  After a bounded number of looks
-      // the team falls back to the ordinary back-off.
-      bool free_now = false;
-      if (t.tl == 0) free_now = (ld_word(a.words + wait_row) >> 63) == 0;
-      free_now = __shfl((int)free_now, t.tb, 64) != 0;
-      if (free_now) {
-        wait_row = ~0u;
-      } else {
-        ++polls;
-        const uint32_t sh = polls < 10 ? polls : 10;
-        ready_at = now + 1 + (mix64(((uint64_t)txn << 24) ^ ((uint64_t)polls << 8) ^ attempts) %
-                              ((uint64_t)a.backoff_ticks << sh));
-        if (polls >= 16) wait_row = ~0u;
-      }
     }
     const bool active = txn >= 0 && now >= ready_at;
     if (ballot(active) == 0) {
@@ -215,11 +197,6 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
           }
           reserved = 0;
           txn = -1;
-        } else if (a.wait_unlock && r == ABORT_LOCK && s.block != ~0u) {
-          // retry when the row that stopped us is released
-          wait_row = s.block;
-          polls = 0;
-          ready_at = now + 1 + (mix64(((uint64_t)txn << 20) ^ attempts) % a.backoff_ticks);
         } else {
           // randomised exponential back-off
           const uint32_t sh = pass_att < 12 ? pass_att : 12;

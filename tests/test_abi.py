@@ -97,7 +97,7 @@ def _batch(rows, tables=None, fields=None, kinds=None, args=None, txn_lens=None)
 SHAPES = [(100, 4), (10, 2)]
 
 
-@pytest.mark.parametrize("case,status", [
+CHECK_CASES = [
     (dict(rows=[1, 2, 3]), 0),
     (dict(rows=[1, 100]), -2),                                   # row out of range
     (dict(rows=[1, 2], fields=[0, 4]), -2),                      # field out of range
@@ -111,7 +111,12 @@ SHAPES = [(100, 4), (10, 2)]
     (dict(rows=[1, 2], kinds=[3, 0], args=[0, 0]), -1),          # WRITE_SLOT from itself
     (dict(rows=[1, 2, 3, 1], txn_lens=[2, 2]), 0),               # the same row in different txns is fine
     (dict(rows=list(range(80)) * 4, fields=[0] * 80 + [1] * 80 + [2] * 80 + [3] * 80, txn_lens=[80] * 4), 0),
-])
+    (dict(rows=[1, 2, 3, 4, 100], txn_lens=[2, 3]), -2),       # the second transaction is malformed
+    (dict(rows=[1, 2, 1, 4, 100], txn_lens=[3, 2]), -3),       # both are: the first one's status wins
+]
+
+
+@pytest.mark.parametrize("case,status", CHECK_CASES)
 def test_check_batch_statuses(b, case, status):
     txns, ops = _batch(**case)
     assert b.cc_check_batch(SHAPES, txns, ops, 0) == status
@@ -200,3 +205,39 @@ def test_every_entry_point_rejects_a_null_context(b):
         assert call() == b.CC_E_INVAL, name
     assert lib.cc_destroy(None) == b.CC_OK
     assert isinstance(lib.cc_last_error(None), bytes)
+
+
+def test_run_parameter_checks_without_a_device(b):
+    ok = b.cc_check_run_params
+    P = b.run_params
+    assert ok(b.CC_OCC) == b.CC_OK and ok(b.CC_OCC, P(flags=b.CC_RUN_PRECHECK | b.CC_RUN_STRICT_FENCES)) == b.CC_OK
+    assert ok(b.CC_OCC, P(mode=7)) == b.CC_E_INVAL
+    assert ok(b.CC_OCC, P(lanes_per_txn=8)) == b.CC_E_INVAL
+    assert ok(b.CC_OCC, P(waves_per_wg=17)) == b.CC_E_INVAL
+    assert ok(b.CC_OCC, P(flags=1 << 20)) == b.CC_E_INVAL
+    assert ok(99) == b.CC_E_INVAL
+    # the pre-check round exists for OCC, TicToc, TO and MVCC only, and its two flags exclude each other
+    for name in ("occ", "tictoc", "to", "mvcc"):
+        for f in (b.CC_RUN_PRECHECK, b.CC_RUN_NO_PRECHECK):
+            assert ok(b.SCHEMES[name], P(flags=f)) == b.CC_OK, name
+        assert ok(b.SCHEMES[name], P(flags=b.CC_RUN_PRECHECK | b.CC_RUN_NO_PRECHECK)) == b.CC_E_INVAL
+    for name in ("2pl_nw", "2pl_wd", "gacco", "gputx"):
+        for f in (b.CC_RUN_PRECHECK, b.CC_RUN_NO_PRECHECK):
+            assert ok(b.SCHEMES[name], P(flags=f)) == b.CC_E_INVAL, name
+    # eager install is an OCC option
+    assert ok(b.CC_OCC, P(flags=b.CC_RUN_EAGER_INSTALL)) == b.CC_OK
+    for name in ("2pl_nw", "2pl_wd", "to", "mvcc", "tictoc", "gacco", "gputx"):
+        assert ok(b.SCHEMES[name], P(flags=b.CC_RUN_EAGER_INSTALL)) == b.CC_E_INVAL, name
+    # the retry-when-free flag is reserved and always rejected
+    for sch in range(8):
+        assert ok(sch, P(flags=b.CC_RUN_WAIT_UNLOCK)) == b.CC_E_INVAL
+    # options of other schemes, and what GaccO / GPUTx do not run
+    assert ok(b.CC_OCC, P(flags=b.CC_RUN_SHARED_READS)) == b.CC_E_INVAL
+    assert ok(b.CC_GACCO, P(flags=b.CC_RUN_SHARED_READS)) == b.CC_OK
+    assert ok(b.CC_GPUTX, P(flags=b.CC_RUN_SHARED_READS)) == b.CC_E_INVAL
+    assert ok(b.CC_OCC, P(wait_limit_us=5)) == b.CC_E_INVAL
+    assert ok(b.CC_GACCO, P(wait_limit_us=5)) == b.CC_OK
+    for sch in (b.CC_GACCO, b.CC_GPUTX):
+        assert ok(sch, P(mode=b.CC_MODE_EPOCH)) == b.CC_E_INVAL
+        assert ok(sch, P(flags=b.CC_RUN_LATCH)) == b.CC_E_INVAL
+    assert ok(b.CC_OCC, P(flags=b.CC_RUN_LATCH, mode=b.CC_MODE_EPOCH)) == b.CC_OK

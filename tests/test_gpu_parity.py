@@ -6,6 +6,8 @@ element, and add-only batches end in the order-free closed form.  Special
 cases pin outputs with no GPU input at all (single team = serial execution,
 read-only batches, disjoint keys), and tiny batches are brute-forced.
 """
+import functools
+
 import numpy as np
 import pytest
 
@@ -269,6 +271,28 @@ def test_order_entry(scheme, warehouses):
     assert oracle.order_entry_invariants(tabs, final, b, out["status"] == 1) == []
 
 
+@functools.lru_cache(maxsize=1)
+def _order_entry_64():
+    # the order-entry configuration at its largest size: 64 warehouses (6.4M stock rows, 1.92M customers)
+    return wl.order_entry_workload(64, 20_000, seed=64)
+
+
+@pytest.mark.parametrize("scheme", IMPLEMENTED + ["gacco", "gputx"])
+def test_order_entry_64_warehouses(scheme):
+    tabs, b = _order_entry_64()
+    print(f"[gpu] order-entry W=64 {scheme}: {b.n_txns} txns, {b.total_ops} ops", flush=True)
+    out, reads, final, st = run_batch(tabs, b, scheme)
+    assert "error" not in st, st["error"]
+    assert np.all(out["status"] == oracle.COMMITTED)
+    if scheme in ("gacco", "gputx"):
+        exp_fin, exp_reads = oracle.id_order_expected(tabs, b)
+        assert np.array_equal(np.asarray(reads, np.int64), exp_reads)
+        assert all(np.array_equal(g, x) for g, x in zip(final, exp_fin))
+    rep = check(tabs, b, out, reads, final)
+    assert rep.ok, rep
+    assert oracle.order_entry_invariants(tabs, final, b, out["status"] == 1) == []
+
+
 @pytest.mark.parametrize("scheme", ["to", "mvcc"])
 def test_timestamp_overflow_is_reported(scheme):
     bb = binding()
@@ -298,6 +322,24 @@ def test_epoch_mode(scheme):
     tabs, b = wl.kv_workload(n_rows=100_000, n_fields=4, n_txns=20_000, ops=(2, 64), theta=0.8, seed=21)
     out, reads, final, st = run_and_check(tabs, b, scheme, mode=bb.CC_MODE_EPOCH)
     assert st["epochs"] >= 4 and st["epochs"] % 4 == 0
+
+
+@functools.lru_cache(maxsize=1)
+def _uneven_full():
+    # the batching configuration at its largest batch: 2^20 transactions of 2-64 ops, Zipf 0.8,
+    # on the 10M-row x 10-field table
+    return wl.kv_workload(n_txns=1 << 20, ops=(2, 64), theta=0.8, seed=0)
+
+
+@pytest.mark.parametrize("scheme", ["occ", "tictoc"])
+def test_epoch_mode_full_batch(scheme):
+    bb = binding()
+    tabs, b = _uneven_full()
+    print(f"[gpu] epoch mode, 2^20 uneven txns ({b.total_ops} ops), {scheme}", flush=True)
+    out, reads, final, st = run_and_check(tabs, b, scheme, mode=bb.CC_MODE_EPOCH)
+    assert st["epochs"] >= 4
+    assert np.array_equal(final[0], oracle.final_add_only(tabs, b)[0])
+    print(f"[gpu] epochs={st['epochs']} passes={st['passes']} {b.n_txns / (st['run_ns'] * 1e-9):.3e} txn/s", flush=True)
 
 
 @pytest.mark.parametrize("scheme", ["occ", "tictoc"])

@@ -69,6 +69,45 @@ def test_serve_alone_vs_mix():
 
 
 @pytest.mark.parametrize("scheme", ["occ", "mvcc"])
+def test_serve_alone_vs_mix_full_size(scheme):
+    # the serving configuration's shape: the 10M-row x 10-field key-value table (8-32 ops, Zipf 0.9)
+    # mixed 50/50 with order-entry at 8 warehouses, 50k Poisson arrivals at 2M txn/s offered
+    kw = dict(kv_rows=10_000_000, isolated_frac=0.05, seed=35)
+    tabs, mix, arr, m = wl.serve_stream(50_000, 2e6, **kw)
+    _, alone, arr_a, ma = wl.serve_stream(50_000, 2e6, with_oe=False, **kw)
+    print(f"[gpu] serving full size {scheme}: mix {mix.n_txns} txns, alone {alone.n_txns}", flush=True)
+    out_m, reads_m, fin_m, st_m = serve(tabs, mix, arr, scheme)
+    out_a, reads_a, fin_a, st_a = serve(tabs, alone, arr_a, scheme)
+    rep = check(tabs, mix, out_m, reads_m, fin_m)
+    assert rep.ok, rep
+    rep = check(tabs, alone, out_a, reads_a, fin_a)
+    assert rep.ok, rep
+    assert np.all(out_m["commit_ns"] + 10 >= arr) and np.all(out_a["commit_ns"] + 10 >= arr_a)
+    cf = oracle.final_add_only([tabs[0]], alone)[0]
+    assert np.array_equal(fin_a[0], cf) and np.array_equal(fin_m[0], cf)
+    assert oracle.order_entry_invariants(tabs[1:], fin_m[1:], _oe_part(mix, m), out_m["status"][~m["is_kv"]] == 1) == []
+    kv_ids_mix = np.nonzero(m["is_kv"])[0]
+    iso_a = np.nonzero(ma["is_isolated"])[0]
+    assert len(iso_a) > 1000
+    for t_a in iso_a:
+        ra = reads_a[alone.txn_slice(int(t_a))]
+        rm = reads_m[mix.txn_slice(int(kv_ids_mix[t_a]))]
+        assert np.array_equal(ra, rm)
+    print(f"[gpu] p50/p99 mix {st_m['lat_p50_ns'] / 1e6:.3f}/{st_m['lat_p99_ns'] / 1e6:.3f} ms, "
+          f"alone {st_a['lat_p50_ns'] / 1e6:.3f}/{st_a['lat_p99_ns'] / 1e6:.3f} ms", flush=True)
+
+
+def _oe_part(mix, m):
+    """The order-entry transactions of a mixed stream as a batch over the order-entry tables alone."""
+    oe_ids = np.nonzero(~m["is_kv"])[0]
+    part = wl.concat_batches([(mix, oe_ids)])
+    part.table = (part.table - 1).astype(np.uint16)
+    part.meta = {"is_new_order": np.array([bool((part.table[part.txn_slice(i)] == wl.T_ORDER).any())
+                                           for i in range(part.n_txns)])}
+    return part
+
+
+@pytest.mark.parametrize("scheme", ["occ", "mvcc"])
 def test_serve_small_budget_throttles_but_loses_nothing(scheme):
     bb = binding()
     tabs, b, arr, m = wl.serve_stream(3_000, 20e6, kv_rows=100_000, seed=33)
