@@ -91,6 +91,31 @@ __device__ __forceinline__ void w_st(const RunArgs &a, uint64_t *w, uint64_t v) 
   else st_word(w, v);
 }
 
+// An update whose kind is data: one call site, and so one spin loop, serves
+// lanes that need different updates at the same program point.  With LATCH
+// this matters for forward progress: when two sibling branches each took a
+// latch, the compiler may hoist their identical latch CAS above the branch,
+// so a lane of one branch holds its latch while masked off until the other
+// branch's spin loop has finished -- and a lane of that loop spinning on the
+// same latch never gets it.  Returns the word before the update; WOP_CAS
+// (x = expected, y = desired) succeeded iff the result equals x.
+enum WordOp : uint32_t { WOP_ADD = 0, WOP_AND = 1, WOP_CAS = 2 };
+
+template <bool LATCH, bool STRICT>
+__device__ __forceinline__ uint64_t w_apply(const RunArgs &a, uint64_t *w, uint32_t op, uint64_t x, uint64_t y) {
+  if constexpr (LATCH) {
+    return latched<STRICT>(a, w, [&](uint64_t o) {
+      return op == WOP_ADD ? o + x : (op == WOP_AND ? (o & x) : (o == x ? y : o));
+    });
+  } else {
+    if (op == WOP_ADD) return add_word(w, x);
+    if (op == WOP_AND) return and_word(w, x);
+    uint64_t e = x;
+    (void)cas_word(w, &e, y);
+    return e;
+  }
+}
+
 // ===========================================================================
 // OCC, Silo-style (paper Section 2 "Optimistic Concurrency Control";
 // Section 3.5 "OCC"; control word per row = lock bit + 63-bit TID, Table 2).
@@ -246,18 +271,14 @@ __device__ __forceinline__ int tpl_attempt(const Team<L> &t, Slots<K> &s, bool a
     shared[k] = false;
     if (active && s.valid[k] && op_leader(s.rowk[k])) {
       uint64_t *w = a.words + op_row(s.rowk[k]);
-      if (op_written(s.rowk[k])) {
-        uint64_t expected = 0;
-        s.got[k] = w_cas<LATCH, STRICT>(a, w, &expected, TPL_EXCL | ((uint64_t)(txn & 0x7FFFFFFFu) << 32));
-        if (!s.got[k] && (expected & TPL_EXCL) && blk == ~0u) blk = op_row(s.rowk[k]);
-        fail |= !s.got[k];
-      } else {
-        const uint64_t old = w_add<LATCH, STRICT>(a, w, 1ull);
-        shared[k] = true;  // our increment is in the word until we take it out
-        s.got[k] = !(old & TPL_EXCL);
-        if (!s.got[k] && blk == ~0u) blk = op_row(s.rowk[k]);
-        fail |= !s.got[k];
-      }
+      // exclusive: CAS 0 -> EXCL|holder; shared: add one holder
+      const bool wr = op_written(s.rowk[k]);
+      const uint64_t old = w_apply<LATCH, STRICT>(a, w, wr ? WOP_CAS : WOP_ADD, wr ? 0ull : 1ull,
+                                                  TPL_EXCL | ((uint64_t)(txn & 0x7FFFFFFFu) << 32));
+      shared[k] = !wr;  // a shared increment is in the word until we take it out
+      s.got[k] = wr ? old == 0 : !(old & TPL_EXCL);
+      if (!s.got[k] && (!wr || (old & TPL_EXCL)) && blk == ~0u) blk = op_row(s.rowk[k]);
+      fail |= !s.got[k];
     }
   }
   order_point<STRICT>();
@@ -268,8 +289,8 @@ __device__ __forceinline__ int tpl_attempt(const Team<L> &t, Slots<K> &s, bool a
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       uint64_t *w = a.words + op_row(s.rowk[k]);
-      if (shared[k]) w_add<LATCH, STRICT>(a, w, ~0ull);
-      else if (s.got[k]) w_and<LATCH, STRICT>(a, w, TPL_COUNT);
+      if (shared[k] || s.got[k])
+        (void)w_apply<LATCH, STRICT>(a, w, shared[k] ? WOP_ADD : WOP_AND, shared[k] ? ~0ull : TPL_COUNT, 0);
     }
   }
 #pragma unroll
@@ -283,8 +304,8 @@ __device__ __forceinline__ int tpl_attempt(const Team<L> &t, Slots<K> &s, bool a
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       uint64_t *w = a.words + op_row(s.rowk[k]);
-      if (shared[k]) w_add<LATCH, STRICT>(a, w, ~0ull);
-      else if (s.got[k]) w_and<LATCH, STRICT>(a, w, TPL_COUNT);
+      if (shared[k] || s.got[k])
+        (void)w_apply<LATCH, STRICT>(a, w, shared[k] ? WOP_ADD : WOP_AND, shared[k] ? ~0ull : TPL_COUNT, 0);
     }
   }
   *hi = 0;
@@ -332,17 +353,11 @@ __device__ __forceinline__ int tplwd_attempt(const Team<L> &t, Slots<K> &s, bool
     if (active && s.valid[k] && op_leader(s.rowk[k]) && !s.got[k]) {
       uint64_t *w = a.words + op_row(s.rowk[k]);
       uint64_t seen = 0;
-      if (op_written(s.rowk[k])) {
-        uint64_t expected = 0;
-        s.got[k] = w_cas<LATCH, STRICT>(a, w, &expected, TPL_EXCL | (me << 32));
-        seen = expected;
-      } else {
-        const uint64_t old = w_add<LATCH, STRICT>(a, w, 1ull);
-        s.got[k] = !(old & TPL_EXCL);
-        s.sh[k] = s.got[k];
-        if (!s.got[k]) w_add<LATCH, STRICT>(a, w, ~0ull);  // take the increment back out
-        seen = old;
-      }
+      const bool wr = op_written(s.rowk[k]);
+      seen = w_apply<LATCH, STRICT>(a, w, wr ? WOP_CAS : WOP_ADD, wr ? 0ull : 1ull, TPL_EXCL | (me << 32));
+      s.got[k] = wr ? seen == 0 : !(seen & TPL_EXCL);
+      s.sh[k] = !wr && s.got[k];
+      if (!wr && !s.got[k]) (void)w_apply<LATCH, STRICT>(a, w, WOP_ADD, ~0ull, 0);  // take the increment back out
       if (!s.got[k]) {
         if (blk == ~0u) blk = op_row(s.rowk[k]);
         const uint64_t holder = (seen >> 32) & 0x7FFFFFFFu;
@@ -361,8 +376,7 @@ __device__ __forceinline__ int tplwd_attempt(const Team<L> &t, Slots<K> &s, bool
     for (int k = 0; k < K; ++k) {
       if (!s.got[k]) continue;
       uint64_t *w = a.words + op_row(s.rowk[k]);
-      if (s.sh[k]) w_add<LATCH, STRICT>(a, w, ~0ull);
-      else w_and<LATCH, STRICT>(a, w, TPL_COUNT);
+      (void)w_apply<LATCH, STRICT>(a, w, s.sh[k] ? WOP_ADD : WOP_AND, s.sh[k] ? ~0ull : TPL_COUNT, 0);
       s.got[k] = false;
       s.sh[k] = false;
     }
@@ -380,8 +394,7 @@ __device__ __forceinline__ int tplwd_attempt(const Team<L> &t, Slots<K> &s, bool
     for (int k = 0; k < K; ++k) {
       if (!s.got[k]) continue;
       uint64_t *w = a.words + op_row(s.rowk[k]);
-      if (s.sh[k]) w_add<LATCH, STRICT>(a, w, ~0ull);
-      else w_and<LATCH, STRICT>(a, w, TPL_COUNT);
+      (void)w_apply<LATCH, STRICT>(a, w, s.sh[k] ? WOP_ADD : WOP_AND, s.sh[k] ? ~0ull : TPL_COUNT, 0);
     }
   }
   *hi = 0;
@@ -459,14 +472,18 @@ __device__ __forceinline__ int to_attempt(const Team<L> &t, Slots<K> &s, bool ac
       uint64_t w = ld_word(wp);
       bool done = false, bad = false;
       for (int it = 0; it < CAS_RETRIES && !done && !bad; ++it) {
+        // a write marks the row dirty, a read raises RTS to ts: either way
+        // one CAS, issued from a single site (see w_apply)
+        bool try_cas = false;
+        uint64_t desired = 0;
         if (w & TO_DIRTY) {
           bad = true;
         } else if (op_written(s.rowk[k])) {
           if (ts < to_rts(w) || ts < to_wts(w)) {
             bad = true;
-          } else if (w_cas<LATCH, STRICT>(a, wp, &w, w | TO_DIRTY)) {
-            done = true;
-            s.got[k] = true;
+          } else {
+            try_cas = true;
+            desired = w | TO_DIRTY;
           }
         } else if (ts < to_wts(w)) {
           if (MV) {
@@ -477,8 +494,13 @@ __device__ __forceinline__ int to_attempt(const Team<L> &t, Slots<K> &s, bool ac
           }
         } else if (!lead || to_rts(w) >= ts) {
           done = true;
-        } else if (w_cas<LATCH, STRICT>(a, wp, &w, to_word(ts, to_wts(w)))) {
+        } else {
+          try_cas = true;
+          desired = to_word(ts, to_wts(w));
+        }
+        if (try_cas && w_cas<LATCH, STRICT>(a, wp, &w, desired)) {
           done = true;
+          s.got[k] = op_written(s.rowk[k]);
         }
       }
       s.v[k] = w;
