@@ -107,6 +107,8 @@ enum cc_op_kind { CC_READ = 0, CC_ADD = 1, CC_COND_ADD = 2, CC_WRITE_SLOT = 3 };
 #define CC_MAX_TABLES 16
 #define CC_MAX_TOTAL_ROWS (1ull << 28)   /* summed over all tables */
 #define CC_MAX_TOTAL_CELLS (1ull << 32)  /* summed rows x fields over all tables */
+#define CC_STATIC_MAX_TXNS (1u << 18)     /* cc_run_static: transactions per call */
+#define CC_STATIC_MAX_OPS (1u << 20)      /* cc_run_static: ops per call */
 
 typedef struct {
   uint32_t row;   /* row index within the table */
@@ -446,6 +448,41 @@ cc_status cc_stats(cc_ctx *ctx, uint64_t batch_id, uint64_t *counters, uint32_t 
 
 /* Free a batch's device buffers. */
 cc_status cc_release_batch(cc_ctx *ctx, uint64_t batch_id);
+
+/*
+ * Allocation-free run, for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  One call validates, packs and runs a batch that is already in
+ * device memory and writes its outcomes into the caller's device arrays, as
+ * cc_submit_batch (on_device = 1) + cc_run + cc_fetch_outcomes
+ * (dst_on_device = 1) + cc_release_batch would, and allocates nothing.
+ *
+ *   txns, ops            device memory of the context's device, n_txns and
+ *                        n_ops entries, as for cc_submit_batch; borrowed for
+ *                        the call and not modified.
+ *   per_txn, per_op_read device memory, n_txns and n_ops entries; the run's
+ *                        outcomes and read values (entries of ops that no
+ *                        transaction names are 0).
+ *   scheme               CC_OCC, CC_2PL_NW, CC_2PL_WD, CC_TO or CC_TICTOC;
+ *                        the others need buffers sized by the batch
+ *                        (CC_E_INVAL).
+ *   params               as for cc_run (NULL: defaults); CC_MODE_PLAIN only
+ *                        and no CC_RUN_LATCH (CC_E_INVAL).
+ *   counters             optional host array of n_counters entries that
+ *                        receives the run's statistics (enum cc_stat order;
+ *                        the latency percentiles are not computed: 0).
+ * Limits: n_txns <= CC_STATIC_MAX_TXNS and n_ops <= CC_STATIC_MAX_OPS, else
+ * CC_E_RANGE before anything touches the device.  The descriptors, the
+ * pending list and the ingest words live in one 23 MiB array per device
+ * (static device memory, held until the process ends).  Every call on a
+ * device, from any context or thread, shares that array: calls that overlap
+ * on one GPU race, and the caller must serialise them.  Each call clears what
+ * it reads before using it.  Errors: as cc_submit_batch and cc_run; a
+ * malformed batch is reported before any transaction runs.
+ */
+cc_status cc_run_static(cc_ctx *ctx, const cc_txn *txns, uint64_t n_txns, const cc_op *ops, uint64_t n_ops,
+                        int scheme, const cc_run_params *params, cc_outcome *per_txn, int64_t *per_op_read,
+                        uint64_t *counters, uint32_t n_counters);
 
 /*
  * Memory micro-benchmarks that measure the roofline of the transaction

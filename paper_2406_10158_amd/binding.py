@@ -45,6 +45,8 @@ STAT_NAMES = ["committed", "attempts", "abort_lock", "abort_valid", "kernel_ns",
               "occ_r1_ns", "occ_r2_ns", "occ_r3_ns", "occ_r4_ns", "prep_ns", "index_ns", "wd_waits", "ksets",
               "packed_state"]
 CC_N_STATS = 32
+CC_STATIC_MAX_TXNS = 1 << 18
+CC_STATIC_MAX_OPS = 1 << 20
 
 OP_DTYPE = np.dtype([("row", "<u4"), ("table", "<u2"), ("field", "u1"), ("kind", "u1"), ("arg", "<i8")])
 TXN_DTYPE = np.dtype([("first_op", "<u8"), ("n_ops", "<u4"), ("reserved", "<u4")])
@@ -88,6 +90,8 @@ _SIGS = {
     "cc_stats": (_S, [_P, ctypes.c_uint64, _P, ctypes.c_uint32]),
     "cc_set_arrivals": (_S, [_P, ctypes.c_uint64, _P, ctypes.c_uint64]),
     "cc_release_batch": (_S, [_P, ctypes.c_uint64]),
+    "cc_run_static": (_S, [_P, _P, ctypes.c_uint64, _P, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(cc_run_params),
+                           _P, _P, _P, ctypes.c_uint32]),
     "cc_device_info": (_S, [_P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]),
     "cc_probe": (_S, [_P, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
                       ctypes.POINTER(ctypes.c_double)]),
@@ -278,6 +282,18 @@ def cc_stats(ctx, batch_id: int) -> dict:
     c = np.zeros(CC_N_STATS, np.uint64)
     _check(lib.cc_stats(ctx, batch_id, _ptr(c), CC_N_STATS), ctx)
     return {n: int(c[i]) for i, n in enumerate(STAT_NAMES)}
+
+
+def cc_run_static(ctx, txns, ops, scheme: int, params: cc_run_params | None = None, per_txn=None,
+                  per_op_read=None) -> dict:
+    """Allocation-free run of a device-resident batch (device tensors of ABI structs as bytes) into the
+    caller's device output tensors; returns the run's statistics."""
+    n_txns, n_ops = _count(txns, TXN_DTYPE.itemsize), _count(ops, OP_DTYPE.itemsize)
+    ctr = np.zeros(CC_N_STATS, np.uint64)
+    p = ctypes.byref(params) if params is not None else None
+    _check(lib.cc_run_static(ctx, _ptr(txns), n_txns, _ptr(ops), n_ops, scheme, p, _ptr(per_txn),
+                             _ptr(per_op_read), _ptr(ctr), CC_N_STATS), ctx)
+    return {k: int(v) for k, v in zip(STAT_NAMES, ctr)}
 
 
 def cc_release_batch(ctx, batch_id: int) -> None:

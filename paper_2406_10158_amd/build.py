@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcc.so")
 SOURCES = [os.path.join(CSRC, f) for f in
            ("txn_occ.hip", "txn_2pl.hip", "txn_2plwd.hip", "txn_to.hip", "txn_mvcc.hip", "txn_tictoc.hip", "gacco.hip",
-            "gacco_exec.hip", "gputx.hip", "index.hip", "ingest.hip", "kernels.hip", "roofline.hip", "api.cpp")]
+            "gacco_exec.hip", "gputx.hip", "index.hip", "ingest.hip", "kernels.hip", "roofline.hip", "static_run.hip", "api.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else "hipcc")
 ARCH = "gfx950"
 # Packed FP32 instructions are disabled in all device code.

@@ -76,6 +76,7 @@ struct cc_ctx {
   uint32_t *d_latch = nullptr;        // CC_RUN_LATCH: one latch per global row
   uint64_t *d_kstate = nullptr;       // GPUTx: per-row rank state
   uint64_t *d_ingest = nullptr;       // device-side batch ingest: reduced results
+  unsigned char *d_static = nullptr;  // cc_run_static: this device's static scratch (never freed)
   std::map<uint64_t, Batch> batches;
   uint64_t next_batch = 1;
   hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -294,6 +295,15 @@ cc_status cc_init(cc_ctx **out, const cc_config *cfg) {
       return CC_E_HIP;
     }
   }
+  // the allocation-free run's scratch on this device (the device is current)
+  void *sp = nullptr;
+  const hipError_t se = static_scratch_address(dev, &sp);
+  if (se != hipSuccess) {
+    cc_destroy(c);
+    g_init_err = std::string("device address of the static scratch: ") + hipGetErrorString(se);
+    return CC_E_HIP;
+  }
+  c->d_static = (unsigned char *)sp;
   *out = c;
   return CC_OK;
 }
@@ -1073,15 +1083,12 @@ cc_status cc_check_run_params(int scheme, const cc_run_params *pp) {
   return check_run_params(nullptr, scheme, pp ? *pp : cc_run_params{});
 }
 
-cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
-  if (!c) return CC_E_INVAL;
-  auto it = c->batches.find(batch_id);
-  if (it == c->batches.end()) return fail(c, CC_E_NOBATCH, "unknown batch");
-  Batch &b = it->second;
-  cc_run_params p{};
-  if (pp) p = *pp;
-  const cc_status pst = check_run_params(c, b.scheme, p);
-  if (pst) return pst;
+}  // extern "C"
+
+// One run of a batch whose parameters have been checked (cc_run, and
+// cc_run_static with a batch that lives in the static scratch).  host_stats:
+// copy the outcomes back for the latency percentiles.
+static cc_status run_batch(cc_ctx *c, Batch &b, const cc_run_params &p, bool host_stats) {
   if (p.mode == CC_MODE_SERVE && b.n_txns && !b.d_arrival)
     return fail(c, CC_E_STATE, "CC_MODE_SERVE needs cc_set_arrivals first");
   uint32_t lanes = p.lanes_per_txn;
@@ -1300,7 +1307,7 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
     b.stats[CC_STAT_OCC_R1_NS + i] = (uint64_t)((double)h.stats[DS_R1 + i] * ns_per_tick);
   b.stats[CC_STAT_INDEX_NS] = (uint64_t)((double)ms_index * 1e6);
   b.ran = true;
-  if (b.n_txns) {
+  if (b.n_txns && host_stats) {
     std::vector<cc_outcome> o(b.n_txns);
     HIP_OR(c, hipMemcpy(o.data(), b.d_out, b.n_txns * sizeof(cc_outcome), hipMemcpyDeviceToHost));
     if (p.mode == CC_MODE_SERVE)
@@ -1318,6 +1325,88 @@ cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
     return fail(c, CC_E_LIVELOCK, msg);
   }
   return CC_OK;
+}
+
+extern "C" {
+
+cc_status cc_run(cc_ctx *c, uint64_t batch_id, const cc_run_params *pp) {
+  if (!c) return CC_E_INVAL;
+  auto it = c->batches.find(batch_id);
+  if (it == c->batches.end()) return fail(c, CC_E_NOBATCH, "unknown batch");
+  Batch &b = it->second;
+  cc_run_params p{};
+  if (pp) p = *pp;
+  const cc_status pst = check_run_params(c, b.scheme, p);
+  if (pst) return pst;
+  return run_batch(c, b, p, true);
+}
+
+cc_status cc_run_static(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, const cc_op *ops, uint64_t n_ops, int scheme,
+                        const cc_run_params *pp, cc_outcome *per_txn, int64_t *per_op_read, uint64_t *counters,
+                        uint32_t n_counters) {
+  if (!c) return CC_E_INVAL;
+  if ((n_txns && (!txns || !per_txn)) || (n_ops && (!ops || !per_op_read)) || (n_counters && !counters))
+    return fail(c, CC_E_INVAL, "null array");
+  if (scheme != CC_OCC && scheme != CC_2PL_NW && scheme != CC_2PL_WD && scheme != CC_TO && scheme != CC_TICTOC)
+    return fail(c, CC_E_INVAL, "cc_run_static runs CC_OCC, CC_2PL_NW, CC_2PL_WD, CC_TO and CC_TICTOC");
+  cc_run_params p{};
+  if (pp) p = *pp;
+  const cc_status pst = check_run_params(c, scheme, p);
+  if (pst) return pst;
+  if (p.mode != CC_MODE_PLAIN) return fail(c, CC_E_INVAL, "cc_run_static runs in CC_MODE_PLAIN only");
+  if (p.flags & CC_RUN_LATCH) return fail(c, CC_E_INVAL, "cc_run_static does not take CC_RUN_LATCH");
+  if (n_txns > CC_STATIC_MAX_TXNS || n_ops > CC_STATIC_MAX_OPS)
+    return fail(c, CC_E_RANGE, "batch larger than the static scratch (CC_STATIC_MAX_TXNS, CC_STATIC_MAX_OPS)");
+  if (!c->frozen) return fail(c, CC_E_STATE, "load the tables before running a batch");
+  if (!c->d_static) return fail(c, CC_E_STATE, "no static scratch on this context's device");
+  if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
+  if (!device_range(c, txns, n_txns * sizeof(cc_txn)) || !device_range(c, ops, n_ops * sizeof(cc_op)) ||
+      !device_range(c, per_txn, n_txns * sizeof(cc_outcome)) || !device_range(c, per_op_read, n_ops * sizeof(int64_t)))
+    return fail(c, CC_E_INVAL, "arrays must lie in device memory of the context's device");
+  unsigned char *sc = c->d_static;
+  Batch b;
+  b.scheme = scheme;
+  b.n_txns = n_txns;
+  b.n_ops = n_ops;
+  b.d_ops = (DevOp *)(sc + STATIC_OFF_OPS);
+  b.d_txns = (DevTxn *)(sc + STATIC_OFF_TXNS);
+  b.d_list = (uint32_t *)(sc + STATIC_OFF_LIST);
+  b.d_out = (DevOutcome *)per_txn;
+  b.d_reads = per_op_read;
+  IngestArgs ia{};
+  ia.txns = txns;
+  ia.ops = ops;
+  ia.op_keys = nullptr;
+  ia.n_txns = n_txns;
+  ia.n_ops = n_ops;
+  ia.n_tables = (uint32_t)c->tables.size();
+  for (uint32_t t = 0; t < ia.n_tables; ++t) {
+    const Table &tb = c->tables[t];
+    ia.tab[t] = IngestTable{tb.n_rows, tb.row_base, tb.elem_base, tb.n_fields, 0u};
+  }
+  ia.dops = b.d_ops;
+  ia.dtx = b.d_txns;
+  ia.owner = (uint32_t *)(sc + STATIC_OFF_OWNER);
+  ia.meta = nullptr;
+  ia.rows0 = nullptr;
+  ia.out = (uint64_t *)(sc + STATIC_OFF_INGEST);
+  uint64_t res[INGEST_N] = {};
+  hipError_t e = launch_ingest(c->stream, ia);
+  if (e == hipSuccess) e = launch_fill_zero(c->stream, per_op_read, n_ops);
+  if (e == hipSuccess) e = hipMemcpyAsync(res, ia.out, sizeof res, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "batch ingest");
+  if (res[INGEST_ERR] != ~0ull) {
+    const uint64_t w = res[INGEST_ERR];
+    const cc_status code = -(cc_status)(w & 15u);
+    return fail(c, code, std::string(ingest_message((uint32_t)((w >> 4) & 0xFFFu))) + " (transaction " +
+                             std::to_string(w >> 16) + ")");
+  }
+  b.max_ops = (uint32_t)res[INGEST_MAX_OPS];
+  b.has_slot = res[INGEST_HAS_SLOT] != 0;
+  const cc_status st = run_batch(c, b, p, false);
+  for (uint32_t i = 0; i < n_counters; ++i) counters[i] = i < CC_N_STATS ? b.stats[i] : 0;
+  return st;
 }
 
 cc_status cc_fetch_outcomes(cc_ctx *c, uint64_t batch_id, cc_outcome *per_txn, int64_t *per_op, int on_device) {

@@ -283,6 +283,25 @@ CCE_DECLARE_LAUNCH(launch_txn_tictoc)
 CCE_DECLARE_LAUNCH(launch_txn_2plwd)
 #undef CCE_DECLARE_LAUNCH
 
+// The allocation-free run's device buffers (static_run.hip): one file-scope
+// array per device, carved into the regions below.  Sizes follow
+// CC_STATIC_MAX_TXNS and CC_STATIC_MAX_OPS (cc.h).
+constexpr uint64_t STATIC_OFF_OPS = 0;
+constexpr uint64_t STATIC_OFF_TXNS = STATIC_OFF_OPS + (uint64_t)CC_STATIC_MAX_OPS * sizeof(DevOp);
+constexpr uint64_t STATIC_OFF_LIST = STATIC_OFF_TXNS + (uint64_t)CC_STATIC_MAX_TXNS * sizeof(DevTxn);
+constexpr uint64_t STATIC_OFF_OWNER = STATIC_OFF_LIST + (uint64_t)CC_STATIC_MAX_TXNS * sizeof(uint32_t);
+constexpr uint64_t STATIC_OFF_INGEST = STATIC_OFF_OWNER + (uint64_t)CC_STATIC_MAX_OPS * sizeof(uint32_t);
+constexpr uint64_t STATIC_SCRATCH_BYTES = STATIC_OFF_INGEST + 256;
+static_assert(STATIC_OFF_TXNS % 256 == 0 && STATIC_OFF_LIST % 256 == 0 && STATIC_OFF_OWNER % 256 == 0 &&
+                  STATIC_OFF_INGEST % 256 == 0 && INGEST_N * sizeof(uint64_t) <= 256,
+              "static scratch regions are 256-byte aligned");
+// Device address of `device`'s array; `device` must be current.  Resolved
+// with hipGetSymbolAddress on a device's first call, then kept.
+constexpr int STATIC_MAX_DEVICES = 64;
+hipError_t static_scratch_address(int device, void **ptr);
+// Clears n int64 words with a fill kernel.
+hipError_t launch_fill_zero(hipStream_t s, int64_t *p, uint64_t n);
+
 // Memory micro-benchmarks (roofline.hip); see cc_probe in cc.h.
 hipError_t run_probe(hipStream_t s, int kind, uint64_t footprint_bytes, uint64_t n_ops, int peer, double *ms_out,
                      uint64_t *err_out, int n_cu);

@@ -197,6 +197,7 @@ def test_every_entry_point_rejects_a_null_context(b):
         "cc_set_arrivals": lambda: lib.cc_set_arrivals(None, 1, None, 0),
         "cc_stats": lambda: lib.cc_stats(None, 1, None, 0),
         "cc_release_batch": lambda: lib.cc_release_batch(None, 1),
+        "cc_run_static": lambda: lib.cc_run_static(None, None, 0, None, 0, 0, None, None, None, None, 0),
         "cc_device_info": lambda: lib.cc_device_info(None, None, None),
         "cc_probe": lambda: lib.cc_probe(None, 0, 1 << 20, 1, 1, None),
         "cc_init": lambda: lib.cc_init(None, None),
