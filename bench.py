@@ -537,6 +537,15 @@ def main():
                                         if measured["active_bound"] == "contention" else
                                         "random loads, atomics, stores and streamed bytes at the probed rates")}
 
+    # the batch's most written row during the last step (OCC's lock-hold counters)
+    hot_row = None
+    if args.scheme == "occ" and st["hot_acq"]:
+        held = st["hot_hold_ns"] / max(st["kernel_ns"], 1)
+        hot_row = {"writes_H": st["hot_writes"], "lock_acquisitions": st["hot_acq"],
+                   "failed_holds": st["hot_failed"], "held_share": round(held, 4), "idle_share": round(1 - held, 4),
+                   "hold_per_acquisition_ns": round(st["hot_hold_ns"] / st["hot_acq"], 1),
+                   "kernel_ns_per_hot_commit": round(st["kernel_ns"] / max(st["hot_writes"], 1), 1)}
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(tables, batch, out_last, reads_last, final_last)
@@ -560,6 +569,7 @@ def main():
                               "device-to-device from a pristine copy before each step, outside the events"},
         "roofline": roofline,
         "measured_roofline": measured,
+        "hot_row": hot_row,
         "cpu_baseline": cpu,
         "host_wall_s": round(wall, 3),
     }

@@ -188,8 +188,10 @@ enum cc_mode { CC_MODE_PLAIN = 0, CC_MODE_EPOCH = 1, CC_MODE_SERVE = 2 };
 #define CC_RUN_PRECHECK 0x8u      /* OCC, TicToc, TO and MVCC: an extra first round loads every row's word and aborts before
                                      taking any lock if one is held -- on every attempt.  By default it
                                      runs from a transaction's second attempt on (a failure is the
-                                     sign of contention).  CC_E_INVAL for another scheme, or together
-                                     with CC_RUN_NO_PRECHECK */
+                                     sign of contention) when the batch's most written row takes writes
+                                     from at least 2% of its transactions, and never below that, where
+                                     the extra round costs more than it saves.  CC_E_INVAL for another
+                                     scheme, or together with CC_RUN_NO_PRECHECK */
 #define CC_RUN_NO_PRECHECK 0x10u  /* OCC, TicToc, TO and MVCC: never run the pre-check round (CC_E_INVAL for
                                      another scheme) */
 #define CC_RUN_LATCH 0x40u        /* latch variants of the non-deterministic schemes (paper Section 4.2,
@@ -205,15 +207,32 @@ enum cc_mode { CC_MODE_PLAIN = 0, CC_MODE_EPOCH = 1, CC_MODE_SERVE = 2 };
 #define CC_RUN_INDEX_TREE 0x20u   /* keyed batches: look keys up by descending the index's 16-way tree
                                      (one 128-byte node per level) instead of by binary search of the
                                      sorted keys */
+#define CC_RUN_HOT_LAST 0x100u    /* OCC: lock the batch's hottest rows (found at submission: at most 8, each
+                                     written at least a quarter as often as the hottest) in a round of their
+                                     own, after every other row of the transaction is held, so that a hot
+                                     row is held only for the commit rounds and never by an attempt that
+                                     fails on another row's lock.  Off by default: the extra round lengthens
+                                     every attempt and the read rows' validation window, which costs more
+                                     than the shorter holds save.  Not applied with one lane per
+                                     transaction or 16 ops per lane. */
+#define CC_RUN_NO_HOT_LAST 0x200u /* OCC: one lock round for every row, the default (CC_E_INVAL with
+                                     CC_RUN_HOT_LAST) */
 #define CC_RUN_EAGER_INSTALL 0x2u /* OCC only (CC_E_INVAL for another scheme): store new values in the
                                      validation round (undo on abort) instead of after validation
                                      succeeds; measured ~3% slower on the key-value workload, kept for
                                      comparison */
 
 typedef struct {
-  uint32_t lanes_per_txn; /* lanes cooperating on one transaction: 1, 4, 16, 64; 0 = smallest >= longest txn */
-  uint32_t waves_per_wg;  /* 64-lane wavefronts per workgroup, 1..16; 0 = 1 */
-  uint32_t grid;          /* workgroups of the first pass; 0 = one per compute unit */
+  uint32_t lanes_per_txn; /* lanes cooperating on one transaction: 1, 4, 16, 64; 0 = chosen by contention
+                             (see below) */
+  uint32_t waves_per_wg;  /* 64-lane wavefronts per workgroup, 1..16; 0 = chosen by contention */
+  uint32_t grid;          /* workgroups of the first pass; 0 = one per compute unit
+                             Defaults by contention, from the share h of transactions that write the
+                             batch's most written row (counted at submission): below 0.1% (no hot row)
+                             4 lanes per transaction and 4 wavefronts per workgroup when the longest
+                             transaction has at most 64 ops, so that 4096 transactions are in flight;
+                             otherwise one wavefront per workgroup and the smallest lane count
+                             >= the longest transaction, which keeps fewer transactions in flight. */
   uint32_t mode;          /* enum cc_mode */
   uint64_t max_attempts;  /* give up (CC_E_LIVELOCK) after this many attempts of one txn; 0 = 1<<24 */
   uint32_t max_epochs;    /* CC_MODE_EPOCH: epochs before CC_E_LIVELOCK; 0 = 1<<20 */
@@ -265,6 +284,11 @@ enum cc_stat {
   CC_STAT_KSETS = 26,      /* CC_GPUTX: K-sets (largest rank + 1) */
   CC_STAT_PACKED_STATE = 27, /* CC_GPUTX: 1 if the rank pass kept each row's rank state in its turn word
                                 (fewer than 2^20 transactions and 2^24 operations), else 0 */
+  CC_STAT_HOT_ACQ = 28,    /* OCC: acquisitions of the lock of the batch's most written row */
+  CC_STAT_HOT_FAILED = 29, /* OCC: of those, acquisitions whose attempt aborted (a failed hold) */
+  CC_STAT_HOT_HOLD_NS = 30,/* OCC: time that row's lock was held, summed over acquisitions (the rest of
+                              CC_STAT_KERNEL_NS it was free) */
+  CC_STAT_HOT_WRITES = 31, /* writes to the batch's most written row (counted at submission) */
   CC_N_STATS = 32
 };
 

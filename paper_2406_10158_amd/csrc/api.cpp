@@ -47,6 +47,13 @@ struct Batch {
   int epoch_grid = 0;
   bool ran = false;
   uint64_t stats[CC_N_STATS] = {};
+  // counted at submission (find_hot_rows): writes to the most written row,
+  // and the most written rows (most first); hot_known is false for a batch
+  // nobody counted (cc_run_static), which then runs with the contended defaults
+  bool hot_known = false;
+  uint64_t hot_writes = 0;
+  uint32_t n_hot = 0;
+  uint32_t hot_rows[HOT_MAX] = {};
 };
 
 }  // namespace
@@ -678,6 +685,41 @@ cc_status run_gputx(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes,
   return CC_OK;
 }
 
+// The batch's most written rows, counted at submission from its packed
+// descriptors: write accesses (row groups that write) per global row; the
+// most written row, and every row written at least a quarter as often, at
+// most HOT_MAX of them, most written first (ties: lower row first).
+void find_hot_rows(const DevOp *dops, uint64_t n_ops, uint64_t total_rows, Batch &b) {
+  std::vector<uint32_t> cnt(std::max<uint64_t>(total_rows, 1), 0u);
+  for (uint64_t i = 0; i < n_ops; ++i) {
+    const uint32_t rk = dops[i].rowk;
+    if (!(rk & FOLLOWER_BIT) && (rk & WRITTEN_BIT)) ++cnt[rk & ROW_MASK];
+  }
+  uint32_t top = 0;
+  for (uint32_t c : cnt) top = std::max(top, c);
+  b.hot_known = true;
+  b.hot_writes = top;
+  b.n_hot = 0;
+  if (top == 0) return;
+  const uint32_t thr = std::max<uint32_t>(1u, (top + 3) / 4);
+  uint32_t best_c[HOT_MAX] = {}, best_r[HOT_MAX] = {};
+  uint32_t n = 0;
+  for (uint64_t r = 0; r < total_rows; ++r) {
+    const uint32_t c = cnt[r];
+    if (c < thr || (n == (uint32_t)HOT_MAX && c <= best_c[HOT_MAX - 1])) continue;
+    uint32_t i = n < (uint32_t)HOT_MAX ? n++ : (uint32_t)HOT_MAX - 1;
+    while (i > 0 && best_c[i - 1] < c) {
+      best_c[i] = best_c[i - 1];
+      best_r[i] = best_r[i - 1];
+      --i;
+    }
+    best_c[i] = c;
+    best_r[i] = (uint32_t)r;
+  }
+  for (uint32_t i = 0; i < n; ++i) b.hot_rows[i] = best_r[i];
+  b.n_hot = n;
+}
+
 // Run parameters against the scheme, before anything touches the device
 // (cc_check_run_params and cc_run).  c may be NULL (no message kept).
 cc_status check_run_params(cc_ctx *c, int scheme, const cc_run_params &p) {
@@ -689,7 +731,8 @@ cc_status check_run_params(cc_ctx *c, int scheme, const cc_run_params &p) {
     return fail(c, CC_E_INVAL, "lanes_per_txn must be 1, 4, 16 or 64");
   if (p.waves_per_wg > 16) return fail(c, CC_E_INVAL, "waves_per_wg must be 1..16");
   if (p.flags & ~(CC_RUN_STRICT_FENCES | CC_RUN_EAGER_INSTALL | CC_RUN_WAIT_UNLOCK | CC_RUN_PRECHECK |
-                  CC_RUN_NO_PRECHECK | CC_RUN_INDEX_TREE | CC_RUN_LATCH | CC_RUN_SHARED_READS))
+                  CC_RUN_NO_PRECHECK | CC_RUN_INDEX_TREE | CC_RUN_LATCH | CC_RUN_SHARED_READS | CC_RUN_HOT_LAST |
+                  CC_RUN_NO_HOT_LAST))
     return fail(c, CC_E_INVAL, "unknown run flag");
   if ((p.flags & CC_RUN_SHARED_READS) && scheme != CC_GACCO)
     return fail(c, CC_E_INVAL, "CC_RUN_SHARED_READS is a CC_GACCO option");
@@ -723,6 +766,9 @@ cc_status check_run_params(cc_ctx *c, int scheme, const cc_run_params &p) {
     return fail(c, CC_E_INVAL, "the pre-check round exists for CC_OCC, CC_TICTOC, CC_TO and CC_MVCC only");
   if ((p.flags & CC_RUN_EAGER_INSTALL) && scheme != CC_OCC)
     return fail(c, CC_E_INVAL, "CC_RUN_EAGER_INSTALL is a CC_OCC option");
+  const uint32_t hot = CC_RUN_HOT_LAST | CC_RUN_NO_HOT_LAST;
+  if ((p.flags & hot) == hot) return fail(c, CC_E_INVAL, "CC_RUN_HOT_LAST and CC_RUN_NO_HOT_LAST exclude each other");
+  if ((p.flags & hot) && scheme != CC_OCC) return fail(c, CC_E_INVAL, "CC_RUN_HOT_LAST is a CC_OCC option");
   return CC_OK;
 }
 
@@ -896,6 +942,15 @@ static cc_status submit_impl(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, con
       b.d_meta = nullptr;
       b.d_rows = nullptr;
     }
+    if (!b.keyed) {
+      // the packed descriptors come back once, to count the rows' writes
+      std::vector<DevOp> hd(n_ops);
+      if (n_ops && (e = hipMemcpy(hd.data(), b.d_ops, n_ops * sizeof(DevOp), hipMemcpyDeviceToHost)) != hipSuccess) {
+        free_batch(b);
+        return hip_fail(c, e, "batch descriptors");
+      }
+      find_hot_rows(hd.data(), n_ops, c->total_rows, b);
+    }
     const uint64_t id = c->next_batch++;
     c->batches[id] = b;
     *batch_id = id;
@@ -932,6 +987,8 @@ static cc_status submit_impl(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, con
   b.max_ops = max_ops;
   b.has_slot = has_slot;
   b.keyed = keyed;
+  // keyed ops learn their rows only when the index is searched, at the run
+  if (!keyed) find_hot_rows(dops.data(), n_ops, c->total_rows, b);
   hipError_t e = alloc_batch(b, scheme, keyed);
   if (e != hipSuccess) return hip_fail(c, e, "batch allocation");
   auto copy_in = [&]() -> hipError_t {
@@ -1091,12 +1148,24 @@ cc_status cc_check_run_params(int scheme, const cc_run_params *pp) {
 static cc_status run_batch(cc_ctx *c, Batch &b, const cc_run_params &p, bool host_stats) {
   if (p.mode == CC_MODE_SERVE && b.n_txns && !b.d_arrival)
     return fail(c, CC_E_STATE, "CC_MODE_SERVE needs cc_set_arrivals first");
+  // contention of the batch: the share of transactions that write its most
+  // written row (unknown: treated as contended)
+  const double hot_share = b.hot_known && b.n_txns ? (double)b.hot_writes / (double)b.n_txns : 1.0;
+  const bool no_hot_row = hot_share < 0.001, contended = hot_share >= 0.02;
   uint32_t lanes = p.lanes_per_txn;
+  uint32_t wpw = p.waves_per_wg;
   if (lanes == 0) {
-    lanes = 1;
-    while (lanes < 64 && lanes < b.max_ops) lanes *= 4;
+    if (no_hot_row && b.max_ops <= 64 && b.scheme != CC_GACCO && b.scheme != CC_GPUTX) {
+      // nothing to wait for: 4 lanes per transaction, 4 wavefronts per
+      // workgroup (4096 transactions in flight at one workgroup per CU)
+      lanes = 4;
+      if (wpw == 0) wpw = 4;
+    } else {
+      lanes = 1;
+      while (lanes < 64 && lanes < b.max_ops) lanes *= 4;
+    }
   }
-  const uint32_t wpw = p.waves_per_wg ? p.waves_per_wg : 1;
+  if (wpw == 0) wpw = 1;
   if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
   if (b.scheme == CC_GACCO) return run_gacco(c, b, p, lanes, wpw);
   if (b.scheme == CC_GPUTX) return run_gputx(c, b, p, lanes, wpw);
@@ -1122,7 +1191,13 @@ static cc_status run_batch(cc_ctx *c, Batch &b, const cc_run_params &p, bool hos
   a.ns_per_tick_q16 = (uint32_t)((1000000ull << 16) / c->wallclock_khz);
   a.has_slot = b.has_slot ? 1u : 0u;
   a.eager_install = (p.flags & CC_RUN_EAGER_INSTALL) ? 1u : 0u;
-  a.precheck = (p.flags & CC_RUN_PRECHECK) ? 2u : ((p.flags & CC_RUN_NO_PRECHECK) ? 0u : 1u);
+  a.precheck = (p.flags & CC_RUN_PRECHECK) ? 2u : ((p.flags & CC_RUN_NO_PRECHECK) ? 0u : (contended ? 1u : 0u));
+  a.hot0 = b.n_hot ? b.hot_rows[0] : ~0u;
+  a.n_late = 0;
+  if (b.scheme == CC_OCC && (p.flags & CC_RUN_HOT_LAST) && b.hot_known) {
+    a.n_late = b.n_hot;
+    for (uint32_t i = 0; i < b.n_hot; ++i) a.late[i] = b.hot_rows[i];
+  }
   a.wd_wait_limit = 64;
   if (p.flags & CC_RUN_LATCH) {
     if (!c->d_latch) {
@@ -1303,6 +1378,10 @@ static cc_status run_batch(cc_ctx *c, Batch &b, const cc_run_params &p, bool hos
   b.stats[CC_STAT_GAVE_UP] = h.stats[DS_GAVE_UP];
   b.stats[CC_STAT_ADMIT_WAITS] = h.stats[DS_ADMIT_WAITS];
   b.stats[CC_STAT_WD_WAITS] = h.stats[DS_WD_WAITS];
+  b.stats[CC_STAT_HOT_ACQ] = h.stats[DS_HOT_ACQ];
+  b.stats[CC_STAT_HOT_FAILED] = h.stats[DS_HOT_FAILED];
+  b.stats[CC_STAT_HOT_HOLD_NS] = (uint64_t)((double)h.stats[DS_HOT_HOLD] * ns_per_tick);
+  b.stats[CC_STAT_HOT_WRITES] = b.hot_writes;
   for (int i = 0; i < 4; ++i)
     b.stats[CC_STAT_OCC_R1_NS + i] = (uint64_t)((double)h.stats[DS_R1 + i] * ns_per_tick);
   b.stats[CC_STAT_INDEX_NS] = (uint64_t)((double)ms_index * 1e6);

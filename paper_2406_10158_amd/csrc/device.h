@@ -178,6 +178,8 @@ struct Slots {
   bool sh[K];     // 2PL wait-die: this slot holds a shared lock (kept while the team waits)
   uint32_t block; // a row another transaction held when this attempt failed to lock (~0u: none)
   uint64_t tr[4]; // wall clock at the end of each round (OCC; for the per-round time breakdown)
+  uint64_t hot_dt; // OCC: ticks this lane held the batch's most written row in the attempt
+  bool hot_got;    // OCC: this lane took that row's lock in the attempt
 };
 
 // The first row (in lane order) that a lane of my team found held by another

@@ -64,6 +64,9 @@ enum DevStat {
   DS_INDEX_MISS = 16,   // keyed operations whose key no row holds
   DS_WD_WAITS = 17,     // 2PL wait-die: times a team kept its locks and waited
   DS_LATCH_STUCK = 18,  // CC_RUN_LATCH: latches not obtained within the spin limit (run invalid)
+  DS_HOT_ACQ = 19,      // OCC: acquisitions of the batch's most written row's lock
+  DS_HOT_FAILED = 20,   //   of which the attempt then aborted
+  DS_HOT_HOLD = 21,     //   ticks the row was held, summed over acquisitions
   DS_N = 24
 };
 
@@ -80,6 +83,9 @@ struct Ctl {
 };
 
 // Kernel arguments for a transaction run.
+// Rows a batch's submission singles out as hot (most writes first).
+constexpr int HOT_MAX = 8;
+
 struct RunArgs {
   const DevOp *ops;
   const DevTxn *txns;
@@ -109,6 +115,13 @@ struct RunArgs {
   uint32_t wd_wait_limit;  // 2PL wait-die: waits of one attempt before it dies anyway
   uint32_t pad5;
   uint32_t *latch;         // CC_RUN_LATCH: one 32-bit latch per global row (else unused)
+  // OCC: the batch's hottest written rows (most writes first), locked -- or,
+  // for a read-only access, looked at -- in a round of their own once every
+  // other row of the transaction is held (0 rows: one lock round)
+  uint32_t n_late;
+  uint32_t late[HOT_MAX];
+  uint32_t hot0;           // the batch's most written row (~0u: none), for the hold statistics
+  uint32_t pad6;
 };
 
 // A table's index on the device (index.hip): the table's keys sorted, with

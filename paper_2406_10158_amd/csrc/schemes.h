@@ -142,20 +142,56 @@ __device__ __forceinline__ uint64_t w_apply(const RunArgs &a, uint64_t *w, uint3
 // ===========================================================================
 constexpr uint64_t OCC_LOCK = 1ull << 63;
 
+// True if `row` is one of the batch's hot rows (RunArgs::late).
+__device__ __forceinline__ bool is_late(const RunArgs &a, uint32_t row) {
+  bool r = false;
+#pragma unroll
+  for (int i = 0; i < HOT_MAX; ++i) r |= (uint32_t)i < a.n_late && a.late[i] == row;
+  return r;
+}
+
+// True if this lane holds the lock of the batch's most written row.
+template <int K>
+__device__ __forceinline__ bool holds_hot0(const Slots<K> &s, const RunArgs &a) {
+  bool h = false;
+#pragma unroll
+  for (int k = 0; k < K; ++k) h |= s.got[k] && op_row(s.rowk[k]) == a.hot0;
+  return h;
+}
+
 template <int L, int K, bool STRICT, bool LATCH>
 __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool active, const RunArgs &a,
                                            bool precheck, uint64_t *hi, uint64_t *lo) {
   bool fail = false;
   uint32_t blk = ~0u;
   bool pre_fail = false;
+  s.hot_dt = 0;
+  s.hot_got = false;
+  // Hot rows last (RunArgs::late): when any team of the wavefront touches one
+  // of the batch's hot rows, the lock round is split.  R1 takes every other
+  // row; R1b, once those are all held, takes the hot rows.  A hot row is then
+  // held only from R1b to R4, and never by an attempt that fails on another
+  // row's lock.
+  // Not with one lane per transaction, nor in the 16-slot variants: the one
+  // run of the split rounds with one lane and 16 slots faulted the GPU, with
+  // no out-of-bounds access found in the source, so those variants keep one
+  // lock round.
+  constexpr bool SPLIT_OK = K < 16 && L > 1;
+  bool late[K];
+  bool has_late = false;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    late[k] = SPLIT_OK && active && s.valid[k] && a.n_late && is_late(a, op_row(s.rowk[k]));
+    has_late |= late[k];
+  }
+  const bool split = SPLIT_OK && ballot(has_late) != 0;  // wavefront-uniform
   if (ballot(active && precheck)) {
-    // R0, by default from a transaction's second attempt on: load every
-    // row's word and give up before taking any lock if one is held, so that
-    // failing attempts never hold rows (or write their lines) while they
-    // fail elsewhere.  Read-only rows keep the word loaded here, exactly as
-    // R1 would load it.  First attempts skip it: until a transaction has
-    // failed there is no sign of contention, and at low contention the extra
-    // round (which its whole wavefront waits for) costs more than it saves.
+    // R0, on retries of a contended batch (cc.h, CC_RUN_PRECHECK): load
+    // every row's word and give up before taking any lock if one is held, so
+    // that failing attempts never hold rows (or write their lines) while
+    // they fail elsewhere.  Read-only rows keep the word loaded here, exactly
+    // as R1 would load it.  First attempts skip it: until a transaction has
+    // failed there is no sign of contention.
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (active && precheck && s.valid[k] && op_leader(s.rowk[k])) {
@@ -169,17 +205,27 @@ __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool a
     pre_fail = t.any(fail);
   }
   const bool go = active && !pre_fail;
+  // R1: locks of written rows, words of read-only rows (hot rows excluded
+  // when split).  A split round after R0 also loads these rows' values: a
+  // read-only row's value comes after the word R0 saw, which R3 validates; a
+  // written row's value is issued beside its lock, and is the row's value
+  // under the lock if the lock returns exactly the word R0 saw, unlocked --
+  // every commit changes the word to a new ticket for good, and a writer
+  // whose install the load could have seen held the lock from before the
+  // load until after its new ticket was stored.  A lock that returns another
+  // word fails the attempt.
+  const bool early_vals = split && precheck;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     s.got[k] = false;
-    if (go && s.valid[k] && op_leader(s.rowk[k]) && (!precheck || op_written(s.rowk[k]))) {
+    if (go && s.valid[k] && op_leader(s.rowk[k]) && !late[k] && (!precheck || op_written(s.rowk[k]))) {
       uint64_t *w = a.words + op_row(s.rowk[k]);
       if (op_written(s.rowk[k])) {
         const uint64_t old = w_or<LATCH, STRICT>(a, w, OCC_LOCK);
-        s.v[k] = old;
         s.got[k] = !(old & OCC_LOCK);
         if (!s.got[k] && blk == ~0u) blk = op_row(s.rowk[k]);
-        fail |= !s.got[k];
+        fail |= !s.got[k] || (early_vals && old != s.v[k]);
+        s.v[k] = old;
       } else {
         const uint64_t o = ld_word(w);
         s.v[k] = o;
@@ -187,21 +233,62 @@ __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool a
         fail |= (o & OCC_LOCK) != 0;
       }
     }
+    if (early_vals && go && s.valid[k] && !late[k]) s.x[k] = ld_val(a.data + s.elem[k]);
   }
   order_point<STRICT>();
   s.tr[0] = wall_clock64();
-  s.block = blocking_row(t, blk);
-  const bool lock_fail = t.any(fail);
-  const bool alive = active && !lock_fail;
+  uint64_t hot_t0 = holds_hot0(s, a) ? s.tr[0] : 0;
+  bool lock_fail = t.any(fail);
   if (active && lock_fail) {
 #pragma unroll
     for (int k = 0; k < K; ++k)
       if (s.got[k]) w_st<LATCH, STRICT>(a, a.words + op_row(s.rowk[k]), s.v[k]);
   }
-  // R2: values under the locks / after the observed words, and the ticket
+  if (split) {
+    // R1b: the hot rows, once every other row is held; without R0 also the
+    // other rows' values (under their locks, after their words)
+    const bool go2 = active && !lock_fail;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (go2 && op_leader(s.rowk[k]) && late[k]) {
+        uint64_t *w = a.words + op_row(s.rowk[k]);
+        if (op_written(s.rowk[k])) {
+          const uint64_t old = w_or<LATCH, STRICT>(a, w, OCC_LOCK);
+          s.v[k] = old;
+          s.got[k] = !(old & OCC_LOCK);
+          if (!s.got[k] && blk == ~0u) blk = op_row(s.rowk[k]);
+          fail |= !s.got[k];
+        } else {
+          const uint64_t o = ld_word(w);
+          s.v[k] = o;
+          if ((o & OCC_LOCK) && blk == ~0u) blk = op_row(s.rowk[k]);
+          fail |= (o & OCC_LOCK) != 0;
+        }
+      }
+      if (go2 && !precheck && s.valid[k] && !late[k]) s.x[k] = ld_val(a.data + s.elem[k]);
+    }
+    order_point<STRICT>();
+    s.tr[0] = wall_clock64();
+    if (!hot_t0 && holds_hot0(s, a)) hot_t0 = s.tr[0];
+    const bool fail_b = t.any(fail);
+    if (active && fail_b && !lock_fail) {
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (s.got[k]) w_st<LATCH, STRICT>(a, a.words + op_row(s.rowk[k]), s.v[k]);
+    }
+    lock_fail = fail_b;
+  }
+  s.block = blocking_row(t, blk);
+  const bool alive = active && !lock_fail;
+  if (hot_t0 && !alive) {
+    s.hot_got = true;
+    s.hot_dt = wall_clock64() - hot_t0;
+  }
+  // R2: values under the locks / after the observed words (only the hot
+  // rows' when split), and the ticket
 #pragma unroll
   for (int k = 0; k < K; ++k)
-    if (alive && s.valid[k]) s.x[k] = ld_val(a.data + s.elem[k]);
+    if (alive && s.valid[k] && (!split || late[k])) s.x[k] = ld_val(a.data + s.elem[k]);
   const uint64_t ticket = t.claim(&a.ctl->ticket, alive, 1) + 1;
   order_point<STRICT>();
   s.tr[1] = wall_clock64();
@@ -238,6 +325,10 @@ __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool a
   for (int k = 0; k < K; ++k)
     if (alive && s.got[k]) w_st<LATCH, STRICT>(a, a.words + op_row(s.rowk[k]), (commit || eager) ? ticket : s.v[k]);
   s.tr[3] = wall_clock64();
+  if (hot_t0 && alive) {
+    s.hot_got = true;
+    s.hot_dt = s.tr[3] - hot_t0;
+  }
   *hi = 0;
   *lo = ticket;
   if (!active) return COMMIT;

@@ -46,6 +46,7 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
   bool resume = false;      // 2PL wait-die: the team waits holding locks; its next attempt continues this one
   uint32_t waits = 0;       // 2PL wait-die: waits of the current attempt
   uint64_t n_waits = 0;
+  uint64_t n_hot_acq = 0, n_hot_fail = 0, t_hot = 0;  // OCC: the most written row, in the lane holding it
 
   for (;;) {
     if constexpr (LATCH) {
@@ -148,6 +149,13 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
         }
       }
     }
+    if constexpr (SCHEME == CC_OCC) {
+      if (active && s.hot_got) {
+        ++n_hot_acq;
+        n_hot_fail += r != COMMIT;
+        t_hot += s.hot_dt;
+      }
+    }
     if (active && r == WAITING) {
       // wait-die: keep the locks and try the missing ones again shortly (a
       // wait is not an attempt; an attempt's waits are bounded)
@@ -212,6 +220,7 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
                  c4 = wave_sum(n_gave), c5 = wave_max(max_att), c6 = wave_sum(n_defer), c7 = wave_sum(n_ovf);
   const uint64_t c8 = wave_sum(t_useful), c9 = wave_sum(t_abort), c10 = wave_sum(t_wait),
                  c11 = wave_sum(n_admit_wait), c13 = wave_sum(n_waits);
+  const uint64_t c14 = wave_sum(n_hot_acq), c15 = wave_sum(n_hot_fail), c16 = wave_sum(t_hot);
   uint64_t cr[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) cr[i] = wave_sum(t_round[i]);
@@ -229,6 +238,9 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
     if (c10) atomicAdd((unsigned long long *)&a.ctl->stats[DS_T_WAIT], (unsigned long long)c10);
     if (c11) atomicAdd((unsigned long long *)&a.ctl->stats[DS_ADMIT_WAITS], (unsigned long long)c11);
     if (c13) atomicAdd((unsigned long long *)&a.ctl->stats[DS_WD_WAITS], (unsigned long long)c13);
+    if (c14) atomicAdd((unsigned long long *)&a.ctl->stats[DS_HOT_ACQ], (unsigned long long)c14);
+    if (c15) atomicAdd((unsigned long long *)&a.ctl->stats[DS_HOT_FAILED], (unsigned long long)c15);
+    if (c16) atomicAdd((unsigned long long *)&a.ctl->stats[DS_HOT_HOLD], (unsigned long long)c16);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
       if (cr[i]) atomicAdd((unsigned long long *)&a.ctl->stats[DS_R1 + i], (unsigned long long)cr[i]);
