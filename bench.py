@@ -54,7 +54,12 @@ def algorithmic_bytes(batch) -> int:
 
 
 def access_counts(batch) -> dict:
-    """Memory operations one committed pass of the OCC hot path must issue, from the batch itself."""
+    """Memory operations one committed pass of the OCC hot path must issue, from the batch itself.
+
+    Control words (8 B per row, 80 MB for 10M rows) and values (the 800 MB
+    value arena) are separate arrays, so their random accesses are counted
+    apart: they are priced at the rates of their own footprints.
+    """
     kind = batch.kind
     n_ops = batch.total_ops
     first = np.zeros(n_ops, bool)
@@ -68,16 +73,26 @@ def access_counts(batch) -> dict:
     n_groups, n_wgroups = len(written), int(written.sum())
     n_writes = int((kind != 0).sum())
     return {
-        # value reads + word reads of read-only rows + validation re-reads
-        "random_loads": n_ops + 2 * (n_groups - n_wgroups),
-        "random_atomics": n_wgroups,                 # write-row try-locks
-        "random_stores": n_writes + n_wgroups,       # new values + publishing words
+        "value_loads": n_ops,                          # every op reads its value
+        "word_loads": 2 * (n_groups - n_wgroups),      # read-only rows: word + validation re-read
+        "word_atomics": n_wgroups,                     # write-row try-locks
+        "value_stores": n_writes,                      # new values
+        "word_stores": n_wgroups,                      # publishing words
         "stream_bytes": n_ops * (16 + 8) + batch.n_txns * (8 + 32),
     }
 
 
-def run_probes(ctx, binding, quick=False) -> dict:
-    """Self-measured rates of the memory operations the hot path is made of."""
+def run_probes(ctx, binding, batch=None, quick=False) -> dict:
+    """Self-measured rates of the memory operations the hot path is made of.
+
+    Random 8-byte coherent loads at three footprints: 80 MB (the 10M-row
+    control-word array, which fits the 256 MB Infinity Cache), 880 MB (words
+    plus the 800 MB value arena) and 1.4 GB; stores at 80 and 880 MB; 64-bit
+    fetch_or at 80 MB with uniform addresses and, given a batch, at the
+    batch's own written rows (its Zipf distribution, in batch order); the
+    single-word hand-off and the OCC commit hand-off with the second side on
+    the same CU, on another CU of the same XCD, and on another XCD.
+    """
     n_cu, _ = binding.cc_device_info(ctx)
     threads = n_cu * 8 * 256
 
@@ -86,24 +101,32 @@ def run_probes(ctx, binding, quick=False) -> dict:
         return threads * per
 
     out = {}
-    fp = 1 << 30
     n = 1 << (26 if quick else 28)
-    words = 1
-    while words * 16 <= (2 << 30):
-        words *= 2
     ms = binding.cc_probe(ctx, "stream", 2 << 30, 0)
-    out["stream_GBps"] = words * 8 / ms / 1e6
-    for name in ("gather", "scatter", "atomic"):
-        ms = binding.cc_probe(ctx, name, fp, n)
-        out[f"{name}_Gops"] = ops_of(n) / ms / 1e6
+    out["stream_GBps"] = ((2 << 30) // 32 * 32) / ms / 1e6  # half the buffer read, half written
+    for mb in (80, 880, 1400):
+        out[f"gather_{mb}MB_Gops"] = ops_of(n) / binding.cc_probe(ctx, "gather", mb * 1_000_000, n) / 1e6
+    for mb in (80, 880):
+        out[f"scatter_{mb}MB_Gops"] = ops_of(n) / binding.cc_probe(ctx, "scatter", mb * 1_000_000, n) / 1e6
+    out["atomic_80MB_Gops"] = ops_of(n) / binding.cc_probe(ctx, "atomic", 80_000_000, n) / 1e6
+    if batch is not None:
+        rows = batch.row[batch.kind != 0].astype(np.uint64)
+        if len(rows):
+            ms = binding.cc_probe_indices(ctx, "atomic", max(80_000_000, (int(rows.max()) + 4) * 8), rows)
+            out["atomic_batch_rows_Gops"] = len(rows) / ms / 1e6
     rounds = 4000 if quick else 20000
-    ms = binding.cc_probe(ctx, "handoff", 1 << 20, rounds, 1)
-    out["handoff_ns"] = ms * 1e6 / (2 * rounds)
-    ms = binding.cc_probe(ctx, "commit_handoff", 1 << 20, rounds, 1)
-    out["commit_handoff_ns"] = ms * 1e6 / rounds
+    for name, peer in (("same_cu", 0), ("same_xcd", 8), ("cross_xcd", 1)):
+        ms = binding.cc_probe(ctx, "handoff", 1 << 20, rounds, peer)
+        out[f"handoff_{name}_ns"] = ms * 1e6 / (2 * rounds)
+        ms = binding.cc_probe(ctx, "commit_handoff", 1 << 20, rounds, peer)
+        out[f"commit_handoff_{name}_ns"] = ms * 1e6 / rounds
+    # the hot row is touched from every XCD: the bounds take the cross-XCD hand-offs
+    out["handoff_ns"] = out["handoff_cross_xcd_ns"]
+    out["commit_handoff_ns"] = out["commit_handoff_cross_xcd_ns"]
     ms = binding.cc_probe(ctx, "wave_counter", 1 << 20, 1 << 26)
     out["one_word_atomic_ns"] = ms * 1e6 / (threads // 64 * (((1 << 26) + threads - 1) // threads + 3) // 4 * 4)
     return {k: round(v, 3) for k, v in out.items()}
+
 
 
 def _cpu_model() -> str:
@@ -418,7 +441,9 @@ def main():
 
     if args.probes:
         ctx = binding.cc_init(0)
-        print(json.dumps({"probes": run_probes(ctx, binding)}))
+        _, b = workload.kv_workload(n_rows=args.rows, n_fields=args.fields, n_txns=args.txns, ops=args.ops,
+                                    theta=args.theta, seed=args.seed)
+        print(json.dumps({"probes": run_probes(ctx, binding, batch=b)}))
         binding.cc_destroy(ctx)
         return
     if args.suite:
@@ -503,10 +528,15 @@ def main():
                 "avg_launch_ms": round(k_step_s * 1e3 / launches, 4)}
 
     # measured random-access / atomic roofline and hot-row contention bound
-    probes = run_probes(eng.ctx, binding, quick=True)
+    probes = run_probes(eng.ctx, binding, batch=batch, quick=True)
     acc = access_counts(batch)
-    t_roof = (acc["random_loads"] / (probes["gather_Gops"] * 1e9) + acc["random_atomics"] / (probes["atomic_Gops"] * 1e9)
-              + acc["random_stores"] / (probes["scatter_Gops"] * 1e9) + acc["stream_bytes"] / (probes["stream_GBps"] * 1e9))
+    # control words at the 80 MB rates, values at the 880 MB rates
+    t_roof = (acc["word_loads"] / (probes["gather_80MB_Gops"] * 1e9)
+              + acc["value_loads"] / (probes["gather_880MB_Gops"] * 1e9)
+              + acc["word_atomics"] / (probes["atomic_80MB_Gops"] * 1e9)
+              + acc["value_stores"] / (probes["scatter_880MB_Gops"] * 1e9)
+              + acc["word_stores"] / (probes["scatter_80MB_Gops"] * 1e9)
+              + acc["stream_bytes"] / (probes["stream_GBps"] * 1e9))
     x_roof = batch.n_txns / t_roof
     if args.scheme == "gacco":
         # every access of the hottest row (reads too) is one turn of its word;

@@ -526,8 +526,11 @@ cc_status cc_run_static(cc_ctx *ctx, const cc_txn *txns, uint64_t n_txns, const 
  *                          value store, publish), alternating between two
  *                          workgroups `peer` apart: ms / n_ops is the hot-row
  *                          hand-off time t_h
- * Random addresses are uniform over the largest power-of-two number of words
- * that fits footprint_bytes.  *ms receives the kernel time (HIP events).
+ * Random addresses are uniform over the footprint_bytes / 8 words of the
+ * probe's buffer (rounded down to a multiple of 4).  For the hand-off probes,
+ * peer places the second side: 0 in the same workgroup (same CU), 8 in
+ * another workgroup of the same XCD, 1 on another XCD (workgroups are dealt
+ * round-robin to the 8 XCDs).  *ms receives the kernel time (HIP events).
  * Allocates and frees its own buffers.  CC_E_LIVELOCK if a hand-off turn
  * exceeded its bounded wait.
  */
@@ -543,6 +546,17 @@ enum cc_probe_kind {
   CC_PROBE_COMMIT_HANDOFF = 8
 };
 cc_status cc_probe(cc_ctx *ctx, int kind, uint64_t footprint_bytes, uint64_t n_ops, int peer, double *ms);
+
+/*
+ * The gather, plain-gather, scatter or atomic probe at the caller's word
+ * indices: op i touches word indices[i] of a footprint_bytes buffer, so a
+ * skewed distribution (the workload's Zipf rows) can be measured.  indices is
+ * a host array of n entries, each below footprint_bytes / 8 rounded down to a
+ * multiple of 4 (else CC_E_RANGE); it is copied to the device before the
+ * timed kernel, which also streams it.  *ms receives the kernel time.
+ */
+cc_status cc_probe_indices(cc_ctx *ctx, int kind, uint64_t footprint_bytes, const uint64_t *indices, uint64_t n,
+                           double *ms);
 
 /* Device properties the engine uses: compute units, wall-clock rate (kHz). */
 cc_status cc_device_info(cc_ctx *ctx, uint32_t *n_cu, uint32_t *wallclock_khz);

@@ -95,6 +95,7 @@ _SIGS = {
     "cc_run_static": (_S, [_P, _P, ctypes.c_uint64, _P, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(cc_run_params),
                            _P, _P, _P, ctypes.c_uint32]),
     "cc_device_info": (_S, [_P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]),
+    "cc_probe_indices": (_S, [_P, ctypes.c_int, ctypes.c_uint64, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]),
     "cc_probe": (_S, [_P, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
                       ctypes.POINTER(ctypes.c_double)]),
 }
@@ -168,6 +169,16 @@ def cc_probe(ctx, kind, footprint_bytes: int, n_ops: int, peer: int = 1) -> floa
         kind = PROBES[kind]
     ms = ctypes.c_double()
     _check(lib.cc_probe(ctx, kind, footprint_bytes, n_ops, peer, ctypes.byref(ms)), ctx)
+    return float(ms.value)
+
+
+def cc_probe_indices(ctx, kind, footprint_bytes: int, indices: np.ndarray) -> float:
+    """Run the gather / scatter / atomic probe at the given word indices; returns its kernel time in ms."""
+    if isinstance(kind, str):
+        kind = PROBES[kind]
+    idx = _host(indices, np.uint64)
+    ms = ctypes.c_double()
+    _check(lib.cc_probe_indices(ctx, kind, footprint_bytes, _ptr(idx), len(idx), ctypes.byref(ms)), ctx)
     return float(ms.value)
 
 

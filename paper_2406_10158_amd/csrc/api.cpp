@@ -344,13 +344,29 @@ cc_status cc_probe(cc_ctx *c, int kind, uint64_t footprint_bytes, uint64_t n_ops
   if (!c || !ms) return CC_E_INVAL;
   if (kind < CC_PROBE_STREAM || kind > CC_PROBE_COMMIT_HANDOFF) return fail(c, CC_E_INVAL, "unknown probe");
   const bool pair = kind == CC_PROBE_HANDOFF || kind == CC_PROBE_COMMIT_HANDOFF;
-  if (footprint_bytes < 4096 || (pair && (peer < 1 || peer > 64)))
+  if (footprint_bytes < 4096 || (pair && (peer < 0 || peer > 64)))
     return fail(c, CC_E_INVAL, "bad probe size or peer");
   if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
   uint64_t err = 0;
-  hipError_t e = run_probe(c->stream, kind, footprint_bytes, n_ops, peer, ms, &err, c->n_cu);
+  hipError_t e = run_probe(c->stream, kind, footprint_bytes, n_ops, peer, nullptr, ms, &err, c->n_cu);
   if (e != hipSuccess) return hip_fail(c, e, "probe");
   if (err) return fail(c, CC_E_LIVELOCK, "hand-off turn exceeded its bounded wait");
+  return CC_OK;
+}
+
+cc_status cc_probe_indices(cc_ctx *c, int kind, uint64_t footprint_bytes, const uint64_t *indices, uint64_t n,
+                           double *ms) {
+  if (!c || !ms || (n && !indices)) return CC_E_INVAL;
+  if (kind != CC_PROBE_GATHER && kind != CC_PROBE_GATHER_PLAIN && kind != CC_PROBE_SCATTER && kind != CC_PROBE_ATOMIC)
+    return fail(c, CC_E_INVAL, "cc_probe_indices runs the gather, scatter and atomic probes");
+  if (footprint_bytes < 4096) return fail(c, CC_E_INVAL, "bad probe size");
+  const uint64_t words = footprint_bytes / sizeof(uint64_t) / 4 * 4;
+  for (uint64_t i = 0; i < n; ++i)
+    if (indices[i] >= words) return fail(c, CC_E_RANGE, "index beyond the probe's footprint");
+  if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
+  uint64_t err = 0;
+  hipError_t e = run_probe(c->stream, kind, footprint_bytes, n, 1, indices, ms, &err, c->n_cu);
+  if (e != hipSuccess) return hip_fail(c, e, "probe");
   return CC_OK;
 }
 

@@ -316,7 +316,7 @@ hipError_t static_scratch_address(int device, void **ptr);
 hipError_t launch_fill_zero(hipStream_t s, int64_t *p, uint64_t n);
 
 // Memory micro-benchmarks (roofline.hip); see cc_probe in cc.h.
-hipError_t run_probe(hipStream_t s, int kind, uint64_t footprint_bytes, uint64_t n_ops, int peer, double *ms_out,
-                     uint64_t *err_out, int n_cu);
+hipError_t run_probe(hipStream_t s, int kind, uint64_t footprint_bytes, uint64_t n_ops, int peer,
+                     const uint64_t *host_idx, double *ms_out, uint64_t *err_out, int n_cu);
 
 }  // namespace cce

@@ -3,6 +3,8 @@
 // roofline is set by how many of those the memory system sustains, not by
 // streaming bandwidth or arithmetic.  Each probe times one kernel with HIP
 // events; addresses come from a hash of the op index (no index traffic).
+#include <algorithm>
+
 #include "engine.h"
 
 namespace cce {
@@ -20,33 +22,44 @@ __global__ void __launch_bounds__(256) probe_stream(const uint4 *src, uint4 *dst
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
-// Random 8-byte accesses over a power-of-two number of words.
+// Random 8-byte accesses over `words` words (any count: the word index is the
+// high half of hash x words, uniform over [0, words)), or, with `idx`, at the
+// caller's word indices idx[i] for op i (threads take ops i, i + threads, ...).
 // mode 0: agent-scope loads   1: plain loads   2: agent-scope stores
 //      3: agent-scope fetch_or   4: agent-scope fetch_add on one word (every lane)
 //      5: agent-scope fetch_add on one word, one per wavefront
 template <int MODE>
-__global__ void __launch_bounds__(256) probe_random(uint64_t *words, uint64_t mask, uint64_t per_thread,
-                                                   uint64_t *sink) {
+__global__ void __launch_bounds__(256) probe_random(uint64_t *words, uint64_t n_words, uint64_t per_thread,
+                                                   const uint64_t *idx, uint64_t n_idx, uint64_t *sink) {
   const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t threads = (uint64_t)gridDim.x * blockDim.x;
   uint64_t acc = 0;
   for (uint64_t j = 0; j < per_thread; j += 4) {
     uint64_t v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const uint64_t idx = hash64((tid << 24) ^ (j + u)) & mask;
+      uint64_t w;
+      bool on = true;
+      if (idx) {
+        const uint64_t i = (j + u) * threads + tid;
+        on = i < n_idx;
+        w = on ? idx[i] : 0;
+      } else {
+        w = __umul64hi(hash64((tid << 24) ^ (j + u)), n_words);
+      }
+      v[u] = 0;
+      if (!on) continue;
       if constexpr (MODE == 0) {
-        v[u] = __hip_atomic_load(words + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v[u] = __hip_atomic_load(words + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else if constexpr (MODE == 1) {
-        v[u] = words[idx];
+        v[u] = words[w];
       } else if constexpr (MODE == 2) {
-        __hip_atomic_store(words + idx, j + u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        v[u] = 0;
+        __hip_atomic_store(words + w, j + u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else if constexpr (MODE == 3) {
-        v[u] = __hip_atomic_fetch_or(words + idx, 1ull << (u + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v[u] = __hip_atomic_fetch_or(words + w, 1ull << (u + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else if constexpr (MODE == 4) {
         v[u] = __hip_atomic_fetch_add(words, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
-        v[u] = 0;
         if (__lane_id() == 0) v[u] = __hip_atomic_fetch_add(words, 64ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
@@ -55,16 +68,27 @@ __global__ void __launch_bounds__(256) probe_random(uint64_t *words, uint64_t ma
   if (acc == 0x5A5A5A5A5A5A5A5Aull) sink[tid & 1023] = acc;  // keeps the loads live
 }
 
-// Ping-pong on one word between lane 0 of block 0 and lane 0 of block `peer`
-// (blocks are dealt round-robin to the 8 XCDs, so peer 1 is another XCD and
-// peer 8 the same XCD).  Each side waits for its turn with agent-scope loads,
-// bounded by `spin_limit` polls per turn; on exhaustion it records an error.
-__global__ void __launch_bounds__(64) probe_handoff(uint64_t *flag, uint64_t rounds, int peer, uint64_t spin_limit,
-                                                    uint64_t *err) {
-  if (threadIdx.x != 0) return;
-  int side = -1;
-  if (blockIdx.x == 0) side = 0;
-  if ((int)blockIdx.x == peer) side = 1;
+// The two sides of a hand-off probe: lane 0 of block 0 and lane 0 of block
+// `peer`.  Blocks are dealt round-robin to the 8 XCDs, so peer 1 is on another
+// XCD and peer 8 on the same XCD (another CU); peer 0 puts the two sides in
+// the first two wavefronts of block 0, which share one CU.  -1: not a side.
+__device__ __forceinline__ int handoff_side(int peer) {
+  if (threadIdx.x % 64 != 0) return -1;
+  const int wave = (int)threadIdx.x / 64;
+  if (peer == 0) return blockIdx.x == 0 && wave < 2 ? wave : -1;
+  if (wave != 0) return -1;
+  if (blockIdx.x == 0) return 0;
+  if ((int)blockIdx.x == peer) return 1;
+  return -1;
+}
+
+// Ping-pong on one word between the two sides (handoff_side).  Each side
+// waits for its turn with agent-scope loads, bounded by `spin_limit` polls per
+// turn; on exhaustion it records an error and stops, and so does the other
+// side once its own bounded wait runs out.
+__global__ void __launch_bounds__(128) probe_handoff(uint64_t *flag, uint64_t rounds, int peer, uint64_t spin_limit,
+                                                     uint64_t *err) {
+  const int side = handoff_side(peer);
   if (side < 0) return;
   for (uint64_t r = 0; r < rounds; ++r) {
     const uint64_t want = 2 * r + (uint64_t)side;
@@ -80,19 +104,16 @@ __global__ void __launch_bounds__(64) probe_handoff(uint64_t *flag, uint64_t rou
 }
 
 // The OCC commit critical section on one hot row, handed back and forth
-// between lane 0 of block 0 and lane 0 of block `peer`: wait until the row's
+// between the two sides (handoff_side): wait until the row's
 // word carries the previous round's version (bounded), then lock it with
 // fetch_or, read the row's value and draw a ticket, re-read a second word
 // (the validation read), store the new value, wait for completion and
 // publish the word.  The time per round is the shortest interval between two
 // commits on one row that this lock / ticket / validate / install sequence
 // allows: the hot-row hand-off time t_h.
-__global__ void __launch_bounds__(64) probe_commit_handoff(uint64_t *buf, uint64_t rounds, int peer,
-                                                           uint64_t spin_limit, uint64_t *err) {
-  if (threadIdx.x != 0) return;
-  int side = -1;
-  if (blockIdx.x == 0) side = 0;
-  if ((int)blockIdx.x == peer) side = 1;
+__global__ void __launch_bounds__(128) probe_commit_handoff(uint64_t *buf, uint64_t rounds, int peer,
+                                                            uint64_t spin_limit, uint64_t *err) {
+  const int side = handoff_side(peer);
   if (side < 0) return;
   uint64_t *word = buf, *value = buf + 64, *ticket = buf + 128, *other = buf + 192 + 16 * side;
   const uint64_t LOCKBIT = 1ull << 63;
@@ -124,17 +145,21 @@ __global__ void fill_kernel(uint64_t *p, uint64_t n, uint64_t v) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
-hipError_t run_probe(hipStream_t s, int kind, uint64_t footprint_bytes, uint64_t n_ops, int peer, double *ms_out,
-                     uint64_t *err_out, int n_cu) {
+hipError_t run_probe(hipStream_t s, int kind, uint64_t footprint_bytes, uint64_t n_ops, int peer,
+                     const uint64_t *host_idx, double *ms_out, uint64_t *err_out, int n_cu) {
   *err_out = 0;
-  uint64_t words = 1;
-  while (words * 2 * sizeof(uint64_t) <= footprint_bytes) words *= 2;
-  uint64_t *buf = nullptr, *aux = nullptr;
+  const uint64_t words = footprint_bytes / sizeof(uint64_t) / 4 * 4;  // the stream copy moves 4-word chunks
+  uint64_t *buf = nullptr, *aux = nullptr, *idx = nullptr;
   hipError_t e = hipMalloc(&buf, words * sizeof(uint64_t));
   if (e != hipSuccess) return e;
   e = hipMalloc(&aux, 8192 * sizeof(uint64_t));
+  if (e == hipSuccess && host_idx) e = hipMalloc(&idx, std::max<uint64_t>(n_ops, 1) * sizeof(uint64_t));
+  if (e == hipSuccess && host_idx && n_ops)
+    e = hipMemcpyAsync(idx, host_idx, n_ops * sizeof(uint64_t), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) {
     (void)hipFree(buf);
+    if (aux) (void)hipFree(aux);
+    if (idx) (void)hipFree(idx);
     return e;
   }
   hipEvent_t a, b;
@@ -147,24 +172,25 @@ hipError_t run_probe(hipStream_t s, int kind, uint64_t footprint_bytes, uint64_t
   uint64_t per = (n_ops + threads - 1) / threads;
   per = (per + 3) & ~3ull;
   if (per == 0) per = 4;
+  const uint64_t n_idx = host_idx ? n_ops : 0;
   (void)hipEventRecord(a, s);
   switch (kind) {
     case 0:
       hipLaunchKernelGGL(probe_stream, dim3(grid * 4), dim3(256), 0, s, (const uint4 *)buf,
                          (uint4 *)(buf + words / 2), (uint64_t)(words / 4));
       break;
-    case 1: hipLaunchKernelGGL(probe_random<0>, dim3(grid), dim3(block), 0, s, buf, words - 1, per, aux); break;
-    case 2: hipLaunchKernelGGL(probe_random<1>, dim3(grid), dim3(block), 0, s, buf, words - 1, per, aux); break;
-    case 3: hipLaunchKernelGGL(probe_random<2>, dim3(grid), dim3(block), 0, s, buf, words - 1, per, aux); break;
-    case 4: hipLaunchKernelGGL(probe_random<3>, dim3(grid), dim3(block), 0, s, buf, words - 1, per, aux); break;
-    case 5: hipLaunchKernelGGL(probe_random<4>, dim3(grid), dim3(block), 0, s, buf, words - 1, per, aux); break;
-    case 6: hipLaunchKernelGGL(probe_random<5>, dim3(grid), dim3(block), 0, s, buf, words - 1, per, aux); break;
+    case 1: hipLaunchKernelGGL(probe_random<0>, dim3(grid), dim3(block), 0, s, buf, words, per, idx, n_idx, aux); break;
+    case 2: hipLaunchKernelGGL(probe_random<1>, dim3(grid), dim3(block), 0, s, buf, words, per, idx, n_idx, aux); break;
+    case 3: hipLaunchKernelGGL(probe_random<2>, dim3(grid), dim3(block), 0, s, buf, words, per, idx, n_idx, aux); break;
+    case 4: hipLaunchKernelGGL(probe_random<3>, dim3(grid), dim3(block), 0, s, buf, words, per, idx, n_idx, aux); break;
+    case 5: hipLaunchKernelGGL(probe_random<4>, dim3(grid), dim3(block), 0, s, buf, words, per, idx, n_idx, aux); break;
+    case 6: hipLaunchKernelGGL(probe_random<5>, dim3(grid), dim3(block), 0, s, buf, words, per, idx, n_idx, aux); break;
     case 7:
-      hipLaunchKernelGGL(probe_handoff, dim3((unsigned)(peer + 1)), dim3(64), 0, s, buf, n_ops, peer,
+      hipLaunchKernelGGL(probe_handoff, dim3((unsigned)(peer + 1)), dim3(128), 0, s, buf, n_ops, peer,
                          (uint64_t)1 << 20, aux + 4096);
       break;
     case 8:
-      hipLaunchKernelGGL(probe_commit_handoff, dim3((unsigned)(peer + 1)), dim3(64), 0, s, buf, n_ops, peer,
+      hipLaunchKernelGGL(probe_commit_handoff, dim3((unsigned)(peer + 1)), dim3(128), 0, s, buf, n_ops, peer,
                          (uint64_t)1 << 20, aux + 4096);
       break;
     default:
@@ -181,6 +207,7 @@ hipError_t run_probe(hipStream_t s, int kind, uint64_t footprint_bytes, uint64_t
   (void)hipEventDestroy(b);
   (void)hipFree(buf);
   (void)hipFree(aux);
+  if (idx) (void)hipFree(idx);
   return e;
 }
 

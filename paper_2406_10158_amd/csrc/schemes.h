@@ -214,28 +214,37 @@ __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool a
   // whose install the load could have seen held the lock from before the
   // load until after its new ticket was stored.  A lock that returns another
   // word fails the attempt.
+  // The round issues every lock and load first and looks at the results
+  // only after the ordering point: a wavefront whose lanes both lock and load
+  // then waits for one round trip, not for the locks' and the loads' in turn.
   const bool early_vals = split && precheck;
+  bool issued[K];
+  uint64_t seen[K];  // the word R0 saw (early_vals)
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     s.got[k] = false;
-    if (go && s.valid[k] && op_leader(s.rowk[k]) && !late[k] && (!precheck || op_written(s.rowk[k]))) {
+    seen[k] = s.v[k];
+    issued[k] = go && s.valid[k] && op_leader(s.rowk[k]) && !late[k] && (!precheck || op_written(s.rowk[k]));
+    if (issued[k]) {
       uint64_t *w = a.words + op_row(s.rowk[k]);
-      if (op_written(s.rowk[k])) {
-        const uint64_t old = w_or<LATCH, STRICT>(a, w, OCC_LOCK);
-        s.got[k] = !(old & OCC_LOCK);
-        if (!s.got[k] && blk == ~0u) blk = op_row(s.rowk[k]);
-        fail |= !s.got[k] || (early_vals && old != s.v[k]);
-        s.v[k] = old;
-      } else {
-        const uint64_t o = ld_word(w);
-        s.v[k] = o;
-        if ((o & OCC_LOCK) && blk == ~0u) blk = op_row(s.rowk[k]);
-        fail |= (o & OCC_LOCK) != 0;
-      }
+      if (op_written(s.rowk[k])) s.v[k] = w_or<LATCH, STRICT>(a, w, OCC_LOCK);
+      else s.v[k] = ld_word(w);
     }
     if (early_vals && go && s.valid[k] && !late[k]) s.x[k] = ld_val(a.data + s.elem[k]);
   }
   order_point<STRICT>();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (!issued[k]) continue;
+    const uint64_t o = s.v[k];
+    if ((o & OCC_LOCK) && blk == ~0u) blk = op_row(s.rowk[k]);
+    if (op_written(s.rowk[k])) {
+      s.got[k] = !(o & OCC_LOCK);
+      fail |= !s.got[k] || (early_vals && o != seen[k]);
+    } else {
+      fail |= (o & OCC_LOCK) != 0;
+    }
+  }
   s.tr[0] = wall_clock64();
   uint64_t hot_t0 = holds_hot0(s, a) ? s.tr[0] : 0;
   bool lock_fail = t.any(fail);
@@ -250,24 +259,23 @@ __device__ __forceinline__ int occ_attempt(const Team<L> &t, Slots<K> &s, bool a
     const bool go2 = active && !lock_fail;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      if (go2 && op_leader(s.rowk[k]) && late[k]) {
+      issued[k] = go2 && op_leader(s.rowk[k]) && late[k];
+      if (issued[k]) {
         uint64_t *w = a.words + op_row(s.rowk[k]);
-        if (op_written(s.rowk[k])) {
-          const uint64_t old = w_or<LATCH, STRICT>(a, w, OCC_LOCK);
-          s.v[k] = old;
-          s.got[k] = !(old & OCC_LOCK);
-          if (!s.got[k] && blk == ~0u) blk = op_row(s.rowk[k]);
-          fail |= !s.got[k];
-        } else {
-          const uint64_t o = ld_word(w);
-          s.v[k] = o;
-          if ((o & OCC_LOCK) && blk == ~0u) blk = op_row(s.rowk[k]);
-          fail |= (o & OCC_LOCK) != 0;
-        }
+        if (op_written(s.rowk[k])) s.v[k] = w_or<LATCH, STRICT>(a, w, OCC_LOCK);
+        else s.v[k] = ld_word(w);
       }
       if (go2 && !precheck && s.valid[k] && !late[k]) s.x[k] = ld_val(a.data + s.elem[k]);
     }
     order_point<STRICT>();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (!issued[k]) continue;
+      const uint64_t o = s.v[k];
+      if ((o & OCC_LOCK) && blk == ~0u) blk = op_row(s.rowk[k]);
+      if (op_written(s.rowk[k])) s.got[k] = !(o & OCC_LOCK);
+      fail |= (o & OCC_LOCK) != 0;
+    }
     s.tr[0] = wall_clock64();
     if (!hot_t0 && holds_hot0(s, a)) hot_t0 = s.tr[0];
     const bool fail_b = t.any(fail);
@@ -735,26 +743,27 @@ __device__ __forceinline__ int tictoc_attempt(const Team<L> &t, Slots<K> &s, boo
     pre_fail = t.any(fail);
   }
   const bool go = active && !pre_fail;
+  // locks and loads all issued before any result is looked at (see OCC's R1)
+  bool issued[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     s.got[k] = false;
-    if (go && s.valid[k] && op_leader(s.rowk[k]) && (!precheck || op_written(s.rowk[k]))) {
+    issued[k] = go && s.valid[k] && op_leader(s.rowk[k]) && (!precheck || op_written(s.rowk[k]));
+    if (issued[k]) {
       uint64_t *w = a.words + op_row(s.rowk[k]);
-      if (op_written(s.rowk[k])) {
-        const uint64_t old = w_or<LATCH, STRICT>(a, w, TT_LOCK);
-        s.v[k] = old;
-        s.got[k] = !(old & TT_LOCK);
-        if (!s.got[k] && blk == ~0u) blk = op_row(s.rowk[k]);
-        fail |= !s.got[k];
-      } else {
-        const uint64_t o = ld_word(w);
-        s.v[k] = o;
-        if ((o & TT_LOCK) && blk == ~0u) blk = op_row(s.rowk[k]);
-        fail |= (o & TT_LOCK) != 0;
-      }
+      if (op_written(s.rowk[k])) s.v[k] = w_or<LATCH, STRICT>(a, w, TT_LOCK);
+      else s.v[k] = ld_word(w);
     }
   }
   order_point<STRICT>();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (!issued[k]) continue;
+    const uint64_t o = s.v[k];
+    if ((o & TT_LOCK) && blk == ~0u) blk = op_row(s.rowk[k]);
+    if (op_written(s.rowk[k])) s.got[k] = !(o & TT_LOCK);
+    fail |= (o & TT_LOCK) != 0;
+  }
   s.block = blocking_row(t, blk);
   const bool lock_fail = t.any(fail);
   const bool alive = active && !lock_fail;

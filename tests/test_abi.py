@@ -200,6 +200,7 @@ def test_every_entry_point_rejects_a_null_context(b):
         "cc_run_static": lambda: lib.cc_run_static(None, None, 0, None, 0, 0, None, None, None, None, 0),
         "cc_device_info": lambda: lib.cc_device_info(None, None, None),
         "cc_probe": lambda: lib.cc_probe(None, 0, 1 << 20, 1, 1, None),
+        "cc_probe_indices": lambda: lib.cc_probe_indices(None, 1, 1 << 20, None, 0, None),
         "cc_init": lambda: lib.cc_init(None, None),
     }
     for name, call in calls.items():
