@@ -217,6 +217,14 @@ enum cc_mode { CC_MODE_PLAIN = 0, CC_MODE_EPOCH = 1, CC_MODE_SERVE = 2 };
                                      transaction or 16 ops per lane. */
 #define CC_RUN_NO_HOT_LAST 0x200u /* OCC: one lock round for every row, the default (CC_E_INVAL with
                                      CC_RUN_HOT_LAST) */
+#define CC_RUN_WAIT_BLOCKER 0x400u /* OCC and TicToc (CC_E_INVAL for another scheme): after an attempt that
+                                     failed on a row another transaction held, wait until that row is free
+                                     -- its word looked at every ~2 back-off bases, at most 256 bases --
+                                     then retry after a random jitter below 2 bases, instead of backing off.
+                                     Only in passes that defer (CC_MODE_PLAIN's passes before the last,
+                                     CC_MODE_SERVE); the final pass, which never defers, keeps the
+                                     randomised back-off, so two transactions that block each other cannot
+                                     retry in lockstep forever there */
 #define CC_RUN_EAGER_INSTALL 0x2u /* OCC only (CC_E_INVAL for another scheme): store new values in the
                                      validation round (undo on abort) instead of after validation
                                      succeeds; measured ~3% slower on the key-value workload, kept for
@@ -289,7 +297,8 @@ enum cc_stat {
   CC_STAT_HOT_HOLD_NS = 30,/* OCC: time that row's lock was held, summed over acquisitions (the rest of
                               CC_STAT_KERNEL_NS it was free) */
   CC_STAT_HOT_WRITES = 31, /* writes to the batch's most written row (counted at submission) */
-  CC_N_STATS = 32
+  CC_STAT_BLOCKED_WAITS = 32, /* CC_RUN_WAIT_BLOCKER: waits for a held row that failed attempts entered */
+  CC_N_STATS = 40
 };
 
 /* Library version and self-description (no device work). */

@@ -748,7 +748,7 @@ cc_status check_run_params(cc_ctx *c, int scheme, const cc_run_params &p) {
   if (p.waves_per_wg > 16) return fail(c, CC_E_INVAL, "waves_per_wg must be 1..16");
   if (p.flags & ~(CC_RUN_STRICT_FENCES | CC_RUN_EAGER_INSTALL | CC_RUN_WAIT_UNLOCK | CC_RUN_PRECHECK |
                   CC_RUN_NO_PRECHECK | CC_RUN_INDEX_TREE | CC_RUN_LATCH | CC_RUN_SHARED_READS | CC_RUN_HOT_LAST |
-                  CC_RUN_NO_HOT_LAST))
+                  CC_RUN_NO_HOT_LAST | CC_RUN_WAIT_BLOCKER))
     return fail(c, CC_E_INVAL, "unknown run flag");
   if ((p.flags & CC_RUN_SHARED_READS) && scheme != CC_GACCO)
     return fail(c, CC_E_INVAL, "CC_RUN_SHARED_READS is a CC_GACCO option");
@@ -785,6 +785,8 @@ cc_status check_run_params(cc_ctx *c, int scheme, const cc_run_params &p) {
   const uint32_t hot = CC_RUN_HOT_LAST | CC_RUN_NO_HOT_LAST;
   if ((p.flags & hot) == hot) return fail(c, CC_E_INVAL, "CC_RUN_HOT_LAST and CC_RUN_NO_HOT_LAST exclude each other");
   if ((p.flags & hot) && scheme != CC_OCC) return fail(c, CC_E_INVAL, "CC_RUN_HOT_LAST is a CC_OCC option");
+  if ((p.flags & CC_RUN_WAIT_BLOCKER) && scheme != CC_OCC && scheme != CC_TICTOC)
+    return fail(c, CC_E_INVAL, "CC_RUN_WAIT_BLOCKER is a CC_OCC and CC_TICTOC option");
   return CC_OK;
 }
 
@@ -1209,6 +1211,10 @@ static cc_status run_batch(cc_ctx *c, Batch &b, const cc_run_params &p, bool hos
   a.eager_install = (p.flags & CC_RUN_EAGER_INSTALL) ? 1u : 0u;
   a.precheck = (p.flags & CC_RUN_PRECHECK) ? 2u : ((p.flags & CC_RUN_NO_PRECHECK) ? 0u : (contended ? 1u : 0u));
   a.hot0 = b.n_hot ? b.hot_rows[0] : ~0u;
+  a.wait_blocker = (p.flags & CC_RUN_WAIT_BLOCKER) ? 1u : 0u;
+  a.poll_ticks = 2 * a.backoff_ticks;
+  a.jitter_ticks = 2 * a.backoff_ticks;
+  a.wait_max_ticks = 256ull * a.backoff_ticks;
   a.n_late = 0;
   if (b.scheme == CC_OCC && (p.flags & CC_RUN_HOT_LAST) && b.hot_known) {
     a.n_late = b.n_hot;
@@ -1398,6 +1404,7 @@ static cc_status run_batch(cc_ctx *c, Batch &b, const cc_run_params &p, bool hos
   b.stats[CC_STAT_HOT_FAILED] = h.stats[DS_HOT_FAILED];
   b.stats[CC_STAT_HOT_HOLD_NS] = (uint64_t)((double)h.stats[DS_HOT_HOLD] * ns_per_tick);
   b.stats[CC_STAT_HOT_WRITES] = b.hot_writes;
+  b.stats[CC_STAT_BLOCKED_WAITS] = h.stats[DS_BLOCKED_WAITS];
   for (int i = 0; i < 4; ++i)
     b.stats[CC_STAT_OCC_R1_NS + i] = (uint64_t)((double)h.stats[DS_R1 + i] * ns_per_tick);
   b.stats[CC_STAT_INDEX_NS] = (uint64_t)((double)ms_index * 1e6);

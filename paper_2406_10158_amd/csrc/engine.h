@@ -67,6 +67,7 @@ enum DevStat {
   DS_HOT_ACQ = 19,      // OCC: acquisitions of the batch's most written row's lock
   DS_HOT_FAILED = 20,   //   of which the attempt then aborted
   DS_HOT_HOLD = 21,     //   ticks the row was held, summed over acquisitions
+  DS_BLOCKED_WAITS = 22,// CC_RUN_WAIT_BLOCKER: waits for a held row entered
   DS_N = 24
 };
 
@@ -121,7 +122,15 @@ struct RunArgs {
   uint32_t n_late;
   uint32_t late[HOT_MAX];
   uint32_t hot0;           // the batch's most written row (~0u: none), for the hold statistics
-  uint32_t pad6;
+  // OCC, TicToc (CC_RUN_WAIT_BLOCKER): in passes that defer, a team that failed
+  // on a held row looks at that row's word every ~poll_ticks until it is free
+  // or wait_max_ticks have passed, then retries after a random jitter below
+  // jitter_ticks, instead of backing off
+  uint32_t wait_blocker;
+  uint32_t poll_ticks;
+  uint32_t jitter_ticks;
+  uint32_t pad7;
+  uint64_t wait_max_ticks;
 };
 
 // A table's index on the device (index.hip): the table's keys sorted, with

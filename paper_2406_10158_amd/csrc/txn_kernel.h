@@ -47,6 +47,9 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
   uint32_t waits = 0;       // 2PL wait-die: waits of the current attempt
   uint64_t n_waits = 0;
   uint64_t n_hot_acq = 0, n_hot_fail = 0, t_hot = 0;  // OCC: the most written row, in the lane holding it
+  uint32_t wait_row = ~0u;  // CC_RUN_WAIT_BLOCKER: the held row the team waits for (~0u: not waiting)
+  uint64_t wait_since = 0, next_poll = 0;
+  uint64_t n_blocked = 0;   // waits entered
 
   for (;;) {
     if constexpr (LATCH) {
@@ -67,6 +70,7 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
         admitted = false;
         resume = false;
         waits = 0;
+        wait_row = ~0u;
       } else {
         done = true;
       }
@@ -96,6 +100,26 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
       res_pos = (uint64_t)__shfl((long long)pos, t.tb, 64);
       admitted = __shfl((int)ok, t.tb, 64) != 0;
       if (!admitted) ready_at = now + 1 + (mix64(((uint64_t)txn << 20) ^ now) % (4ull * a.backoff_ticks));
+    }
+    if (a.wait_blocker) {
+      // a waiting team looks at its row's word, at randomised intervals, until
+      // the row is free or the wait times out; then it retries after a jitter.
+      // Every wait ends: the time-out bounds it, and the final pass, which
+      // never defers, never waits (the team loop's CPU model checks this rule).
+      const bool poll = txn >= 0 && wait_row != ~0u && now >= next_poll;  // team-uniform
+      bool free_now = false;
+      if (poll && t.tl == 0)
+        free_now = !(ld_word(a.words + wait_row) & (1ull << 63)) || now - wait_since > a.wait_max_ticks;
+      free_now = __shfl((int)free_now, t.tb, 64) != 0;
+      if (poll) {
+        const uint64_t r = mix64(((uint64_t)txn << 24) ^ now);
+        if (free_now) {
+          wait_row = ~0u;
+          ready_at = now + r % ((uint64_t)a.jitter_ticks + 1);
+        } else {
+          next_poll = now + a.poll_ticks / 2 + r % ((uint64_t)a.poll_ticks + 1);
+        }
+      }
     }
     const bool active = txn >= 0 && now >= ready_at;
     if (ballot(active) == 0) {
@@ -205,6 +229,13 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
           }
           reserved = 0;
           txn = -1;
+        } else if (a.wait_blocker && a.defer_after && s.block != ~0u) {
+          // wait for the row another transaction held (passes that defer only)
+          wait_row = s.block;
+          wait_since = now;
+          next_poll = now + a.poll_ticks;
+          ready_at = ~0ull;
+          if (t.tl == 0) ++n_blocked;
         } else {
           // randomised exponential back-off
           const uint32_t sh = pass_att < 12 ? pass_att : 12;
@@ -220,7 +251,8 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
                  c4 = wave_sum(n_gave), c5 = wave_max(max_att), c6 = wave_sum(n_defer), c7 = wave_sum(n_ovf);
   const uint64_t c8 = wave_sum(t_useful), c9 = wave_sum(t_abort), c10 = wave_sum(t_wait),
                  c11 = wave_sum(n_admit_wait), c13 = wave_sum(n_waits);
-  const uint64_t c14 = wave_sum(n_hot_acq), c15 = wave_sum(n_hot_fail), c16 = wave_sum(t_hot);
+  const uint64_t c14 = wave_sum(n_hot_acq), c15 = wave_sum(n_hot_fail), c16 = wave_sum(t_hot),
+                 c17 = wave_sum(n_blocked);
   uint64_t cr[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) cr[i] = wave_sum(t_round[i]);
@@ -241,6 +273,7 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) txn_kernel(RunArgs a) {
     if (c14) atomicAdd((unsigned long long *)&a.ctl->stats[DS_HOT_ACQ], (unsigned long long)c14);
     if (c15) atomicAdd((unsigned long long *)&a.ctl->stats[DS_HOT_FAILED], (unsigned long long)c15);
     if (c16) atomicAdd((unsigned long long *)&a.ctl->stats[DS_HOT_HOLD], (unsigned long long)c16);
+    if (c17) atomicAdd((unsigned long long *)&a.ctl->stats[DS_BLOCKED_WAITS], (unsigned long long)c17);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
       if (cr[i]) atomicAdd((unsigned long long *)&a.ctl->stats[DS_R1 + i], (unsigned long long)cr[i]);

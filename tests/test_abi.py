@@ -212,6 +212,14 @@ def test_every_entry_point_rejects_a_null_context(b):
 def test_run_parameter_checks_without_a_device(b):
     ok = b.cc_check_run_params
     P = b.run_params
+    # waiting for a blocking row, and hot rows last, exist for the schemes that implement them
+    assert ok(b.CC_OCC, P(flags=b.CC_RUN_WAIT_BLOCKER)) == b.CC_OK
+    assert ok(b.CC_TICTOC, P(flags=b.CC_RUN_WAIT_BLOCKER)) == b.CC_OK
+    for sch in (b.CC_2PL_NW, b.CC_2PL_WD, b.CC_TO, b.CC_MVCC, b.CC_GACCO, b.CC_GPUTX):
+        assert ok(sch, P(flags=b.CC_RUN_WAIT_BLOCKER)) == b.CC_E_INVAL
+    assert ok(b.CC_OCC, P(flags=b.CC_RUN_HOT_LAST)) == b.CC_OK
+    assert ok(b.CC_OCC, P(flags=b.CC_RUN_HOT_LAST | b.CC_RUN_NO_HOT_LAST)) == b.CC_E_INVAL
+    assert ok(b.CC_TICTOC, P(flags=b.CC_RUN_HOT_LAST)) == b.CC_E_INVAL
     assert ok(b.CC_OCC) == b.CC_OK and ok(b.CC_OCC, P(flags=b.CC_RUN_PRECHECK | b.CC_RUN_STRICT_FENCES)) == b.CC_OK
     assert ok(b.CC_OCC, P(mode=7)) == b.CC_E_INVAL
     assert ok(b.CC_OCC, P(lanes_per_txn=8)) == b.CC_E_INVAL

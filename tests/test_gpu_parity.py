@@ -198,6 +198,37 @@ def test_wait_unlock_flag_is_rejected():
         assert np.array_equal(eng.tables()[0], tabs[0])
 
 
+@pytest.mark.parametrize("shape", [(16, 1), (64, 1), (4, 2), (1, 1), (1, 4)])
+@pytest.mark.parametrize("scheme", ["occ", "tictoc"])
+def test_wait_for_blocking_row(scheme, shape):
+    # CC_RUN_WAIT_BLOCKER: a failed attempt waits (bounded) for the row another transaction held,
+    # in passes that defer; the final pass backs off (the team-loop CPU model's rule)
+    b_ = binding()
+    lanes, waves = shape
+    print(f"[gpu] wait-for-blocker {scheme} L={lanes} waves={waves}", flush=True)
+    tabs, b = wl.kv_workload(n_rows=20_000, n_fields=4, n_txns=20_000, ops=(1, 16) if lanes == 1 else 16,
+                             theta=0.99, seed=47)
+    _, _, _, st = run_and_check(tabs, b, scheme, flags=b_.CC_RUN_WAIT_BLOCKER, lanes_per_txn=lanes,
+                                waves_per_wg=waves)
+    assert st["blocked_waits"] > 0
+    # every transaction adds to both of two rows: the pairs that block each other
+    b2 = wl.kv_batch(2, 1, 5_000, ops=2, read_ratio=0.3, arg_range=(-5, 5), seed=48)
+    run_and_check([wl.kv_table(2, 1)], b2, scheme, flags=b_.CC_RUN_WAIT_BLOCKER, lanes_per_txn=max(lanes, 4),
+                  waves_per_wg=waves)
+    if lanes >= 16:
+        tabs, b = wl.order_entry_workload(1, 1_000, seed=49)
+        run_and_check(tabs, b, scheme, flags=b_.CC_RUN_WAIT_BLOCKER, lanes_per_txn=64, waves_per_wg=waves)
+
+
+@pytest.mark.parametrize("pre", [0, 1, 2])
+def test_wait_for_blocking_row_with_each_precheck_setting(pre):
+    b_ = binding()
+    f = b_.CC_RUN_WAIT_BLOCKER | [b_.CC_RUN_NO_PRECHECK, 0, b_.CC_RUN_PRECHECK][pre]
+    tabs, b = wl.kv_workload(n_rows=50_000, n_fields=4, n_txns=30_000, ops=16, theta=0.9, seed=50 + pre)
+    run_and_check(tabs, b, "occ", flags=f)
+    run_and_check(tabs, b, "occ", flags=f | b_.CC_RUN_STRICT_FENCES)
+
+
 @pytest.mark.parametrize("flags", ["precheck", "precheck+eager", "no-precheck", "precheck+latch"])
 @pytest.mark.parametrize("theta", [0.6, 0.99])
 @pytest.mark.parametrize("scheme", ["occ", "to", "mvcc", "tictoc"])
