@@ -376,30 +376,60 @@ def suite_batching(args, binding, workload):
 
 
 def suite_serving(args, binding, workload):
-    """Poisson streams of key-value (8-32 ops, Zipf 0.9) + order-entry (W=8) at increasing offered load."""
-    # one stream of transactions; each offered load rescales its arrival times
-    tables, batch, arr1, m = workload.serve_stream(args.serve_arrivals, 1e6, kv_rows=args.rows,
-                                                   kv_fields=args.fields, seed=args.seed)
+    """Poisson streams of key-value (8-32 ops, Zipf 0.9) + order-entry (W=8) at increasing offered load.
+
+    One stream of --serve-arrivals transactions is generated once (in parallel
+    processes for long streams) and its arrival times are rescaled for each
+    offered load, so the 1M txn/s point spans arrivals / 1M seconds.  OCC runs
+    every load under the --serve-cap admission budget; MVCC then runs the 2M
+    txn/s point with the version arena sized by a 64 MB cap and without a cap,
+    to show that the cap bounds the arena whatever the stream's length.
+    """
+    t0 = time.time()
+    workers = min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count() or 1)
+    tables, batch, arr1, m = workload.serve_stream(
+        args.serve_arrivals, 1e6, kv_rows=args.rows, kv_fields=args.fields, seed=args.seed, workers=workers,
+        log=lambda msg: print(f"[serving] {msg} ({time.time() - t0:.0f}s)", file=sys.stderr, flush=True))
+    print(f"[serving] {batch.n_txns} arrivals, {batch.total_ops} ops generated in {time.time() - t0:.0f}s "
+          f"({workers} processes)", file=sys.stderr, flush=True)
     eng = binding.Engine(tables)
-    bid = eng.submit(batch, "occ")
-    for rate in (1e6, 2e6, 5e6, 10e6, 20e6, 50e6):
+
+    def point(scheme, rate, cap, bid):
         arr = (arr1 * (1e6 / rate)).astype(np.int64)
         binding.cc_set_arrivals(eng.ctx, bid, arr)
-        rec = {"suite": "serving", "offered_txn_per_s": rate, "arrivals": batch.n_txns,
-               "hbm_cap_bytes": args.serve_cap}
+        rec = {"suite": "serving", "scheme": scheme, "offered_txn_per_s": rate, "arrivals": batch.n_txns,
+               "stream_span_s": round(float(arr[-1]) / 1e9, 3), "hbm_cap_bytes": cap}
         try:
             eng.load(tables)
-            st = eng.run(bid, mode=binding.CC_MODE_SERVE, hbm_cap_bytes=args.serve_cap)
+            st = eng.run(bid, mode=binding.CC_MODE_SERVE, hbm_cap_bytes=cap)
             out, _ = eng.outcomes(bid, batch.n_txns, 0)
             span_ns = float(out["commit_ns"].max())
-            rec.update(committed=st["committed"], committed_txn_per_s=round(st["committed"] / (span_ns * 1e-9), 1),
+            committed_rate = st["committed"] / (span_ns * 1e-9)
+            rec.update(committed=st["committed"], committed_txn_per_s=round(committed_rate, 1),
                        p50_latency_ms=round(st["lat_p50_ns"] / 1e6, 4), p99_latency_ms=round(st["lat_p99_ns"] / 1e6, 4),
                        abort_rate=round((st["attempts"] - st["committed"]) / max(st["committed"], 1), 3),
                        admit_waits=st["admit_waits"], passes=st["passes"],
-                       stream_span_ms=round(float(arr[-1]) / 1e6, 3))
+                       # below saturation the engine keeps up with the offered load, the queue stays
+                       # short and the latencies are the steady state's; above it they grow with the
+                       # backlog, i.e. with the stream's length
+                       steady_state=bool(committed_rate >= 0.99 * rate))
+            if scheme == "mvcc":
+                rec.update(version_slots=st["version_slots"], version_arena_bytes=st["version_slots"] * 32,
+                           version_misses=st["version_misses"], writes=int((batch.kind != 0).sum()))
         except binding.CCError as e:
             rec["error"] = str(e)
         _emit(rec)
+        print(f"[serving] {scheme} {rate:.0e}: {rec.get('committed_txn_per_s')} txn/s, "
+              f"p99 {rec.get('p99_latency_ms')} ms", file=sys.stderr, flush=True)
+
+    bid = eng.submit(batch, "occ")
+    for rate in (1e6, 2e6, 5e6, 10e6, 20e6, 50e6):
+        point("occ", rate, args.serve_cap, bid)
+    eng.release(bid)
+    bid = eng.submit(batch, "mvcc")
+    for cap in (64 << 20, 0):
+        point("mvcc", 2e6, cap, bid)
+    eng.release(bid)
     eng.close()
 
 

@@ -174,7 +174,12 @@ typedef struct {
  *                  fits in the hbm_cap_bytes budget of uncommitted work; it
  *                  releases the bytes when it commits; aborts retry after
  *                  back-off while later arrivals proceed.  Latency statistics
- *                  are commit time minus arrival time.
+ *                  are commit time minus arrival time.  Under CC_MVCC the
+ *                  cap also sizes the version arena (hbm_cap_bytes / 32
+ *                  slots, reused as a ring; CC_STAT_VERSION_SLOTS), so the
+ *                  device memory that old versions take is bounded by the cap
+ *                  however long the stream; a reader whose version's slot was
+ *                  reused aborts and retries with a newer timestamp.
  */
 enum cc_mode { CC_MODE_PLAIN = 0, CC_MODE_EPOCH = 1, CC_MODE_SERVE = 2 };
 #define CC_SERVE_BYTES_PER_OP 32 /* read value + new value + undo / version record, 8 B each + 8 B index */
@@ -252,7 +257,8 @@ typedef struct {
                              0 = 1 */
   uint64_t ts_start;      /* first value of the run's ticket / timestamp counter (0 for normal runs; a
                              large value forces the 31-bit TO/MVCC timestamp-overflow path) */
-  uint64_t hbm_cap_bytes; /* CC_MODE_SERVE: admission budget for uncommitted work; 0 = no cap */
+  uint64_t hbm_cap_bytes; /* CC_MODE_SERVE: admission budget for uncommitted work and, under CC_MVCC, the
+                             version arena's size; 0 = no cap (one version slot per op of the stream) */
   uint64_t wait_limit_us; /* CC_GACCO, CC_GPUTX: a team that sees no progress on its waits for this long
                              stops every team and the run fails with CC_E_LIVELOCK; 0 = 4 s.  It cannot
                              trigger while the lock table is consistent (the smallest unfinished
@@ -298,6 +304,10 @@ enum cc_stat {
                               CC_STAT_KERNEL_NS it was free) */
   CC_STAT_HOT_WRITES = 31, /* writes to the batch's most written row (counted at submission) */
   CC_STAT_BLOCKED_WAITS = 32, /* CC_RUN_WAIT_BLOCKER: waits for a held row that failed attempts entered */
+  CC_STAT_VERSION_SLOTS = 33, /* CC_MVCC: slots of the version arena (32 bytes each): one per op of the
+                                 batch, or hbm_cap_bytes / 32 in CC_MODE_SERVE with a cap; at least 1024 */
+  CC_STAT_VERSION_MISSES = 34,/* CC_MVCC: old-version reads whose version's slot the ring had reused
+                                 (the attempt aborted and retried with a newer timestamp) */
   CC_N_STATS = 40
 };
 

@@ -32,7 +32,8 @@ struct Batch {
   DevOutcome *d_out = nullptr;
   int64_t *d_reads = nullptr;
   uint32_t *d_list = nullptr;  // pending transactions between passes
-  uint64_t *d_nodes = nullptr; // MVCC history nodes (3 words per op)
+  uint64_t *d_nodes = nullptr; // MVCC version arena: a 32-byte header (the ring counter), then node_slots x 4 words
+  uint64_t node_slots = 0;
   bool keyed = false;            // some ops name their row by key (cc_submit_batch_keyed)
   int64_t *d_opkeys = nullptr;   // keyed batches: per-op key
   uint32_t *d_meta = nullptr;    // keyed batches: per-op keyed flag, table, field
@@ -191,6 +192,7 @@ void free_batch(Batch &b) {
   b.epoch_graph = nullptr;
   b.d_list = nullptr;
   b.d_nodes = nullptr;
+  b.node_slots = 0;
   b.d_ops = nullptr;
   b.d_txns = nullptr;
   b.d_out = nullptr;
@@ -824,7 +826,6 @@ static hipError_t alloc_batch(Batch &b, int scheme, bool keyed) {
       (e = alloc((void **)&b.d_out, n_txns * sizeof(DevOutcome))) != hipSuccess ||
       (e = alloc((void **)&b.d_reads, n_ops * sizeof(int64_t))) != hipSuccess ||
       (e = alloc((void **)&b.d_list, n_txns * sizeof(uint32_t))) != hipSuccess ||
-      (scheme == CC_MVCC && (e = alloc((void **)&b.d_nodes, n_ops * 3 * sizeof(uint64_t))) != hipSuccess) ||
       (ordered_scheme && (e = alloc((void **)&b.d_rank, n_ops * sizeof(uint32_t))) != hipSuccess) ||
       (ordered_scheme &&
        (e = alloc((void **)&b.d_gscratch, gacco_scratch_words(n_ops) * sizeof(uint32_t))) != hipSuccess) ||
@@ -1198,8 +1199,32 @@ static cc_status run_batch(cc_ctx *c, Batch &b, const cc_run_params &p, bool hos
     HIP_OR(c, hipMalloc(&c->d_aux, std::max<uint64_t>(c->total_rows, 1) * sizeof(uint64_t)));
   }
   a.aux = c->d_aux;
-  a.nodes = b.d_nodes;
-  a.n_nodes = b.scheme == CC_MVCC ? b.n_ops : 0;
+  if (b.scheme == CC_MVCC) {
+    // the version arena: one slot per op of the batch, or, when serving with
+    // a cap, hbm_cap_bytes / 32 slots, reused as a ring; at least 1024 slots,
+    // more than one transaction's writes (256), so that no commit's slots wrap
+    // onto each other
+    const uint64_t slots = (p.mode == CC_MODE_SERVE && p.hbm_cap_bytes)
+                               ? std::max<uint64_t>(p.hbm_cap_bytes / 32, 1024)
+                               : std::max<uint64_t>(b.n_ops, 1024);
+    if (!b.d_nodes || b.node_slots != slots) {
+      if (b.d_nodes) (void)hipFree(b.d_nodes);
+      b.d_nodes = nullptr;
+      b.node_slots = 0;
+      if (b.epoch_graph) {
+        // a captured epoch holds the old arena's address
+        (void)hipGraphExecDestroy(b.epoch_graph);
+        b.epoch_graph = nullptr;
+      }
+      const uint64_t bytes = 32 + slots * 4 * sizeof(uint64_t);
+      HIP_OR(c, hipMalloc(&b.d_nodes, bytes));
+      HIP_OR(c, hipMemsetAsync(b.d_nodes, 0, bytes, c->stream));  // tags 0 (lap 0), ring counter 0
+      b.node_slots = slots;
+    }
+  }
+  a.nodes = b.d_nodes ? b.d_nodes + 4 : nullptr;
+  a.node_ring = b.d_nodes;
+  a.n_nodes = b.node_slots;
   a.out = b.d_out;
   a.reads = b.d_reads;
   a.ctl = c->d_ctl;
@@ -1405,6 +1430,8 @@ static cc_status run_batch(cc_ctx *c, Batch &b, const cc_run_params &p, bool hos
   b.stats[CC_STAT_HOT_HOLD_NS] = (uint64_t)((double)h.stats[DS_HOT_HOLD] * ns_per_tick);
   b.stats[CC_STAT_HOT_WRITES] = b.hot_writes;
   b.stats[CC_STAT_BLOCKED_WAITS] = h.stats[DS_BLOCKED_WAITS];
+  b.stats[CC_STAT_VERSION_SLOTS] = b.node_slots;
+  b.stats[CC_STAT_VERSION_MISSES] = h.stats[DS_VERSION_MISS];
   for (int i = 0; i < 4; ++i)
     b.stats[CC_STAT_OCC_R1_NS + i] = (uint64_t)((double)h.stats[DS_R1 + i] * ns_per_tick);
   b.stats[CC_STAT_INDEX_NS] = (uint64_t)((double)ms_index * 1e6);

@@ -87,6 +87,20 @@ __device__ __forceinline__ uint64_t wave_max(uint64_t v) {
   return v;
 }
 
+// Exclusive prefix sum of v over the wavefront's lanes (lane order); *total
+// receives the sum over all lanes.  All lanes must call it.
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t *total) {
+  const int lane = __lane_id();
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)x, o, 64);
+    if (lane >= o) x += y;
+  }
+  *total = (uint32_t)__shfl((int)x, 63, 64);
+  return x - v;
+}
+
 // A team: the L consecutive lanes (L a power of two) that execute one
 // transaction together.
 template <int L>

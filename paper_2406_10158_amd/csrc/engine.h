@@ -68,6 +68,7 @@ enum DevStat {
   DS_HOT_FAILED = 20,   //   of which the attempt then aborted
   DS_HOT_HOLD = 21,     //   ticks the row was held, summed over acquisitions
   DS_BLOCKED_WAITS = 22,// CC_RUN_WAIT_BLOCKER: waits for a held row entered
+  DS_VERSION_MISS = 23, // MVCC: old-version reads that found their version's slot reused (attempt aborted)
   DS_N = 24
 };
 
@@ -95,8 +96,9 @@ struct RunArgs {
   int64_t *data;    // value arena
   uint64_t *words;  // one control word per global row
   uint64_t *aux;    // second word per row (MVCC version pointer)
-  uint64_t *nodes;  // MVCC history nodes, 3 words per op of the batch
+  uint64_t *nodes;  // MVCC version arena: n_nodes slots of 4 words {tag, prev, writer ts | cell << 32, pre-image}
   uint64_t n_nodes;
+  uint64_t *node_ring;  // MVCC: slots handed out so far (the arena is a ring; pos -> slot pos % n_nodes)
   DevOutcome *out;
   int64_t *reads;   // per op read value
   Ctl *ctl;

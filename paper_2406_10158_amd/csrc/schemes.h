@@ -521,10 +521,21 @@ __device__ __forceinline__ int tplwd_attempt(const Team<L> &t, Slots<K> &s, bool
 //       it) store new values, wait, publish word = {RTS=ts, WTS=ts}.
 // Serial key (0, ts).  Timestamps are relative to the run and must stay
 // below 2^31; reaching it stops the run with CC_E_TS_OVERFLOW.
-// History nodes (MVCC): one per write operation, 3 words {prev node,
-// writer ts | cell << 32, pre-image}; node i+1 belongs to op i (0 = none).
-// A chain lists a row's writers newest first; a reader at ts starts from the
-// current value and undoes, field by field, every writer newer than ts.
+// Version arena (MVCC): a ring of n_nodes slots of 4 words {tag, prev,
+// writer ts | cell << 32, pre-image}.  A committing writer takes one slot per
+// written field from the ring counter (position pos: slot pos % n_nodes, lap
+// gen = pos / n_nodes + 1) and claims it by CAS on the tag, from an idle
+// (even) tag of an earlier lap to 2gen-1 (writing), and stores 2gen once the
+// node is written.  A version pointer (the row's, or a node's prev) is gen << 32 |
+// (slot + 1); 0 is none.  A chain lists a row's writers newest first; a
+// reader at ts starts from the current value and undoes, field by field,
+// every writer newer than ts.  It reads a node's fields, then its tag: a tag
+// other than 2gen means the slot was taken again by a later lap, so the
+// version is gone and the attempt aborts (its retry draws a newer ts).  A
+// node is complete before any reader can reach it: it is linked while its
+// writer holds the row dirty, and readers walk only chains they found clean
+// and unchanged in R3.  The ring is sized by the run: one slot per op of the
+// batch, or, when serving, hbm_cap_bytes / 32, which bounds the arena.
 // ===========================================================================
 constexpr uint64_t TO_DIRTY = 1ull << 63;
 constexpr uint64_t TO_MASK31 = (1ull << 31) - 1ull;
@@ -650,40 +661,110 @@ __device__ __forceinline__ int to_attempt(const Team<L> &t, Slots<K> &s, bool ac
         int64_t val = s.x[k];
         uint64_t p = ptr[k];
         int steps = 0;
-        while (p != 0 && p <= a.n_nodes && steps < MVCC_MAX_WALK) {
-          const uint64_t *node = a.nodes + 3 * (p - 1);
-          const uint64_t tf = ld_word(node + 1);
+        bool gone = false;
+        while (p != 0 && steps < MVCC_MAX_WALK) {
+          const uint64_t slot = (p & 0xFFFFFFFFull) - 1, gen = p >> 32;
+          if (slot >= a.n_nodes) {
+            gone = true;
+            break;
+          }
+          const uint64_t *node = a.nodes + 4 * slot;
+          const uint64_t prev = ld_word(node + 1), tf = ld_word(node + 2), pre = ld_word(node + 3);
+          order_point<STRICT>();
+          // the fields belong to this version only if the slot still carries its tag
+          if (ld_word(node) != 2 * gen) {
+            gone = true;
+            break;
+          }
           if ((tf & 0xFFFFFFFFull) <= ts) break;
-          if ((uint32_t)(tf >> 32) == cell) val = (int64_t)ld_word(node + 2);
-          p = ld_word(node);
+          if ((uint32_t)(tf >> 32) == cell) val = (int64_t)pre;
+          p = prev;
           ++steps;
         }
-        if (p > a.n_nodes || steps >= MVCC_MAX_WALK) bad = true;
+        if (gone) add_word(&a.ctl->stats[DS_VERSION_MISS], 1ull);
+        if (gone || steps >= MVCC_MAX_WALK) bad = true;
         s.x[k] = val;
       }
     }
   }
-  const bool valid_fail = t.any(bad);
-  const bool commit = alive && !valid_fail;
+  bool valid_fail = t.any(bad);
+  bool commit = alive && !valid_fail;
+  uint64_t pos[K];
+  if (MV) {
+    // claim a slot of the version ring for every write op of the committing
+    // teams: one fetch_add per wavefront, then a CAS on each slot's tag
+    uint32_t nw = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) nw += commit && s.valid[k] && op_kind(s.rowk[k]) != CC_READ;
+    uint32_t total = 0;
+    const uint32_t before = wave_excl_scan(nw, &total);
+    uint64_t base = 0;
+    bool claim_fail = false;
+    bool claimed[K];
+    if (total) {
+      const int first = __ffsll((unsigned long long)ballot(nw != 0)) - 1;
+      if (t.lane == first) base = add_word(a.node_ring, (uint64_t)total);
+      base = readlane64(base, first);
+      uint32_t j = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        claimed[k] = false;
+        pos[k] = 0;
+        if (commit && s.valid[k] && op_kind(s.rowk[k]) != CC_READ) {
+          pos[k] = base + before + j++;
+          // any idle tag of an older lap will do (a lap whose claim failed
+          // left its older tag behind); an odd tag is a writer at work
+          const uint64_t gen = pos[k] / a.n_nodes + 1;
+          uint64_t *tag = a.nodes + 4 * (pos[k] % a.n_nodes);
+          uint64_t seen = 2 * (gen - 1);
+          for (int i = 0; i < 4 && !claimed[k]; ++i) {
+            if ((seen & 1) || seen >= 2 * gen) break;
+            claimed[k] = cas_word(tag, &seen, 2 * gen - 1);
+          }
+          claim_fail |= !claimed[k];
+        }
+      }
+      order_point<STRICT>();
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) claimed[k] = false;
+    }
+    // a slot still being written by a writer of an earlier lap fails the
+    // commit: the slots taken are marked done for this lap, holding no
+    // version (nothing links to them), and the attempt aborts
+    if (t.any(claim_fail) && commit) {
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (claimed[k]) st_word(a.nodes + 4 * (pos[k] % a.n_nodes), 2 * (pos[k] / a.n_nodes + 1));
+      commit = false;
+      valid_fail = true;
+    }
+  }
   if (alive && valid_fail) {
 #pragma unroll
     for (int k = 0; k < K; ++k)
       if (s.got[k]) w_st<LATCH, STRICT>(a, a.words + op_row(s.rowk[k]), s.v[k]);
   }
   if (MV) {
-    // history nodes for every write op: pre-image, writer ts, cell; link with
-    // an exchange on the row's version pointer (we hold the row, so only our
-    // own lanes link concurrently)
+    // link each claimed node into its row's chain (we hold the row dirty, so
+    // only our own lanes link it concurrently) and fill it; the tag that
+    // validates it is stored with the installs, before the row is published
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (commit && s.valid[k] && op_kind(s.rowk[k]) != CC_READ) {
-        uint64_t *node = a.nodes + 3 * (uint64_t)s.oi[k];
-        st_word(node + 1, ts | ((uint64_t)s.elem[k] << 32));
-        st_word(node + 2, (uint64_t)s.x[k]);
-        const uint64_t prev = xchg_word(a.aux + op_row(s.rowk[k]), (uint64_t)s.oi[k] + 1);
-        st_word(node, prev);
+        uint64_t *node = a.nodes + 4 * (pos[k] % a.n_nodes);
+        const uint64_t me = ((pos[k] / a.n_nodes + 1) << 32) | (pos[k] % a.n_nodes + 1);
+        st_word(node + 2, ts | ((uint64_t)s.elem[k] << 32));
+        st_word(node + 3, (uint64_t)s.x[k]);
+        const uint64_t prev = xchg_word(a.aux + op_row(s.rowk[k]), me);
+        st_word(node + 1, prev);
       }
     }
+    order_point<STRICT>();
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (commit && s.valid[k] && op_kind(s.rowk[k]) != CC_READ)
+        st_word(a.nodes + 4 * (pos[k] % a.n_nodes), 2 * (pos[k] / a.n_nodes + 1));
   }
   install_values<L, K>(t, s, commit, a);
   order_point<STRICT>();

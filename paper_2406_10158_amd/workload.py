@@ -493,23 +493,119 @@ def order_entry_workload(n_warehouses: int, n_txns: int, seed: int = 0, new_orde
 # Serving streams: Poisson arrivals over a key-value / order-entry mix
 # ----------------------------------------------------------------------------
 
+def _gather_ops(sources, src, idx):
+    """Operation index arrays of the transactions (sources[src[i]], idx[i]), concatenated in order.
+
+    Returns (lengths, per-source op indices) so that the caller can gather
+    each column from its source without a loop over transactions.
+    """
+    src = np.asarray(src, np.int64)
+    idx = np.asarray(idx, np.int64)
+    lengths = np.zeros(len(src), np.int64)
+    firsts = np.zeros(len(src), np.int64)
+    for j, bt in enumerate(sources):
+        m = src == j
+        lengths[m] = bt.n_ops[idx[m]].astype(np.int64)
+        firsts[m] = bt.first_op[idx[m]].astype(np.int64)
+    total = int(lengths.sum())
+    starts = np.zeros(len(src), np.int64)
+    if len(src) > 1:
+        starts[1:] = np.cumsum(lengths[:-1])
+    # op k of the result: source op firsts[t] + (k - starts[t]) of the transaction t that owns it
+    owner = np.repeat(np.arange(len(src)), lengths)
+    op_idx = firsts[owner] + (np.arange(total, dtype=np.int64) - starts[owner])
+    return lengths, src[owner], op_idx
+
+
 def concat_batches(parts):
     """One batch holding the given batches' transactions, in the given (batch, txn ids) order."""
-    lengths, row, table, field, kind, arg = [], [], [], [], [], []
+    sources = []
+    src, idx = [], []
     for bt, ids in parts:
-        for t in ids:
-            sl = bt.txn_slice(int(t))
-            lengths.append(int(bt.n_ops[t]))
-            row.append(bt.row[sl]); table.append(bt.table[sl]); field.append(bt.field[sl])
-            kind.append(bt.kind[sl]); arg.append(bt.arg[sl])
-    cat = (lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.zeros(0, dt))
-    return _pack(lengths, cat(row, np.uint32), cat(table, np.uint16), cat(field, np.uint8), cat(kind, np.uint8),
-                 cat(arg, np.int64), {})
+        j = next((i for i, x in enumerate(sources) if x is bt), None)
+        if j is None:
+            sources.append(bt)
+            j = len(sources) - 1
+        ids = np.asarray(ids, np.int64).reshape(-1)
+        src.append(np.full(len(ids), j, np.int64))
+        idx.append(ids)
+    src = np.concatenate(src) if src else np.zeros(0, np.int64)
+    idx = np.concatenate(idx) if idx else np.zeros(0, np.int64)
+    return _concat_sources(sources, src, idx)
+
+
+def _concat_sources(sources, src, idx):
+    lengths, op_src, op_idx = _gather_ops(sources, src, idx)
+    cols = {}
+    for name, dt in (("row", np.uint32), ("table", np.uint16), ("field", np.uint8), ("kind", np.uint8),
+                     ("arg", np.int64)):
+        out = np.zeros(len(op_idx), dt)
+        for j, bt in enumerate(sources):
+            m = op_src == j
+            out[m] = getattr(bt, name)[op_idx[m]]
+        cols[name] = out
+    return _pack(lengths, cols["row"], cols["table"], cols["field"], cols["kind"], cols["arg"], {})
+
+
+def _kv_chunk(args):
+    n_rows, n_fields, n, ops, theta, seed = args
+    return kv_batch(n_rows, n_fields, n, ops=ops, theta=theta, seed=seed)
+
+
+def kv_parallel(n_rows: int, n_fields: int, n_txns: int, ops=16, theta: float = 0.0, seed: int = 0,
+                workers: int = 8, chunk: int = 0):
+    """Key-value transactions generated in chunks on `workers` processes (chunk i: seed * 7919 + i)."""
+    import multiprocessing as mp
+    chunk = chunk or max(20_000, -(-n_txns // (4 * max(workers, 1))))
+    sizes = [min(chunk, n_txns - i) for i in range(0, n_txns, chunk)]
+    jobs = [(n_rows, n_fields, n, ops, theta, seed * 7919 + i) for i, n in enumerate(sizes)]
+    with mp.get_context("fork").Pool(max(1, min(workers, len(jobs)))) as pool:
+        chunks = pool.map(_kv_chunk, jobs)
+    src = np.concatenate([np.full(len(b.n_ops), j, np.int64) for j, b in enumerate(chunks)])
+    idx = np.concatenate([np.arange(len(b.n_ops), dtype=np.int64) for b in chunks])
+    return _concat_sources(chunks, src, idx)
+
+
+def _oe_chunk(args):
+    w, n, seed = args
+    _, b = order_entry_workload(w, n, seed=seed)
+    return b
+
+
+def order_entry_parallel(n_warehouses: int, n_txns: int, seed: int = 0, workers: int = 8, chunk: int = 0):
+    """Order-entry transactions generated in chunks on `workers` processes.
+
+    Chunk i is ``order_entry_workload(W, ., seed + 1 + i)``; its order and
+    order-line slots are moved past the previous chunks' slots, so that every
+    new-order still owns its own slots.  The tables are the single-process
+    generator's for ``seed`` with room for every slot.
+    """
+    import multiprocessing as mp
+    chunk = chunk or max(20_000, -(-n_txns // (4 * max(workers, 1))))
+    sizes = [min(chunk, n_txns - i) for i in range(0, n_txns, chunk)]
+    jobs = [(n_warehouses, n, seed + 1 + i) for i, n in enumerate(sizes)]
+    with mp.get_context("fork").Pool(max(1, min(workers, len(jobs)))) as pool:
+        chunks = pool.map(_oe_chunk, jobs)
+    no_off = lo_off = 0
+    for b in chunks:
+        m_o = b.table == T_ORDER
+        m_l = b.table == T_ORDER_LINE
+        b.row[m_o] += np.uint32(no_off)
+        b.row[m_l] += np.uint32(lo_off)
+        no_off += int(b.meta["n_new_orders"])
+        lo_off += int(b.meta["n_order_lines"])
+    tables = order_entry_tables(n_warehouses, no_off, lo_off, seed)
+    src = np.concatenate([np.full(len(b.n_ops), j, np.int64) for j, b in enumerate(chunks)])
+    idx = np.concatenate([np.arange(len(b.n_ops), dtype=np.int64) for b in chunks])
+    out = _concat_sources(chunks, src, idx)
+    out.meta = dict(workload="order_entry", n_warehouses=n_warehouses, seed=seed, n_new_orders=no_off,
+                    n_order_lines=lo_off, is_new_order=np.concatenate([b.meta["is_new_order"] for b in chunks]))
+    return tables, out
 
 
 def serve_stream(n_arrivals: int, rate_per_s: float, kv_rows=10_000_000, kv_fields=10, kv_ops=(8, 32),
                  kv_theta=0.9, oe_warehouses=8, kv_frac=0.5, isolated_frac=0.0, seed=0, with_kv=True,
-                 with_oe=True, arrivals_ns=None, kinds=None):
+                 with_oe=True, arrivals_ns=None, kinds=None, workers=0, log=None):
     """A serving stream: tables, one batch in arrival order, arrival times (ns), and masks.
 
     Arrivals are a Poisson process of ``rate_per_s`` (exponential gaps).  Each
@@ -520,6 +616,9 @@ def serve_stream(n_arrivals: int, rate_per_s: float, kv_rows=10_000_000, kv_fiel
     reserved range at the top of the key-value table that nothing else
     touches.  ``with_kv`` / ``with_oe`` drop one kind (keeping the others'
     arrival times), which gives the "alone" runs of a mixed stream.
+    ``workers`` > 0 generates each part of a long stream (more than 200k
+    arrivals of that kind) in chunks on that many processes; ``log`` (a
+    callable) receives a line as each part is done.
     """
     rng = np.random.Generator(np.random.PCG64(seed + 7_000_001))
     if arrivals_ns is None:
@@ -533,7 +632,10 @@ def serve_stream(n_arrivals: int, rate_per_s: float, kv_rows=10_000_000, kv_fiel
     iso_rows_per = kv_ops[1] if isinstance(kv_ops, (tuple, list)) else int(kv_ops)
     reserved = n_iso * iso_rows_per
     shared_rows = kv_rows - reserved
-    kvb = kv_batch(shared_rows, kv_fields, n_kv, ops=kv_ops, theta=kv_theta, seed=seed)
+    if workers and n_kv > 200_000 and n_iso == 0:
+        kvb = kv_parallel(shared_rows, kv_fields, n_kv, ops=kv_ops, theta=kv_theta, seed=seed, workers=workers)
+    else:
+        kvb = kv_batch(shared_rows, kv_fields, n_kv, ops=kv_ops, theta=kv_theta, seed=seed)
     iso = np.zeros(n_kv, bool)
     if n_iso:
         iso_ids = rng.choice(n_kv, size=n_iso, replace=False)
@@ -541,23 +643,28 @@ def serve_stream(n_arrivals: int, rate_per_s: float, kv_rows=10_000_000, kv_fiel
         for j, t in enumerate(np.sort(iso_ids)):
             sl = kvb.txn_slice(int(t))
             kvb.row[sl] = shared_rows + j * iso_rows_per + np.arange(sl.stop - sl.start, dtype=np.uint32)
-    oe_tables, oeb = order_entry_workload(oe_warehouses, max(n_oe, 1), seed=seed + 1)
+    if log:
+        log(f"key-value part: {n_kv} transactions")
+    if workers and n_oe > 200_000:
+        # long streams: order-entry chunks generated in parallel processes
+        oe_tables, oeb = order_entry_parallel(oe_warehouses, n_oe, seed=seed + 1, workers=workers)
+    else:
+        oe_tables, oeb = order_entry_workload(oe_warehouses, max(n_oe, 1), seed=seed + 1)
     oeb.table = (oeb.table + 1).astype(np.uint16)
+    if log:
+        log(f"order-entry part: {n_oe} transactions")
     tables = [kv_table(kv_rows, kv_fields)] + oe_tables
-    parts, is_kv, is_iso, keep = [], [], [], []
-    ik = io = 0
-    for a in range(n_arrivals):
-        if kinds[a]:
-            if with_kv:
-                parts.append((kvb, [ik])); is_kv.append(True); is_iso.append(bool(iso[ik])); keep.append(a)
-            ik += 1
-        else:
-            if with_oe:
-                parts.append((oeb, [io])); is_kv.append(False); is_iso.append(False); keep.append(a)
-            io += 1
-    batch = concat_batches(parts)
+    # interleave in arrival order: the a-th key-value arrival is kv transaction a', the
+    # a-th order-entry arrival order-entry transaction a''
+    kind_idx = np.where(kinds, np.cumsum(kinds) - 1, np.cumsum(~kinds) - 1).astype(np.int64)
+    keep_m = (kinds & with_kv) | (~kinds & with_oe)
+    keep = np.nonzero(keep_m)[0].astype(np.int64)
+    src = np.where(kinds[keep], 0, 1).astype(np.int64)
+    batch = _concat_sources([kvb, oeb], src, kind_idx[keep])
+    is_kv = kinds[keep].astype(bool)
+    is_iso = np.zeros(len(keep), bool)
+    is_iso[is_kv] = iso[kind_idx[keep][is_kv]]
     batch.meta = dict(workload="serve", rate_per_s=rate_per_s, seed=seed, oe_warehouses=oe_warehouses,
-                      is_new_order=np.array([False] * len(is_kv)))
-    keep = np.array(keep, np.int64)
+                      is_new_order=np.zeros(len(keep), bool))
     return tables, batch, arrivals_ns[keep] if len(keep) else np.zeros(0, np.int64), dict(
-        is_kv=np.array(is_kv, bool), is_isolated=np.array(is_iso, bool), arrivals_all=arrivals_ns, kinds=kinds)
+        is_kv=is_kv, is_isolated=is_iso, arrivals_all=arrivals_ns, kinds=kinds)

@@ -118,6 +118,29 @@ def test_serve_small_budget_throttles_but_loses_nothing(scheme):
     assert check(tabs, b, out, reads, final).ok
 
 
+@pytest.mark.parametrize("kv_rows,slots", [(2_000, 1_024), (2_000, 4_096), (100_000, 4_096)])
+def test_serve_mvcc_version_arena_bounded_by_the_cap(kv_rows, slots):
+    # the cap sizes MVCC's version arena (cap / 32 slots, at least 1024); a stream that commits
+    # many times more writes than the arena holds reuses its slots as a ring, and old-version
+    # reads whose slot was reused abort and retry -- the run still equals the serial replay
+    bb = binding()
+    tabs, b, arr, m = wl.serve_stream(30_000, 5e6, kv_rows=kv_rows, seed=36)
+    writes = int((b.kind != 0).sum())
+    cap = slots * 32
+    out, reads, final, st = serve(tabs, b, arr, "mvcc", hbm_cap_bytes=cap)
+    assert st["version_slots"] == slots and writes > 100 * slots
+    assert st["committed"] == b.n_txns
+    rep = check(tabs, b, out, reads, final)
+    assert rep.ok, rep
+    assert oracle.order_entry_invariants(tabs[1:], final[1:], _oe_part(b, m), out["status"][~m["is_kv"]] == 1) == []
+    print(f"[gpu] mvcc serve kv_rows={kv_rows}: {writes} writes through {st['version_slots']} slots, "
+          f"{st['version_misses']} version misses", flush=True)
+    # without a cap: one slot per op of the stream
+    out, reads, final, st = serve(tabs, b, arr, "mvcc")
+    assert st["version_slots"] == max(b.total_ops, 1024)
+    assert check(tabs, b, out, reads, final).ok
+
+
 def test_serve_needs_arrivals():
     bb = binding()
     tabs, b, arr, m = wl.serve_stream(100, 1e6, kv_rows=10_000, seed=34)
