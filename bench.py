@@ -375,6 +375,23 @@ def suite_batching(args, binding, workload):
     eng.close()
 
 
+def suite_epoch(args, binding, workload):
+    """The batching configuration's largest batch (2^20 transactions of 2-64 ops, Zipf 0.8) run once in
+    plain mode and once in epoch mode (one warm-up each), for a kernel trace of the epoch graph."""
+    tables, batch = workload.kv_workload(n_rows=args.rows, n_fields=args.fields, n_txns=1 << 20, ops=(2, 64),
+                                         theta=0.8, seed=args.seed)
+    eng = binding.Engine(tables)
+    bid = eng.submit(batch, "occ")
+    for mode, name in ((binding.CC_MODE_PLAIN, "plain"), (binding.CC_MODE_EPOCH, "epoch")):
+        for rep in range(2):
+            eng.load(tables)
+            st = eng.run(bid, mode=mode)
+        _emit({"suite": "epoch", "mode": name, "txns": batch.n_txns, "txn_per_s": round(batch.n_txns / (st["run_ns"] * 1e-9), 1),
+               "run_ms": round(st["run_ns"] / 1e6, 3), "kernel_ms": round(st["kernel_ns"] / 1e6, 3),
+               "epochs": st["epochs"], "passes": st["passes"], "attempts": st["attempts"]})
+    eng.close()
+
+
 def suite_serving(args, binding, workload):
     """Poisson streams of key-value (8-32 ops, Zipf 0.9) + order-entry (W=8) at increasing offered load.
 
@@ -453,7 +470,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probes", action="store_true", help="only run the memory micro-benchmarks")
-    ap.add_argument("--suite", choices=["schemes", "order_entry", "batching", "serving", "index", "latch", "ycsb"],
+    ap.add_argument("--suite", choices=["schemes", "order_entry", "batching", "serving", "index", "latch", "ycsb",
+                                        "epoch"],
                     help="run a measurement suite instead of the headline step (JSON line per point)")
     ap.add_argument("--only", default="", help="comma-separated schemes a suite runs (default: all of its schemes)")
     ap.add_argument("--oe-txns", type=int, default=100_000)
@@ -478,7 +496,7 @@ def main():
         return
     if args.suite:
         {"schemes": suite_schemes, "order_entry": suite_order_entry, "batching": suite_batching, "index": suite_index,
-         "latch": suite_latch, "ycsb": suite_ycsb,
+         "latch": suite_latch, "ycsb": suite_ycsb, "epoch": suite_epoch,
          "serving": suite_serving}[args.suite](args, binding, workload)
         return
 
