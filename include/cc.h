@@ -305,7 +305,9 @@ enum cc_stat {
   CC_STAT_HOT_WRITES = 31, /* writes to the batch's most written row (counted at submission) */
   CC_STAT_BLOCKED_WAITS = 32, /* CC_RUN_WAIT_BLOCKER: waits for a held row that failed attempts entered */
   CC_STAT_VERSION_SLOTS = 33, /* CC_MVCC: slots of the version arena (32 bytes each): one per op of the
-                                 batch, or hbm_cap_bytes / 32 in CC_MODE_SERVE with a cap; at least 1024 */
+                                 batch, or hbm_cap_bytes / 32 in CC_MODE_SERVE with a cap; at least 1024.
+                                 With at least one slot per op, op i keeps slot i and no slot is
+                                 reused; with fewer, the arena is a ring */
   CC_STAT_VERSION_MISSES = 34,/* CC_MVCC: old-version reads whose version's slot the ring had reused
                                  (the attempt aborted and retried with a newer timestamp) */
   CC_N_STATS = 40

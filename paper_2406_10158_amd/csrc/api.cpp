@@ -1225,6 +1225,8 @@ static cc_status run_batch(cc_ctx *c, Batch &b, const cc_run_params &p, bool hos
   a.nodes = b.d_nodes ? b.d_nodes + 4 : nullptr;
   a.node_ring = b.d_nodes;
   a.n_nodes = b.node_slots;
+  // a slot for every op: op i keeps slot i and no slot is reused in the run
+  a.node_reuse = b.node_slots < b.n_ops ? 1u : 0u;
   a.out = b.d_out;
   a.reads = b.d_reads;
   a.ctl = c->d_ctl;

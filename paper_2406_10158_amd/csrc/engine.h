@@ -116,7 +116,7 @@ struct RunArgs {
   uint32_t pad4;
   uint32_t precheck;       // OCC, TicToc, TO, MVCC: load-only round before any lock: 0 never, 1 on retries, 2 always
   uint32_t wd_wait_limit;  // 2PL wait-die: waits of one attempt before it dies anyway
-  uint32_t pad5;
+  uint32_t node_reuse;     // MVCC: 0 = a slot per op (op i keeps slot i, never reused); 1 = the ring protocol
   uint32_t *latch;         // CC_RUN_LATCH: one 32-bit latch per global row (else unused)
   // OCC: the batch's hottest written rows (most writes first), locked -- or,
   // for a read-only access, looked at -- in a round of their own once every

@@ -536,6 +536,11 @@ __device__ __forceinline__ int tplwd_attempt(const Team<L> &t, Slots<K> &s, bool
 // writer holds the row dirty, and readers walk only chains they found clean
 // and unchanged in R3.  The ring is sized by the run: one slot per op of the
 // batch, or, when serving, hbm_cap_bytes / 32, which bounds the arena.
+// Each run starts with empty chains, so with a slot for every op of the batch
+// no slot is ever taken twice in a run: op i then writes its node into slot i
+// with no claim and no tag, and readers skip the tag check (node_reuse = 0).
+// The claim, the tags and the check are the ring's (node_reuse = 1), for an
+// arena smaller than the batch.
 // ===========================================================================
 constexpr uint64_t TO_DIRTY = 1ull << 63;
 constexpr uint64_t TO_MASK31 = (1ull << 31) - 1ull;
@@ -670,11 +675,13 @@ __device__ __forceinline__ int to_attempt(const Team<L> &t, Slots<K> &s, bool ac
           }
           const uint64_t *node = a.nodes + 4 * slot;
           const uint64_t prev = ld_word(node + 1), tf = ld_word(node + 2), pre = ld_word(node + 3);
-          order_point<STRICT>();
-          // the fields belong to this version only if the slot still carries its tag
-          if (ld_word(node) != 2 * gen) {
-            gone = true;
-            break;
+          if (a.node_reuse) {
+            order_point<STRICT>();
+            // the fields belong to this version only if the slot still carries its tag
+            if (ld_word(node) != 2 * gen) {
+              gone = true;
+              break;
+            }
           }
           if ((tf & 0xFFFFFFFFull) <= ts) break;
           if ((uint32_t)(tf >> 32) == cell) val = (int64_t)pre;
@@ -690,7 +697,11 @@ __device__ __forceinline__ int to_attempt(const Team<L> &t, Slots<K> &s, bool ac
   bool valid_fail = t.any(bad);
   bool commit = alive && !valid_fail;
   uint64_t pos[K];
-  if (MV) {
+  if (MV && !a.node_reuse) {
+    // a slot per op: op i's node is slot i, in lap 1
+#pragma unroll
+    for (int k = 0; k < K; ++k) pos[k] = (uint64_t)s.oi[k];
+  } else if (MV) {
     // claim a slot of the version ring for every write op of the committing
     // teams: one fetch_add per wavefront, then a CAS on each slot's tag
     uint32_t nw = 0;
@@ -760,11 +771,13 @@ __device__ __forceinline__ int to_attempt(const Team<L> &t, Slots<K> &s, bool ac
         st_word(node + 1, prev);
       }
     }
-    order_point<STRICT>();
+    if (a.node_reuse) {
+      order_point<STRICT>();
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (commit && s.valid[k] && op_kind(s.rowk[k]) != CC_READ)
-        st_word(a.nodes + 4 * (pos[k] % a.n_nodes), 2 * (pos[k] / a.n_nodes + 1));
+      for (int k = 0; k < K; ++k)
+        if (commit && s.valid[k] && op_kind(s.rowk[k]) != CC_READ)
+          st_word(a.nodes + 4 * (pos[k] % a.n_nodes), 2 * (pos[k] / a.n_nodes + 1));
+    }
   }
   install_values<L, K>(t, s, commit, a);
   order_point<STRICT>();
