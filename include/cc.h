@@ -230,6 +230,26 @@ enum cc_mode { CC_MODE_PLAIN = 0, CC_MODE_EPOCH = 1, CC_MODE_SERVE = 2 };
                                      CC_MODE_SERVE); the final pass, which never defers, keeps the
                                      randomised back-off, so two transactions that block each other cannot
                                      retry in lockstep forever there */
+#define CC_RUN_HOT_ENGINE 0x800u  /* OCC, CC_MODE_PLAIN (CC_E_INVAL otherwise, and with CC_RUN_LATCH): run
+                                     the transactions that write one of the batch's most written rows
+                                     first, in one workgroup that holds those rows in LDS (hot-row engine:
+                                     up to 32 rows written at least max(2, n_txns / 4096) times, of at most
+                                     64 fields, found at submission; CC_STAT_ENGINE_*).  There an engine
+                                     row takes a reader-writer lock in LDS -- shared to read, exclusive to
+                                     write -- and a transaction that finds it taken gives back what it holds
+                                     and waits until it is free; the other rows follow OCC (lock written
+                                     rows, validate read rows) and the ticket comes from an LDS counter.  The rest of the
+                                     batch then runs as usual, with the engine rows only read.  Paper
+                                     Section 2 "Optimistic Concurrency Control" and Section 3.5 "OCC", with
+                                     hot rows locked pessimistically.  On by default for a contended OCC
+                                     batch (its most written row written by at least 0.1% of its
+                                     transactions) whose rows left out of the engine are written at most a
+                                     quarter as often as the most written one.  The engine runs one
+                                     transaction per wavefront (64 lanes) and as many wavefronts as fit,
+                                     unless lanes_per_txn / waves_per_wg are set; it needs at most 4 ops per
+                                     lane (CC_E_INVAL at cc_run when forced without) and a batch submitted by
+                                     row (the keyed path finds rows only at the run). */
+#define CC_RUN_NO_HOT_ENGINE 0x1000u /* OCC: no hot-row engine (CC_E_INVAL with CC_RUN_HOT_ENGINE) */
 #define CC_RUN_EAGER_INSTALL 0x2u /* OCC only (CC_E_INVAL for another scheme): store new values in the
                                      validation round (undo on abort) instead of after validation
                                      succeeds; measured ~3% slower on the key-value workload, kept for
@@ -310,6 +330,11 @@ enum cc_stat {
                                  reused; with fewer, the arena is a ring */
   CC_STAT_VERSION_MISSES = 34,/* CC_MVCC: old-version reads whose version's slot the ring had reused
                                  (the attempt aborted and retried with a newer timestamp) */
+  CC_STAT_ENGINE_TXNS = 35,   /* CC_RUN_HOT_ENGINE: transactions the hot-row engine ran (0: no engine) */
+  CC_STAT_ENGINE_ROWS = 36,   /* CC_RUN_HOT_ENGINE: rows the engine held in LDS */
+  CC_STAT_ENGINE_NS = 37,     /* CC_RUN_HOT_ENGINE: the engine's kernel time (part of CC_STAT_KERNEL_NS) */
+  CC_STAT_ENGINE_WAITS = 38,  /* CC_RUN_HOT_ENGINE: loop iterations a transaction spent waiting for an
+                                 engine row, keeping its locks */
   CC_N_STATS = 40
 };
 

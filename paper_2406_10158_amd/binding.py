@@ -42,12 +42,14 @@ CC_RUN_SHARED_READS = 0x80
 CC_RUN_HOT_LAST = 0x100
 CC_RUN_NO_HOT_LAST = 0x200
 CC_RUN_WAIT_BLOCKER = 0x400
+CC_RUN_HOT_ENGINE = 0x800
+CC_RUN_NO_HOT_ENGINE = 0x1000
 STAT_NAMES = ["committed", "attempts", "abort_lock", "abort_valid", "kernel_ns", "run_ns", "tickets",
               "max_attempts", "lat_p50_ns", "lat_p99_ns", "epochs", "passes", "deferred", "grid",
               "t_useful_ns", "t_abort_ns", "t_wait_ns", "gave_up", "admit_waits",
               "occ_r1_ns", "occ_r2_ns", "occ_r3_ns", "occ_r4_ns", "prep_ns", "index_ns", "wd_waits", "ksets",
               "packed_state", "hot_acq", "hot_failed", "hot_hold_ns", "hot_writes", "blocked_waits",
-              "version_slots", "version_misses"]
+              "version_slots", "version_misses", "engine_txns", "engine_rows", "engine_ns", "engine_waits"]
 CC_N_STATS = 40
 CC_STATIC_MAX_TXNS = 1 << 18
 CC_STATIC_MAX_OPS = 1 << 20

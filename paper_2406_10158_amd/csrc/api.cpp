@@ -55,6 +55,15 @@ struct Batch {
   uint64_t hot_writes = 0;
   uint32_t n_hot = 0;
   uint32_t hot_rows[HOT_MAX] = {};
+  // OCC hot-row engine, planned at submission (plan_engine): its rows, and
+  // d_part = the transactions that write one of them (n_eng_txns), then the
+  // others; eng_gain: every row left out is written at most a quarter as often
+  // as the most written row
+  EngineArgs eng{};
+  uint64_t n_eng_txns = 0;
+  bool eng_gain = false;
+  uint32_t *d_part = nullptr;
+  std::vector<uint32_t> eng_part;  // host copy until the upload
 };
 
 }  // namespace
@@ -173,6 +182,8 @@ void free_batch(Batch &b) {
   if (b.d_out) (void)hipFree(b.d_out);
   if (b.d_reads) (void)hipFree(b.d_reads);
   if (b.d_list) (void)hipFree(b.d_list);
+  if (b.d_part) (void)hipFree(b.d_part);
+  b.d_part = nullptr;
   if (b.d_nodes) (void)hipFree(b.d_nodes);
   if (b.d_opkeys) (void)hipFree(b.d_opkeys);
   if (b.d_meta) (void)hipFree(b.d_meta);
@@ -703,16 +714,110 @@ cc_status run_gputx(cc_ctx *c, Batch &b, const cc_run_params &p, uint32_t lanes,
   return CC_OK;
 }
 
+// The hot-row engine's plan from the per-row write counts (see find_hot_rows).
+static void plan_engine(const DevOp *dops, const DevTxn *dtx, uint64_t n_txns, const std::vector<Table> &tables,
+                        const std::vector<uint32_t> &cnt, Batch &b) {
+  b.eng = EngineArgs{};
+  b.n_eng_txns = 0;
+  b.eng_gain = false;
+  b.eng_part.clear();
+  const uint32_t thr = (uint32_t)std::max<uint64_t>(2, n_txns / 4096);
+  // candidates: the most written rows (more than fit, to know the best row left out)
+  constexpr int NC = ENG_MAX + 16;
+  uint32_t cc[NC] = {}, cr[NC] = {};
+  int nc = 0;
+  for (uint64_t r = 0; r < cnt.size(); ++r) {
+    const uint32_t c = cnt[r];
+    if (c < thr || (nc == NC && c <= cc[NC - 1])) continue;
+    int i = nc < NC ? nc++ : NC - 1;
+    while (i > 0 && cc[i - 1] < c) {
+      cc[i] = cc[i - 1];
+      cr[i] = cr[i - 1];
+      --i;
+    }
+    cc[i] = c;
+    cr[i] = (uint32_t)r;
+  }
+  if (nc == 0) return;
+  uint32_t left_out = 0;  // writes of the most written row not taken
+  bool full = false;
+  for (int i = 0; i < nc; ++i) {
+    const uint32_t r = cr[i];
+    const Table *tb = nullptr;
+    for (const Table &t : tables)
+      if (r >= t.row_base && r < t.row_base + t.n_rows) tb = &t;
+    bool take = !full && tb && tb->n_fields <= (uint32_t)ENG_FIELDS && b.eng.n_vals + tb->n_fields <= (uint32_t)ENG_VALS;
+    if (take) {
+      const uint32_t k = b.eng.n_rows++;
+      b.eng.row[k] = r;
+      b.eng.elem0[k] = (uint32_t)(tb->elem_base + (r - tb->row_base) * tb->n_fields);
+      b.eng.off[k] = b.eng.n_vals;
+      b.eng.n_vals += tb->n_fields;
+      full = b.eng.n_rows == (uint32_t)ENG_MAX;
+    } else if (!left_out) {
+      left_out = cc[i];
+    }
+  }
+  if (b.eng.n_rows == 0) return;
+  b.eng.off[b.eng.n_rows] = b.eng.n_vals;
+  // a row below the candidates is written at most as often as the last candidate
+  if (!left_out && nc == NC) left_out = cc[NC - 1];
+  b.eng_gain = (uint64_t)left_out * 4 <= (uint64_t)cc[0];
+  std::vector<uint8_t> is_eng(cnt.size(), 0);
+  for (uint32_t k = 0; k < b.eng.n_rows; ++k) is_eng[b.eng.row[k]] = 1;
+  std::vector<uint8_t> in_eng(n_txns, 0);
+  for (uint64_t t = 0; t < n_txns; ++t)
+    for (uint32_t i = 0; i < dtx[t].n && !in_eng[t]; ++i) {
+      const uint32_t rk = dops[dtx[t].first + i].rowk;
+      in_eng[t] = (rk & WRITTEN_BIT) && is_eng[rk & ROW_MASK];
+    }
+  b.eng_part.reserve(n_txns);
+  for (uint64_t t = 0; t < n_txns; ++t)
+    if (in_eng[t]) b.eng_part.push_back((uint32_t)t);
+  b.n_eng_txns = b.eng_part.size();
+  for (uint64_t t = 0; t < n_txns; ++t)
+    if (!in_eng[t]) b.eng_part.push_back((uint32_t)t);
+  if (b.n_eng_txns == 0) {
+    b.eng = EngineArgs{};
+    b.eng_part.clear();
+  }
+}
+
+// Uploads the engine's transaction order planned at submission (nothing
+// without engine rows).
+static hipError_t upload_engine_plan(cc_ctx *c, Batch &b) {
+  if (b.n_eng_txns == 0) return hipSuccess;
+  hipError_t e = hipMalloc(&b.d_part, b.eng_part.size() * sizeof(uint32_t));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b.d_part, b.eng_part.data(), b.eng_part.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                       c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  b.eng_part = std::vector<uint32_t>();
+  return e;
+}
+
 // The batch's most written rows, counted at submission from its packed
 // descriptors: write accesses (row groups that write) per global row; the
 // most written row, and every row written at least a quarter as often, at
 // most HOT_MAX of them, most written first (ties: lower row first).
-void find_hot_rows(const DevOp *dops, uint64_t n_ops, uint64_t total_rows, Batch &b) {
+//
+// With them, the OCC hot-row engine's plan (hot_engine.h): its rows are the
+// most written rows, at most ENG_MAX, each written at least
+// max(2, n_txns / 4096) times, of at most ENG_FIELDS fields and ENG_VALS
+// cells in all, most written first; its transactions are those that write
+// one of them, listed first in eng_part (in batch order), the others after
+// them.  eng_gain holds when every row left out is written at most a quarter
+// as often as the most written row: otherwise the rest of the batch is about
+// as contended as the engine's share, and the engine's serial pass gains
+// nothing.
+void find_hot_rows(const DevOp *dops, uint64_t n_ops, const DevTxn *dtx, uint64_t n_txns,
+                   const std::vector<Table> &tables, uint64_t total_rows, Batch &b) {
   std::vector<uint32_t> cnt(std::max<uint64_t>(total_rows, 1), 0u);
   for (uint64_t i = 0; i < n_ops; ++i) {
     const uint32_t rk = dops[i].rowk;
     if (!(rk & FOLLOWER_BIT) && (rk & WRITTEN_BIT)) ++cnt[rk & ROW_MASK];
   }
+  if (b.scheme == CC_OCC) plan_engine(dops, dtx, n_txns, tables, cnt, b);
   uint32_t top = 0;
   for (uint32_t c : cnt) top = std::max(top, c);
   b.hot_known = true;
@@ -750,7 +855,7 @@ cc_status check_run_params(cc_ctx *c, int scheme, const cc_run_params &p) {
   if (p.waves_per_wg > 16) return fail(c, CC_E_INVAL, "waves_per_wg must be 1..16");
   if (p.flags & ~(CC_RUN_STRICT_FENCES | CC_RUN_EAGER_INSTALL | CC_RUN_WAIT_UNLOCK | CC_RUN_PRECHECK |
                   CC_RUN_NO_PRECHECK | CC_RUN_INDEX_TREE | CC_RUN_LATCH | CC_RUN_SHARED_READS | CC_RUN_HOT_LAST |
-                  CC_RUN_NO_HOT_LAST | CC_RUN_WAIT_BLOCKER))
+                  CC_RUN_NO_HOT_LAST | CC_RUN_WAIT_BLOCKER | CC_RUN_HOT_ENGINE | CC_RUN_NO_HOT_ENGINE))
     return fail(c, CC_E_INVAL, "unknown run flag");
   if ((p.flags & CC_RUN_SHARED_READS) && scheme != CC_GACCO)
     return fail(c, CC_E_INVAL, "CC_RUN_SHARED_READS is a CC_GACCO option");
@@ -789,6 +894,13 @@ cc_status check_run_params(cc_ctx *c, int scheme, const cc_run_params &p) {
   if ((p.flags & hot) && scheme != CC_OCC) return fail(c, CC_E_INVAL, "CC_RUN_HOT_LAST is a CC_OCC option");
   if ((p.flags & CC_RUN_WAIT_BLOCKER) && scheme != CC_OCC && scheme != CC_TICTOC)
     return fail(c, CC_E_INVAL, "CC_RUN_WAIT_BLOCKER is a CC_OCC and CC_TICTOC option");
+  const uint32_t eng = CC_RUN_HOT_ENGINE | CC_RUN_NO_HOT_ENGINE;
+  if ((p.flags & eng) == eng) return fail(c, CC_E_INVAL, "CC_RUN_HOT_ENGINE and CC_RUN_NO_HOT_ENGINE exclude each other");
+  if ((p.flags & eng) && scheme != CC_OCC) return fail(c, CC_E_INVAL, "CC_RUN_HOT_ENGINE is a CC_OCC option");
+  if ((p.flags & CC_RUN_HOT_ENGINE) && p.mode != CC_MODE_PLAIN)
+    return fail(c, CC_E_INVAL, "CC_RUN_HOT_ENGINE runs in CC_MODE_PLAIN only");
+  if ((p.flags & CC_RUN_HOT_ENGINE) && (p.flags & CC_RUN_LATCH))
+    return fail(c, CC_E_INVAL, "CC_RUN_HOT_ENGINE does not take CC_RUN_LATCH");
   return CC_OK;
 }
 
@@ -964,11 +1076,20 @@ static cc_status submit_impl(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, con
     if (!b.keyed) {
       // the packed descriptors come back once, to count the rows' writes
       std::vector<DevOp> hd(n_ops);
+      std::vector<DevTxn> ht(n_txns);
       if (n_ops && (e = hipMemcpy(hd.data(), b.d_ops, n_ops * sizeof(DevOp), hipMemcpyDeviceToHost)) != hipSuccess) {
         free_batch(b);
         return hip_fail(c, e, "batch descriptors");
       }
-      find_hot_rows(hd.data(), n_ops, c->total_rows, b);
+      if (n_txns && (e = hipMemcpy(ht.data(), b.d_txns, n_txns * sizeof(DevTxn), hipMemcpyDeviceToHost)) != hipSuccess) {
+        free_batch(b);
+        return hip_fail(c, e, "batch descriptors");
+      }
+      find_hot_rows(hd.data(), n_ops, ht.data(), n_txns, c->tables, c->total_rows, b);
+      if ((e = upload_engine_plan(c, b)) != hipSuccess) {
+        free_batch(b);
+        return hip_fail(c, e, "engine plan upload");
+      }
     }
     const uint64_t id = c->next_batch++;
     c->batches[id] = b;
@@ -1007,7 +1128,7 @@ static cc_status submit_impl(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, con
   b.has_slot = has_slot;
   b.keyed = keyed;
   // keyed ops learn their rows only when the index is searched, at the run
-  if (!keyed) find_hot_rows(dops.data(), n_ops, c->total_rows, b);
+  if (!keyed) find_hot_rows(dops.data(), n_ops, dtx.data(), n_txns, c->tables, c->total_rows, b);
   hipError_t e = alloc_batch(b, scheme, keyed);
   if (e != hipSuccess) return hip_fail(c, e, "batch allocation");
   auto copy_in = [&]() -> hipError_t {
@@ -1025,7 +1146,7 @@ static cc_status submit_impl(cc_ctx *c, const cc_txn *txns, uint64_t n_txns, con
     if (r == hipSuccess) r = hipStreamSynchronize(c->stream);
     return r;
   };
-  if ((e = copy_in()) != hipSuccess) {
+  if ((e = copy_in()) != hipSuccess || (e = upload_engine_plan(c, b)) != hipSuccess) {
     free_batch(b);
     return hip_fail(c, e, "batch upload");
   }
@@ -1185,6 +1306,13 @@ static cc_status run_batch(cc_ctx *c, Batch &b, const cc_run_params &p, bool hos
     }
   }
   if (wpw == 0) wpw = 1;
+  // the hot-row engine has variants up to 4 ops per lane; unless the caller
+  // chose, it runs one transaction per wavefront (64 lanes): its waiting teams
+  // then poll without waiting for other teams' round trips
+  const uint32_t eng_lanes = p.lanes_per_txn ? lanes : 64;
+  const bool eng_fits = (b.max_ops + eng_lanes - 1) / eng_lanes <= 4;
+  if ((p.flags & CC_RUN_HOT_ENGINE) && !eng_fits)
+    return fail(c, CC_E_INVAL, "CC_RUN_HOT_ENGINE needs at most 4 ops per lane");
   if (!activate(c)) return fail(c, CC_E_HIP, "hipSetDevice failed");
   if (b.scheme == CC_GACCO) return run_gacco(c, b, p, lanes, wpw);
   if (b.scheme == CC_GPUTX) return run_gputx(c, b, p, lanes, wpw);
@@ -1275,7 +1403,8 @@ static cc_status run_batch(cc_ctx *c, Batch &b, const cc_run_params &p, bool hos
     if (st) return st;
   }
   Ctl h{};
-  double kernel_ms = 0;
+  double kernel_ms = 0, engine_ms = 0;
+  uint64_t engine_txns = 0;
   uint32_t passes = 0, epochs = 0;
   int first_grid = 0;
   bool epoch_limit = false;
@@ -1399,8 +1528,39 @@ static cc_status run_batch(cc_ctx *c, Batch &b, const cc_run_params &p, bool hos
       done_before = done;
     }
   } else if (b.n_txns) {
-    cc_status st = plain_passes((int)p.grid, wpw, true);
-    if (st) return st;
+    // OCC's hot-row engine: the transactions that write the batch's engine
+    // rows run first, alone, in one workgroup; the rest then run as usual
+    // (plain mode only: serving also passes here, and the engine knows no arrivals)
+    const bool use_eng = b.scheme == CC_OCC && p.mode == CC_MODE_PLAIN && !latch && eng_fits && b.n_eng_txns &&
+                         b.d_part &&
+                         ((p.flags & CC_RUN_HOT_ENGINE) ||
+                          (!(p.flags & CC_RUN_NO_HOT_ENGINE) && !no_hot_row && b.eng_gain));
+    if (use_eng) {
+      EngineArgs e = b.eng;
+      e.list = b.d_part;
+      e.n_txns = b.n_eng_txns;
+      a.defer_after = 0;
+      HIP_OR(c, hipEventRecord(c->ev[1], c->stream));
+      int threads = 0;
+      // one workgroup: as many wavefronts as the variant allows, unless the caller chose
+      const hipError_t er =
+          launch_engine_occ(c->stream, (int)eng_lanes, (int)b.max_ops, (int)p.waves_per_wg, strict, a, e, &threads);
+      if (er != hipSuccess) return launch_error(c, er);
+      HIP_OR(c, hipEventRecord(c->ev[2], c->stream));
+      HIP_OR(c, hipStreamSynchronize(c->stream));
+      float ms = 0;
+      HIP_OR(c, hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
+      kernel_ms += ms;
+      engine_ms = ms;
+      engine_txns = b.n_eng_txns;
+      ++passes;
+      a.list = b.d_part + b.n_eng_txns;
+      a.n_txns = b.n_txns - b.n_eng_txns;
+    }
+    if (a.n_txns) {
+      cc_status st = plain_passes((int)p.grid, wpw, true);
+      if (st) return st;
+    }
   }
   HIP_OR(c, hipEventRecord(c->ev[3], c->stream));
   HIP_OR(c, hipStreamSynchronize(c->stream));
@@ -1418,6 +1578,10 @@ static cc_status run_batch(cc_ctx *c, Batch &b, const cc_run_params &p, bool hos
   b.stats[CC_STAT_MAX_ATTEMPTS] = h.stats[DS_MAX_ATTEMPTS];
   b.stats[CC_STAT_PASSES] = passes;
   b.stats[CC_STAT_DEFERRED] = h.stats[DS_DEFERRED];
+  b.stats[CC_STAT_ENGINE_TXNS] = engine_txns;
+  b.stats[CC_STAT_ENGINE_ROWS] = engine_txns ? b.eng.n_rows : 0;
+  b.stats[CC_STAT_ENGINE_NS] = (uint64_t)(engine_ms * 1e6);
+  b.stats[CC_STAT_ENGINE_WAITS] = h.stats[DS_ENGINE_WAITS];
   b.stats[CC_STAT_GRID] = (uint64_t)first_grid;
   b.stats[CC_STAT_EPOCHS] = epochs;
   const double ns_per_tick = 1e6 / (double)c->wallclock_khz;

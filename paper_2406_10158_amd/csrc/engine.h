@@ -69,7 +69,8 @@ enum DevStat {
   DS_HOT_HOLD = 21,     //   ticks the row was held, summed over acquisitions
   DS_BLOCKED_WAITS = 22,// CC_RUN_WAIT_BLOCKER: waits for a held row entered
   DS_VERSION_MISS = 23, // MVCC: old-version reads that found their version's slot reused (attempt aborted)
-  DS_N = 24
+  DS_ENGINE_WAITS = 24, // OCC hot-row engine: times a team kept its locks and waited for an engine row
+  DS_N = 25
 };
 
 struct Ctl {
@@ -151,6 +152,23 @@ struct IndexDesc {
   uint64_t elem_base;    // the table's first cell
   uint32_t n_fields;
   uint32_t levels;       // tree levels above level 0
+};
+
+// OCC hot-row engine (hot_engine.h): the batch's most written rows, held in
+// one workgroup's LDS while the transactions that write them run there.
+// Rows of at most ENG_FIELDS fields, ENG_VALS cells in all.
+constexpr int ENG_MAX = 32;
+constexpr int ENG_FIELDS = 64;
+constexpr int ENG_VALS = 1024;
+struct EngineArgs {
+  const uint32_t *list;       // the engine's transactions
+  uint64_t n_txns;
+  uint32_t n_rows;            // engine rows (0: no engine)
+  uint32_t n_vals;            // their cells
+  uint32_t row[ENG_MAX];      // global row of engine row i
+  uint32_t elem0[ENG_MAX];    // its first cell in the value arena
+  uint32_t off[ENG_MAX + 1];  // its first cell in LDS; off[n_rows] = n_vals
+  uint32_t pad[2];
 };
 
 // Per-op metadata of a keyed batch: bit 31 keyed, bits 16-23 table, 0-7 field.
@@ -294,6 +312,13 @@ hipError_t launch_compact(hipStream_t s, const DevOutcome *out, uint64_t n_txns,
 // (lanes, ops-per-lane) combination.
 hipError_t launch_txn(hipStream_t s, int scheme, int lanes, int max_ops, int waves_per_wg, int grid,
                       bool strict, bool latch, const RunArgs &a, int n_cu, int *grid_used);
+
+// The OCC hot-row engine over e.list (txn_occ.hip): one workgroup of `waves`
+// wavefronts (0: the largest size the (lanes, ops-per-lane) variant allows);
+// hipErrorInvalidValue for a combination it has no variant for (more than 4
+// ops per lane).
+hipError_t launch_engine_occ(hipStream_t s, int lanes, int max_ops, int waves, bool strict, const RunArgs &a,
+                             const EngineArgs &e, int *threads_used);
 
 // Per-scheme launchers (txn_<scheme>.hip).
 #define CCE_DECLARE_LAUNCH(NAME)                                                                    \

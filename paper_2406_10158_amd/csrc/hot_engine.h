@@ -1,0 +1,508 @@
+// The OCC hot-row engine: the transactions of a batch that write one of its
+// most written rows run first, in one workgroup that keeps those rows -- their
+// locks, last writers' tickets and values -- in LDS.  The rest of the batch
+// then runs in the transaction kernel, where the engine rows are only read.
+//
+// Why: under skew the batch is serialised on its hottest rows, and on gfx950
+// every agent-scope access to a row's word is a round trip to the coherent
+// level (about half a microsecond, wherever the wavefronts sit).  OCC holds a
+// written row for its ticket, validation and install rounds, and contenders
+// that failed on it back off at random, so the row is idle between holders.
+// In LDS a lock, a ticket and an install take tens of nanoseconds, and
+// contenders can wait for the row instead of backing off.
+//
+// Protocol (OCC, paper Section 2 "Optimistic Concurrency Control" and Section
+// 3.5 "OCC", with the engine rows locked pessimistically -- the hot-record
+// locking of mostly-optimistic concurrency control):
+//   R1   cold rows exactly as OCC: lock written rows (fetch_or on the word,
+//        no wait), load the words of read-only rows; a held row aborts the
+//        attempt.  Then the cold values, under the locks / after the words.
+//   R1b  engine rows in decreasing engine index, so the most written row
+//        (index 0) comes last: a written row takes its LDS lock exclusively,
+//        a read-only row shares it.  At the first row that is not free the
+//        team gives back every row it took -- engine and cold -- and waits,
+//        holding nothing, until that row is free (one LDS load per loop
+//        iteration); then it makes a new attempt.  No one waits while holding
+//        a row, and a team that holds all of its rows never waits, so every
+//        wait ends.
+//   R2   the engine rows' values and the ticket, from an LDS counter that
+//        starts from the run's ticket counter (the engine runs alone, before
+//        the rest of the batch, so its tickets order only its transactions,
+//        and the rest draw later ones).  Read-only engine rows are released
+//        here: a read under a shared lock is ordered by the ticket drawn
+//        while holding it.
+//   R3   validation of the cold read-only rows (word unchanged) and of every
+//        cold word's ticket (older than ours).
+//   R4   engine rows: new values and the ticket into LDS, then the lock
+//        released; cold rows: values stored, waited for, then the word set
+//        to the ticket (publish + unlock), or restored on failure.
+// Serial key (0, ticket), as OCC.  At the end the engine rows' words (their
+// last writer's ticket, unlocked) and values go back to the table, and the
+// LDS ticket counter to the run's.
+#pragma once
+
+#include "schemes.h"
+
+namespace cce {
+
+constexpr uint32_t ENG_WRITER = 1u << 31;  // LDS lock: writer bit; bits 0-30 count readers
+static_assert((ENG_MAX & (ENG_MAX - 1)) == 0 && ENG_MAX <= 32, "engine rows: a power of two, one bit each");
+
+// Engine index of `row` (-1: not an engine row) and, for an engine row, the
+// LDS index of its cell `elem`.  The loop is unrolled so that every e.*[i]
+// is a scalar operand: indexed by a lane's value, the kernel arguments would
+// be read from memory.
+__device__ __forceinline__ int eng_index(const EngineArgs &e, uint32_t row, uint32_t elem, uint32_t *cell) {
+  int r = -1;
+  uint32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < ENG_MAX; ++i) {
+    const bool hit = (uint32_t)i < e.n_rows && e.row[i] == row;
+    r = hit ? i : r;
+    c = hit ? e.off[i] + (elem - e.elem0[i]) : c;
+  }
+  *cell = c;
+  return r;
+}
+
+__device__ __forceinline__ void lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+
+// One attempt of a team (every lane of the wavefront calls it).  WAITING:
+// an engine row was taken (*wait_j: which, and ENG_WRITER if to write it);
+// the attempt gave back everything it held.
+template <int L, int K, bool STRICT>
+__device__ __forceinline__ int engine_attempt(const Team<L> &t, Slots<K> &s, const int (&ei)[K],
+                                              const uint32_t (&cell)[K], uint32_t emask, bool active,
+                                              const RunArgs &a, const EngineArgs &e, uint32_t *lk, uint64_t *tid,
+                                              int64_t *val, uint64_t *ticket_ctr, uint64_t *hot_t0,
+                                              uint64_t *hot_dt, uint32_t *wait_j, uint64_t *key) {
+  bool fail = false;
+  uint32_t blk = ~0u;
+  bool lock_fail = false;
+  {
+    // R1: the cold rows
+    bool issued[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      s.got[k] = false;
+      issued[k] = active && s.valid[k] && op_leader(s.rowk[k]) && ei[k] < 0;
+      if (issued[k]) {
+        uint64_t *w = a.words + op_row(s.rowk[k]);
+        s.v[k] = op_written(s.rowk[k]) ? or_word(w, OCC_LOCK) : ld_word(w);
+      }
+    }
+    order_point<STRICT>();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (!issued[k]) continue;
+      const uint64_t o = s.v[k];
+      if ((o & OCC_LOCK) && blk == ~0u) blk = op_row(s.rowk[k]);
+      if (op_written(s.rowk[k])) s.got[k] = !(o & OCC_LOCK);
+      fail |= (o & OCC_LOCK) != 0;
+    }
+    lock_fail = t.any(fail);
+    if (active && lock_fail) {
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (s.got[k]) st_word(a.words + op_row(s.rowk[k]), s.v[k]);
+    }
+    // the cold values: under the locks, after the read-only rows' words
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (active && !lock_fail && s.valid[k] && ei[k] < 0) s.x[k] = ld_val(a.data + s.elem[k]);
+  }
+  s.block = blocking_row(t, blk);
+
+  // R1b: the engine rows, in decreasing engine index
+  const bool go = active && !lock_fail;
+  const uint32_t need = go ? emask : 0u;  // team-uniform
+  uint32_t held = 0;                      // team-uniform: engine rows taken
+  bool stop = false;                                  // team-uniform: a row was not free
+  uint64_t wneed = 0;
+  {
+    // rows any team of the wavefront still needs (every lane of a team has `need`)
+    uint32_t m = need;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m |= (uint32_t)__shfl_xor((int)m, o, 64);
+    wneed = m;
+  }
+  while (wneed) {
+    const int j = 63 - __clzll((unsigned long long)wneed);  // wavefront-uniform
+    wneed &= ~(1ull << j);
+    const bool want = go && !stop && ((need >> j) & 1u);  // team-uniform
+    bool tried = false, ok = true, wr = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (want && s.valid[k] && op_leader(s.rowk[k]) && ei[k] == j) {
+        tried = true;
+        wr = op_written(s.rowk[k]);
+        if (wr) {
+          uint32_t expect = 0;
+          ok = __hip_atomic_compare_exchange_strong(lk + j, &expect, ENG_WRITER, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+          const uint32_t old = __hip_atomic_fetch_add(lk + j, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (old & ENG_WRITER) {
+            (void)__hip_atomic_fetch_sub(lk + j, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            ok = false;
+          }
+        }
+      }
+    }
+    const bool team_fail = t.any(tried && !ok);
+    const bool team_wr = t.any(tried && wr);
+    if (want) {
+      if (team_fail) {
+        stop = true;
+        *wait_j = (uint32_t)j | (team_wr ? ENG_WRITER : 0u);  // the row waited for, and how
+      } else {
+        held |= 1u << j;
+      }
+    }
+  }
+  lds_fence();  // the locks are taken before anything below reads the rows
+  // a team that stopped gives back everything it took: no one waits holding a row
+  if (go && stop) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (s.valid[k] && op_leader(s.rowk[k]) && ei[k] >= 0 && ((held >> ei[k]) & 1u)) {
+        if (op_written(s.rowk[k]))
+          (void)__hip_atomic_fetch_and(lk + ei[k], ~ENG_WRITER, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+          (void)__hip_atomic_fetch_sub(lk + ei[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      if (s.got[k]) st_word(a.words + op_row(s.rowk[k]), s.v[k]);
+    }
+    held = 0;
+  }
+  // hold statistics of engine row 0 (the batch's most written row), in the
+  // lane that writes it: from its lock to its release
+  bool w0 = false;
+#pragma unroll
+  for (int k = 0; k < K; ++k) w0 |= s.valid[k] && op_leader(s.rowk[k]) && op_written(s.rowk[k]) && ei[k] == 0;
+  if (w0 && go && !stop && (held & 1u)) *hot_t0 = wall_clock64();
+  const bool alive = go && !stop;
+  // the engine rows' holders issue first on their SIMD until they release them:
+  // the waves polling for those rows share it
+  if (ballot(alive)) __builtin_amdgcn_s_setprio(3);
+
+  // R2: engine values, the ticket, read-only engine rows released
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (alive && s.valid[k] && ei[k] >= 0) s.x[k] = val[cell[k]];
+  uint64_t ticket = 0;
+  {
+    const uint64_t m = ballot(alive && t.tl == 0);
+    if (m) {
+      const int first = __ffsll((unsigned long long)m) - 1;
+      uint64_t base = 0;
+      if (t.lane == first)
+        base = __hip_atomic_fetch_add(ticket_ctr, (uint64_t)__popcll(m), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+      base = readlane64(base, first);
+      ticket = base + 1 + (uint64_t)__popcll(m & ((1ull << t.tb) - 1ull));
+    }
+  }
+  lds_fence();  // the ticket is drawn before the releases and validation loads below
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (alive && s.valid[k] && op_leader(s.rowk[k]) && ei[k] >= 0 && !op_written(s.rowk[k]))
+      (void)__hip_atomic_fetch_sub(lk + ei[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+
+  // R3: validation of the cold rows
+  bool bad = false, vload = false;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (alive && s.valid[k] && op_leader(s.rowk[k]) && ei[k] < 0) {
+      if (!op_written(s.rowk[k])) {
+        bad |= ld_word(a.words + op_row(s.rowk[k])) != s.v[k];
+        vload = true;
+      }
+      bad |= (s.v[k] & ~OCC_LOCK) >= ticket;
+    }
+  }
+  if (ballot(vload)) order_point<STRICT>();
+  const bool valid_fail = t.any(bad);
+  const bool commit = alive && !valid_fail;
+
+  // R4: new values (WRITE_SLOT sources move between lanes: every lane takes part)
+  int64_t nv[K];
+  {
+    int64_t src_val[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      uint32_t src = (a.has_slot && s.valid[k] && op_kind(s.rowk[k]) == CC_WRITE_SLOT) ? (uint32_t)(s.arg[k] & 0xFF) : 0u;
+      src_val[k] = a.has_slot ? slot_source<L, K>(t, s, src) : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) nv[k] = apply_op(op_kind(s.rowk[k]), s.x[k], s.arg[k], src_val[k]);
+  }
+  // engine rows first: their install and release wait for nothing global
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (commit && s.valid[k] && op_kind(s.rowk[k]) != CC_READ && ei[k] >= 0) val[cell[k]] = nv[k];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (alive && s.valid[k] && op_leader(s.rowk[k]) && op_written(s.rowk[k]) && ei[k] >= 0 && commit) tid[ei[k]] = ticket;
+  lds_fence();  // values and tickets are in LDS before the locks are free
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (alive && s.valid[k] && op_leader(s.rowk[k]) && op_written(s.rowk[k]) && ei[k] >= 0)
+      (void)__hip_atomic_fetch_and(lk + ei[k], ~ENG_WRITER, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __builtin_amdgcn_s_setprio(0);
+  if (alive && *hot_t0) *hot_dt = wall_clock64() - *hot_t0;
+  // cold rows: values, wait, words
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (commit && s.valid[k] && op_kind(s.rowk[k]) != CC_READ && ei[k] < 0) st_val(a.data + s.elem[k], nv[k]);
+  if (ballot(commit)) order_point<STRICT>();
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (alive && s.got[k]) st_word(a.words + op_row(s.rowk[k]), commit ? ticket : s.v[k]);
+  *key = ticket;
+  if (!active) return COMMIT;
+  if (lock_fail) return ABORT_LOCK;
+  if (stop) return WAITING;
+  return valid_fail ? ABORT_VALID : COMMIT;
+}
+
+template <int L, int K, bool STRICT>
+__global__ void __launch_bounds__(MaxThreads<K>::value) engine_kernel(RunArgs a, EngineArgs e) {
+  __shared__ uint32_t lk[ENG_MAX];
+  __shared__ uint64_t tid[ENG_MAX];
+  __shared__ int64_t val[ENG_VALS];
+  __shared__ uint64_t ticket_ctr;
+  __shared__ uint32_t queue_ctr;
+  const uint32_t me = threadIdx.x, nthr = blockDim.x;
+  // the engine rows come into LDS
+  for (uint32_t i = me; i < e.n_rows; i += nthr) {
+    lk[i] = 0;
+    tid[i] = ld_word(a.words + e.row[i]) & ~OCC_LOCK;
+  }
+  for (uint32_t v = me; v < e.n_vals; v += nthr) {
+    uint32_t i = 0;
+    while (i + 1 < e.n_rows && e.off[i + 1] <= v) ++i;
+    val[v] = ld_val(a.data + e.elem0[i] + (v - e.off[i]));
+  }
+  if (me == 0) {
+    ticket_ctr = ld_word(&a.ctl->ticket);
+    queue_ctr = 0;
+  }
+  __syncthreads();
+
+  Team<L> t;
+  Slots<K> s;
+  int ei[K];
+  uint32_t cell[K];       // an engine op's cell in LDS
+  uint32_t emask = 0;     // team-uniform: engine rows the transaction touches
+  const uint64_t start_clock = a.ctl->start_clock;
+  int64_t txn = -1;
+  uint32_t first = 0, n = 0;  // the transaction's ops, read once when it is claimed
+  uint32_t attempts = 0;
+  uint64_t ready_at = 0;
+  uint32_t wait_j = 0;    // team-uniform: the engine row a waiting team stopped at (ENG_WRITER: to write it)
+  bool done = false;
+  bool staged = false;    // the transaction's ops are in the slots
+  bool waiting = false;   // the team waits, holding nothing, for engine row wait_j
+  uint64_t n_commit = 0, n_att = 0, n_lock = 0, n_valid = 0, n_gave = 0, max_att = 0, n_waits = 0;
+  uint64_t t_useful = 0, t_abort = 0, t_wait = 0;
+  uint64_t n_hot_acq = 0, n_hot_fail = 0, t_hot = 0;
+  uint64_t hot_t0 = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    ei[k] = -1;
+    cell[k] = 0;
+  }
+
+  for (;;) {
+    const bool need = txn < 0 && !done;
+    uint32_t q = 0;
+    {
+      const uint64_t m = ballot(need && t.tl == 0);
+      if (m) {
+        const int first = __ffsll((unsigned long long)m) - 1;
+        uint32_t base = 0;
+        if (t.lane == first)
+          base = __hip_atomic_fetch_add(&queue_ctr, (uint32_t)__popcll(m), __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+        base = (uint32_t)__builtin_amdgcn_readlane((int)base, first);
+        q = base + (uint32_t)__popcll(m & ((1ull << t.tb) - 1ull));
+      }
+    }
+    if (need) {
+      if (q < e.n_txns) {
+        txn = (int64_t)e.list[q];
+        const DevTxn d = a.txns[txn];
+        first = d.first;
+        n = d.n;
+        attempts = 0;
+        ready_at = 0;
+        staged = false;
+        waiting = false;
+      } else {
+        done = true;
+      }
+    }
+    if (ballot(txn >= 0) == 0) break;
+    const uint64_t now = wall_clock64();
+    bool active = txn >= 0 && now >= ready_at;
+    if (active && waiting) {
+      // a waiting team looks only at the row it waits for, and tries again once that row is free
+      const uint32_t w = __hip_atomic_load(lk + (wait_j & (ENG_MAX - 1)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      active = (wait_j & ENG_WRITER) ? w == 0 : !(w & ENG_WRITER);
+    }
+    if (ballot(active) == 0) {
+      __builtin_amdgcn_s_sleep(1);
+      if (txn >= 0 && t.tl == 0) t_wait += wall_clock64() - now;
+      continue;
+    }
+    if (txn >= 0 && !staged) {
+      // the transaction's ops, once per transaction (team-uniform)
+      uint32_t m = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const uint32_t idx = (uint32_t)t.tl + (uint32_t)(k * L);
+        s.valid[k] = idx < n;
+        s.oi[k] = first + idx;
+        if (s.valid[k]) {
+          const DevOp op = a.ops[first + idx];
+          s.rowk[k] = op.rowk;
+          s.elem[k] = op.elem;
+          s.arg[k] = op.arg;
+        } else {
+          s.rowk[k] = FOLLOWER_BIT;
+          s.elem[k] = 0;
+          s.arg[k] = 0;
+        }
+        s.x[k] = 0;
+        s.v[k] = 0;
+        ei[k] = s.valid[k] ? eng_index(e, op_row(s.rowk[k]), s.elem[k], &cell[k]) : -1;
+        if (ei[k] >= 0 && op_leader(s.rowk[k])) m |= 1u << ei[k];
+      }
+      // OR over the team's lanes
+#pragma unroll
+      for (int o = 1; o < L; o <<= 1) m |= (uint32_t)__shfl_xor((int)m, o, 64);
+      emask = m;
+      staged = true;
+    }
+    uint64_t key = 0, hot_dt = 0;
+    const int r = engine_attempt<L, K, STRICT>(t, s, ei, cell, emask, active, a, e, lk, tid, val, &ticket_ctr,
+                                               &hot_t0, &hot_dt, &wait_j, &key);
+    if (t.tl == 0 && txn >= 0) {
+      const uint64_t dt = wall_clock64() - now;
+      if (!active || r == WAITING) t_wait += dt;
+      else if (r == COMMIT) t_useful += dt;
+      else t_abort += dt;
+    }
+    if (active && r != WAITING && hot_t0) {
+      // this lane held the most written row in the attempt that just ended
+      ++n_hot_acq;
+      n_hot_fail += r != COMMIT;
+      t_hot += hot_dt;
+      hot_t0 = 0;
+    }
+    if (active && r == WAITING) {
+      waiting = true;
+      if (t.tl == 0) ++n_waits;
+      ready_at = now;
+    } else if (active) {
+      waiting = false;
+      ++attempts;
+      ++n_att;
+      if (r == COMMIT) {
+        if (t.tl == 0) {
+          DevOutcome o;
+          o.status = CC_COMMITTED;
+          o.attempts = attempts;
+          o.serial_hi = 0;
+          o.serial_lo = key;
+          const uint64_t dt = wall_clock64() - start_clock;
+          o.commit_ns = (int64_t)((dt * a.ns_per_tick_q16) >> 16);
+          a.out[txn] = o;
+          ++n_commit;
+          max_att = attempts > max_att ? attempts : max_att;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+          if (s.valid[k]) __builtin_nontemporal_store(s.x[k], a.reads + first + t.tl + k * L);
+        txn = -1;
+      } else {
+        if (t.tl == 0) {
+          if (r == ABORT_LOCK) ++n_lock;
+          else ++n_valid;
+        }
+        if (attempts >= a.max_attempts) {
+          if (t.tl == 0) {
+            a.out[txn].attempts = attempts;
+            ++n_gave;
+            max_att = attempts > max_att ? attempts : max_att;
+          }
+          txn = -1;
+        } else {
+          const uint32_t sh = attempts < 12 ? attempts : 12;
+          const uint64_t span = (uint64_t)a.backoff_ticks << sh;
+          ready_at = now + (mix64(((uint64_t)txn << 20) ^ attempts) % (span + 1));
+        }
+      }
+    }
+  }
+
+  // the engine rows and the ticket counter go back
+  __syncthreads();
+  for (uint32_t i = me; i < e.n_rows; i += nthr) st_word(a.words + e.row[i], tid[i]);
+  for (uint32_t v = me; v < e.n_vals; v += nthr) {
+    uint32_t i = 0;
+    while (i + 1 < e.n_rows && e.off[i + 1] <= v) ++i;
+    st_val(a.data + e.elem0[i] + (v - e.off[i]), val[v]);
+  }
+  if (me == 0) st_word(&a.ctl->ticket, ticket_ctr);
+
+  n_att = t.tl == 0 ? n_att : 0;
+  const uint64_t c0 = wave_sum(n_commit), c1 = wave_sum(n_att), c2 = wave_sum(n_lock), c3 = wave_sum(n_valid),
+                 c4 = wave_sum(n_gave), c5 = wave_max(max_att), c8 = wave_sum(t_useful), c9 = wave_sum(t_abort),
+                 c10 = wave_sum(t_wait), c13 = wave_sum(n_waits), c14 = wave_sum(n_hot_acq),
+                 c15 = wave_sum(n_hot_fail), c16 = wave_sum(t_hot);
+  if (t.lane == 0) {
+    if (c0) atomicAdd((unsigned long long *)&a.ctl->stats[DS_COMMITTED], (unsigned long long)c0);
+    if (c1) atomicAdd((unsigned long long *)&a.ctl->stats[DS_ATTEMPTS], (unsigned long long)c1);
+    if (c2) atomicAdd((unsigned long long *)&a.ctl->stats[DS_ABORT_LOCK], (unsigned long long)c2);
+    if (c3) atomicAdd((unsigned long long *)&a.ctl->stats[DS_ABORT_VALID], (unsigned long long)c3);
+    if (c4) atomicAdd((unsigned long long *)&a.ctl->stats[DS_GAVE_UP], (unsigned long long)c4);
+    if (c5) atomicMax((unsigned long long *)&a.ctl->stats[DS_MAX_ATTEMPTS], (unsigned long long)c5);
+    if (c8) atomicAdd((unsigned long long *)&a.ctl->stats[DS_T_USEFUL], (unsigned long long)c8);
+    if (c9) atomicAdd((unsigned long long *)&a.ctl->stats[DS_T_ABORT], (unsigned long long)c9);
+    if (c10) atomicAdd((unsigned long long *)&a.ctl->stats[DS_T_WAIT], (unsigned long long)c10);
+    if (c13) atomicAdd((unsigned long long *)&a.ctl->stats[DS_ENGINE_WAITS], (unsigned long long)c13);
+    if (c14) atomicAdd((unsigned long long *)&a.ctl->stats[DS_HOT_ACQ], (unsigned long long)c14);
+    if (c15) atomicAdd((unsigned long long *)&a.ctl->stats[DS_HOT_FAILED], (unsigned long long)c15);
+    if (c16) atomicAdd((unsigned long long *)&a.ctl->stats[DS_HOT_HOLD], (unsigned long long)c16);
+  }
+}
+
+template <int L, int K, bool STRICT>
+static hipError_t launch_engine_one(hipStream_t s, int waves, const RunArgs &a, const EngineArgs &e,
+                                    int *threads_used) {
+  int block = MaxThreads<K>::value;
+  if (waves > 0 && 64 * waves < block) block = 64 * waves;
+  *threads_used = block;
+  hipLaunchKernelGGL((engine_kernel<L, K, STRICT>), dim3(1), dim3(block), 0, s, a, e);
+  return hipGetLastError();
+}
+
+template <bool STRICT>
+static hipError_t engine_dispatch(hipStream_t s, int lanes, int max_ops, int waves, const RunArgs &a,
+                                  const EngineArgs &e, int *threads_used) {
+  const int need_k = (max_ops + lanes - 1) / lanes;
+#define CCE_ENG(LL, KK) \
+  if (lanes == LL && need_k <= KK) return launch_engine_one<LL, KK, STRICT>(s, waves, a, e, threads_used);
+  CCE_ENG(1, 4)
+  CCE_ENG(4, 4)
+  CCE_ENG(16, 1)
+  CCE_ENG(16, 4)
+  CCE_ENG(64, 1)
+  CCE_ENG(64, 4)
+#undef CCE_ENG
+  return hipErrorInvalidValue;
+}
+
+}  // namespace cce

@@ -220,6 +220,18 @@ def test_run_parameter_checks_without_a_device(b):
     assert ok(b.CC_OCC, P(flags=b.CC_RUN_HOT_LAST)) == b.CC_OK
     assert ok(b.CC_OCC, P(flags=b.CC_RUN_HOT_LAST | b.CC_RUN_NO_HOT_LAST)) == b.CC_E_INVAL
     assert ok(b.CC_TICTOC, P(flags=b.CC_RUN_HOT_LAST)) == b.CC_E_INVAL
+    # the hot-row engine: OCC, plain mode, no latches; its two flags exclude each other
+    assert ok(b.CC_OCC, P(flags=b.CC_RUN_HOT_ENGINE)) == b.CC_OK
+    assert ok(b.CC_OCC, P(flags=b.CC_RUN_NO_HOT_ENGINE)) == b.CC_OK
+    assert ok(b.CC_OCC, P(flags=b.CC_RUN_HOT_ENGINE | b.CC_RUN_NO_HOT_ENGINE)) == b.CC_E_INVAL
+    assert ok(b.CC_OCC, P(flags=b.CC_RUN_HOT_ENGINE | b.CC_RUN_LATCH)) == b.CC_E_INVAL
+    assert ok(b.CC_OCC, P(flags=b.CC_RUN_NO_HOT_ENGINE | b.CC_RUN_LATCH)) == b.CC_OK
+    for mode in (b.CC_MODE_EPOCH, b.CC_MODE_SERVE):
+        assert ok(b.CC_OCC, P(flags=b.CC_RUN_HOT_ENGINE, mode=mode)) == b.CC_E_INVAL
+        assert ok(b.CC_OCC, P(flags=b.CC_RUN_NO_HOT_ENGINE, mode=mode)) == b.CC_OK
+    for sch in (b.CC_2PL_NW, b.CC_2PL_WD, b.CC_TO, b.CC_MVCC, b.CC_TICTOC):
+        for f in (b.CC_RUN_HOT_ENGINE, b.CC_RUN_NO_HOT_ENGINE):
+            assert ok(sch, P(flags=f)) == b.CC_E_INVAL
     assert ok(b.CC_OCC) == b.CC_OK and ok(b.CC_OCC, P(flags=b.CC_RUN_PRECHECK | b.CC_RUN_STRICT_FENCES)) == b.CC_OK
     assert ok(b.CC_OCC, P(mode=7)) == b.CC_E_INVAL
     assert ok(b.CC_OCC, P(lanes_per_txn=8)) == b.CC_E_INVAL

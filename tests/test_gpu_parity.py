@@ -61,8 +61,10 @@ def test_grid_sizes(scheme):
 def test_single_team_is_serial_execution(scheme):
     # one workgroup of one wavefront with one 64-lane team: transactions run one at a time in id
     # order, so the result is the oracle's own serial execution, with no GPU input to the oracle
+    # (OCC without the hot-row engine, which runs the hottest rows' writers first)
     tabs, b = wl.kv_workload(n_rows=300, n_fields=3, n_txns=400, ops=(1, 40), theta=0.9, seed=3)
-    out, reads, final, st = run_batch(tabs, b, scheme, lanes_per_txn=64, waves_per_wg=1, grid=1)
+    f = binding().CC_RUN_NO_HOT_ENGINE if scheme == "occ" else 0
+    out, reads, final, st = run_batch(tabs, b, scheme, lanes_per_txn=64, waves_per_wg=1, grid=1, flags=f)
     assert "error" not in st
     exp_final, exp_reads = oracle.serial_execute(tabs, b)
     assert np.array_equal(reads, exp_reads)
@@ -112,7 +114,8 @@ def test_two_hot_rows_stress(scheme):
     b = wl.kv_batch(2, 1, n, ops=2, read_ratio=0.3, arg_range=(-5, 5), seed=6)
     tabs = [wl.kv_table(2, 1)]
     out, reads, final, st = run_and_check(tabs, b, scheme, lanes_per_txn=4)
-    assert st["attempts"] > n  # there was contention
+    # there was contention: aborts, or (OCC's hot-row engine) waits for a row
+    assert st["attempts"] > n or st["engine_waits"] > 0
 
 
 @pytest.mark.parametrize("scheme", IMPLEMENTED)
@@ -208,22 +211,21 @@ def test_wait_for_blocking_row(scheme, shape):
     print(f"[gpu] wait-for-blocker {scheme} L={lanes} waves={waves}", flush=True)
     tabs, b = wl.kv_workload(n_rows=20_000, n_fields=4, n_txns=20_000, ops=(1, 16) if lanes == 1 else 16,
                              theta=0.99, seed=47)
-    _, _, _, st = run_and_check(tabs, b, scheme, flags=b_.CC_RUN_WAIT_BLOCKER, lanes_per_txn=lanes,
-                                waves_per_wg=waves)
+    f = b_.CC_RUN_WAIT_BLOCKER | (b_.CC_RUN_NO_HOT_ENGINE if scheme == "occ" else 0)
+    _, _, _, st = run_and_check(tabs, b, scheme, flags=f, lanes_per_txn=lanes, waves_per_wg=waves)
     assert st["blocked_waits"] > 0
     # every transaction adds to both of two rows: the pairs that block each other
     b2 = wl.kv_batch(2, 1, 5_000, ops=2, read_ratio=0.3, arg_range=(-5, 5), seed=48)
-    run_and_check([wl.kv_table(2, 1)], b2, scheme, flags=b_.CC_RUN_WAIT_BLOCKER, lanes_per_txn=max(lanes, 4),
-                  waves_per_wg=waves)
+    run_and_check([wl.kv_table(2, 1)], b2, scheme, flags=f, lanes_per_txn=max(lanes, 4), waves_per_wg=waves)
     if lanes >= 16:
         tabs, b = wl.order_entry_workload(1, 1_000, seed=49)
-        run_and_check(tabs, b, scheme, flags=b_.CC_RUN_WAIT_BLOCKER, lanes_per_txn=64, waves_per_wg=waves)
+        run_and_check(tabs, b, scheme, flags=f, lanes_per_txn=64, waves_per_wg=waves)
 
 
 @pytest.mark.parametrize("pre", [0, 1, 2])
 def test_wait_for_blocking_row_with_each_precheck_setting(pre):
     b_ = binding()
-    f = b_.CC_RUN_WAIT_BLOCKER | [b_.CC_RUN_NO_PRECHECK, 0, b_.CC_RUN_PRECHECK][pre]
+    f = b_.CC_RUN_WAIT_BLOCKER | [b_.CC_RUN_NO_PRECHECK, 0, b_.CC_RUN_PRECHECK][pre] | b_.CC_RUN_NO_HOT_ENGINE
     tabs, b = wl.kv_workload(n_rows=50_000, n_fields=4, n_txns=30_000, ops=16, theta=0.9, seed=50 + pre)
     run_and_check(tabs, b, "occ", flags=f)
     run_and_check(tabs, b, "occ", flags=f | b_.CC_RUN_STRICT_FENCES)
@@ -239,6 +241,8 @@ def test_precheck(scheme, theta, flags):
         pytest.skip("eager install is an OCC option")
     f = {"precheck": b_.CC_RUN_PRECHECK, "precheck+eager": b_.CC_RUN_PRECHECK | b_.CC_RUN_EAGER_INSTALL,
          "no-precheck": b_.CC_RUN_NO_PRECHECK, "precheck+latch": b_.CC_RUN_PRECHECK | b_.CC_RUN_LATCH}[flags]
+    if scheme == "occ":
+        f |= b_.CC_RUN_NO_HOT_ENGINE  # the rounds of the transaction kernel (the engine has no pre-check)
     tabs, b = wl.kv_workload(n_rows=20_000, n_fields=4, n_txns=20_000, ops=16, theta=theta, seed=37)
     run_and_check(tabs, b, scheme, flags=f)
     tabs, b = wl.order_entry_workload(1, 1_000, seed=38)
@@ -254,6 +258,7 @@ def test_occ_hot_rows_last(shape, hot, pre):
     b_ = binding()
     f = {"hot-last": b_.CC_RUN_HOT_LAST, "one-round": b_.CC_RUN_NO_HOT_LAST}[hot]
     f |= {"default": 0, "precheck": b_.CC_RUN_PRECHECK, "no-precheck": b_.CC_RUN_NO_PRECHECK}[pre]
+    f |= b_.CC_RUN_NO_HOT_ENGINE
     lanes, waves = shape
     if lanes == 1 and hot == "hot-last":
         pytest.skip("the split lock rounds faulted the GPU in the 1-lane, 16-slot kernel with no cause found in "
@@ -279,10 +284,11 @@ def test_occ_eager_install(theta):
     # values stored in the validation round and undone on abort; aborted
     # attempts release with a fresh TID
     b_ = binding()
+    f = b_.CC_RUN_EAGER_INSTALL | b_.CC_RUN_NO_HOT_ENGINE
     tabs, b = wl.kv_workload(n_rows=20_000, n_fields=4, n_txns=20_000, ops=16, theta=theta, seed=17)
-    run_and_check(tabs, b, "occ", flags=b_.CC_RUN_EAGER_INSTALL)
+    run_and_check(tabs, b, "occ", flags=f)
     tabs, b = wl.order_entry_workload(1, 1_000, seed=18)
-    run_and_check(tabs, b, "occ", flags=b_.CC_RUN_EAGER_INSTALL)
+    run_and_check(tabs, b, "occ", flags=f)
 
 
 @pytest.mark.parametrize("scheme", IMPLEMENTED)
@@ -307,7 +313,9 @@ def test_attempt_limit_reports_livelock_and_leaves_no_partial_writes(scheme):
     n = 4_000
     b = wl.kv_batch(2, 1, n, ops=2, read_ratio=0.0, seed=9)
     tabs = [wl.kv_table(2, 1)]
-    out, reads, final, st = run_batch(tabs, b, scheme, max_attempts=1, lanes_per_txn=4)
+    # (OCC without the hot-row engine, where conflicts on the two rows wait instead of aborting)
+    f = bb.CC_RUN_NO_HOT_ENGINE if scheme == "occ" else 0
+    out, reads, final, st = run_batch(tabs, b, scheme, max_attempts=1, lanes_per_txn=4, flags=f)
     assert isinstance(st.get("error"), bb.CCError) and st["error"].status == bb.CC_E_LIVELOCK
     committed = out["status"] == 1
     assert 0 < committed.sum() < n
@@ -323,6 +331,85 @@ def test_full_size_kv_config(scheme):
     tabs, b = wl.kv_workload(theta=0.9, seed=0)
     out, reads, final, st = run_and_check(tabs, b, scheme)
     print(f"full {scheme}: {b.n_txns / (st['run_ns'] * 1e-9):.3e} txn/s attempts={st['attempts']}")
+
+
+def test_full_size_kv_config_without_hot_engine():
+    # the headline configuration through OCC's transaction kernel alone
+    b_ = binding()
+    tabs, b = wl.kv_workload(theta=0.9, seed=0)
+    _, _, _, st = run_and_check(tabs, b, "occ", flags=b_.CC_RUN_NO_HOT_ENGINE)
+    assert st["engine_txns"] == 0
+
+
+def test_full_size_kv_config_runs_the_hot_engine_by_default():
+    tabs, b = wl.kv_workload(theta=0.9, seed=0)
+    _, _, _, st = run_and_check(tabs, b, "occ")
+    h = wl.hottest_row_writes(b)[1]
+    print(f"engine: {st['engine_txns']} txns, {st['engine_rows']} rows, {st['engine_ns'] / 1e6:.1f} ms of "
+          f"{st['run_ns'] / 1e6:.1f} ms; hot row {h} writes, {st['hot_acq']} holds")
+    assert st["engine_txns"] > 0 and st["engine_rows"] == 32
+    assert st["hot_acq"] - st["hot_failed"] == h
+
+
+@pytest.mark.parametrize("theta", [0.6, 0.9, 0.99])
+@pytest.mark.parametrize("shape", [(16, 0), (16, 1), (64, 0), (4, 0), (4, 2), (1, 0)])
+def test_hot_engine(shape, theta):
+    # the transactions that write the batch's most written rows run first in one workgroup that
+    # holds those rows in LDS (waiting for them, the most written last); the rest run as usual
+    b_ = binding()
+    lanes, waves = shape
+    print(f"[gpu] hot engine L={lanes} waves={waves} theta={theta}", flush=True)
+    tabs, b = wl.kv_workload(n_rows=20_000, n_fields=4, n_txns=20_000, ops=(1, 4) if lanes == 1 else 16,
+                             theta=theta, seed=61)
+    _, _, _, st = run_and_check(tabs, b, "occ", flags=b_.CC_RUN_HOT_ENGINE, lanes_per_txn=lanes, waves_per_wg=waves)
+    assert st["engine_txns"] > 0 and 0 < st["engine_rows"] <= 32
+    # every write of the most written row happens in the engine, one per held lock that committed
+    h = wl.hottest_row_writes(b)[1]
+    assert st["hot_acq"] - st["hot_failed"] == h
+    assert st["hot_hold_ns"] > 0
+    # the same with strict fences
+    run_and_check(tabs, b, "occ", flags=b_.CC_RUN_HOT_ENGINE | b_.CC_RUN_STRICT_FENCES, lanes_per_txn=lanes,
+                  waves_per_wg=waves)
+
+
+@pytest.mark.parametrize("waves", [0, 1, 4])
+def test_hot_engine_order_entry_and_tiny_tables(waves):
+    b_ = binding()
+    # order-entry at one and eight warehouses: slots, conditional adds, several ops per row
+    for w in (1, 8):
+        print(f"[gpu] hot engine order-entry W={w} waves={waves}", flush=True)
+        tabs, b = wl.order_entry_workload(w, 2_000, seed=62 + w)
+        _, _, fin, st = run_and_check(tabs, b, "occ", flags=b_.CC_RUN_HOT_ENGINE, lanes_per_txn=64,
+                                      waves_per_wg=waves)
+        assert oracle.order_entry_invariants(tabs, fin, b, np.ones(b.n_txns, bool)) == []
+        assert st["engine_txns"] > 0
+    # every transaction writes both rows of a two-row table: the whole batch runs in the engine
+    print(f"[gpu] hot engine two rows waves={waves}", flush=True)
+    b2 = wl.kv_batch(2, 1, 5_000, ops=2, read_ratio=0.3, arg_range=(-5, 5), seed=63)
+    _, _, _, st = run_and_check([wl.kv_table(2, 1)], b2, "occ", flags=b_.CC_RUN_HOT_ENGINE, lanes_per_txn=4,
+                                waves_per_wg=waves)
+    writes = sum(1 for t in range(b2.n_txns) if (b2.kind[b2.txn_slice(t)] != wl.READ).any())
+    assert st["engine_txns"] == writes
+    # a tiny batch
+    tabs, b = wl.tiny_workload(seed=64)
+    run_and_check(tabs, b, "occ", flags=b_.CC_RUN_HOT_ENGINE, waves_per_wg=waves)
+
+
+def test_hot_engine_needs_at_most_four_ops_per_lane():
+    b_ = binding()
+    tabs, b = wl.kv_workload(n_rows=20_000, n_fields=4, n_txns=2_000, ops=16, theta=0.9, seed=65)
+    with b_.Engine(tabs) as eng:
+        bid = eng.submit(b, "occ")
+        with pytest.raises(b_.CCError) as e:
+            eng.run(bid, flags=b_.CC_RUN_HOT_ENGINE, lanes_per_txn=1)
+        assert e.value.status == b_.CC_E_INVAL
+        # the refused run left the batch as it was: it runs afterwards
+        eng.run(bid, flags=b_.CC_RUN_HOT_ENGINE, lanes_per_txn=16)
+        out, reads = eng.outcomes(bid, b.n_txns, b.total_ops)
+        assert check(tabs, b, out, reads, eng.tables()).ok
+    # by default the engine is simply not used there
+    _, _, _, st = run_and_check(tabs, b, "occ", lanes_per_txn=1)
+    assert st["engine_txns"] == 0
 
 
 @pytest.mark.parametrize("scheme", IMPLEMENTED)

@@ -83,6 +83,8 @@ def test_serve_alone_vs_mix_full_size(scheme):
     rep = check(tabs, alone, out_a, reads_a, fin_a)
     assert rep.ok, rep
     assert np.all(out_m["commit_ns"] + 10 >= arr) and np.all(out_a["commit_ns"] + 10 >= arr_a)
+    # a served stream never runs OCC's hot-row engine, which knows no arrivals
+    assert st_m["engine_txns"] == 0 and st_a["engine_txns"] == 0
     cf = oracle.final_add_only([tabs[0]], alone)[0]
     assert np.array_equal(fin_a[0], cf) and np.array_equal(fin_m[0], cf)
     assert oracle.order_entry_invariants(tabs[1:], fin_m[1:], _oe_part(mix, m), out_m["status"][~m["is_kv"]] == 1) == []
