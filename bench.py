@@ -26,6 +26,11 @@ METRIC = "committed txns/sec on 1 MI355X (Zipf 0.9 KV, 16 ops/txn) + p99 commit 
 HBM_PEAK_GBS = 8000.0
 
 
+# the sources a kernel's HBM counters depend on (profiles/traffic.json keys them by their hash)
+KERNEL_SOURCES = {"txn_kernel": ("kernels.hip", "schemes.h", "txn_kernel.h", "device.h"),
+                  "engine_kernel": ("hot_engine.h", "schemes.h", "device.h")}
+
+
 def algorithmic_bytes(batch) -> int:
     """Bytes the OCC hot path must move for one committed pass over the batch.
 
@@ -123,6 +128,8 @@ def run_probes(ctx, binding, batch=None, quick=False) -> dict:
     # the hot row is touched from every XCD: the bounds take the cross-XCD hand-offs
     out["handoff_ns"] = out["handoff_cross_xcd_ns"]
     out["commit_handoff_ns"] = out["commit_handoff_cross_xcd_ns"]
+    # OCC's hot-row engine passes its rows between wavefronts of one workgroup, in LDS
+    out["engine_handoff_ns"] = binding.cc_probe(ctx, "engine_handoff", 1 << 20, rounds) * 1e6 / rounds
     ms = binding.cc_probe(ctx, "wave_counter", 1 << 20, 1 << 26)
     out["one_word_atomic_ns"] = ms * 1e6 / (threads // 64 * (((1 << 26) + threads - 1) // threads + 3) // 4 * 4)
     return {k: round(v, 3) for k, v in out.items()}
@@ -525,7 +532,7 @@ def main():
         restore()
         eng.run(bid, **params)
     torch.cuda.synchronize()
-    kernel_ns, run_ns, attempts, p50, p99, passes, step_ms = [], [], [], [], [], [], []
+    kernel_ns, run_ns, attempts, p50, p99, passes, step_ms, engine_ns = [], [], [], [], [], [], [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         restore()
@@ -541,6 +548,7 @@ def main():
         p50.append(st["lat_p50_ns"])
         p99.append(st["lat_p99_ns"])
         passes.append(st["passes"])
+        engine_ns.append(st["engine_ns"])
         print(f"[bench] step: {step_ms[-1]:.2f} ms, attempts {st['attempts']}, passes {st['passes']}",
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -551,29 +559,44 @@ def main():
     out_last, reads_last = eng.outcomes(bid, batch.n_txns, batch.total_ops)
     final_last = eng.tables()
 
-    # HBM roofline of the transaction kernel (algorithmic bytes / its time)
-    alg = algorithmic_bytes(batch)
+    # HBM roofline of the dominant kernel (algorithmic bytes / its time): the
+    # transaction kernel, or, when OCC's hot-row engine ran, the engine over
+    # its own share of the batch
+    eng_rows, _, _ = binding.cc_engine_plan(eng.ctx, bid) if args.scheme == "occ" else (np.zeros(0), 0, False)
+    eng_txns = np.zeros(0, np.int64)
+    if len(engine_ns) and np.mean(engine_ns) > 0:
+        w = batch.kind != workload.READ
+        txn_of_op = np.repeat(np.arange(batch.n_txns), batch.n_ops.astype(np.int64))
+        hit = np.zeros(batch.n_txns, bool)
+        hit[txn_of_op[w & (batch.table == 0) & np.isin(batch.row, eng_rows)]] = True
+        eng_txns = np.nonzero(hit)[0]
     k_step_s = float(np.mean(kernel_ns)) * 1e-9
-    launches = float(np.mean(passes))
-    achieved = alg / k_step_s / 1e9
+    if len(eng_txns):
+        alg = algorithmic_bytes(batch.subset(eng_txns))
+        dom_s, launches, dom_kernel = float(np.mean(engine_ns)) * 1e-9, 1.0, "engine_kernel"
+    else:
+        alg = algorithmic_bytes(batch)
+        dom_s, launches = k_step_s, float(np.mean(passes))
+        dom_kernel = {"gacco": "gacco_kernel", "gputx": "gputx_exec_kernel"}.get(args.scheme, "txn_kernel")
+    achieved = alg / dom_s / 1e9
     traffic = None
     if os.path.exists(args.traffic_json):
         import hashlib
         with open(args.traffic_json) as f:
             tj = json.load(f)
-        t = tj.get(f"{args.scheme}:{args.theta}:{args.rows}x{args.fields}:{args.txns}x{args.ops}")
+        t = tj.get(f"{args.scheme}:{args.theta}:{args.rows}x{args.fields}:{args.txns}x{args.ops}:{dom_kernel}")
         csrc = os.path.join(ROOT, "paper_2406_10158_amd", "csrc")
         cur = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
-                                      for f in ("kernels.hip", "schemes.h", "txn_kernel.h", "device.h"))).hexdigest()[:16]
+                                      for f in KERNEL_SOURCES.get(dom_kernel, KERNEL_SOURCES["txn_kernel"]))).hexdigest()[:16]
         # counters taken on another version of the kernel do not describe this one
         if t and t.get("kernel_src_sha256_16") == cur:
             traffic = t["total_bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
-                "kernel": {"gacco": "gacco_kernel", "gputx": "gputx_exec_kernel"}.get(args.scheme, "txn_kernel"),
+                "kernel": dom_kernel,
                 "launches_per_step": launches,
                 "algorithmic_bytes_per_launch": int(alg / launches),
-                "avg_launch_ms": round(k_step_s * 1e3 / launches, 4)}
+                "avg_launch_ms": round(dom_s * 1e3 / launches, 4)}
 
     # measured random-access / atomic roofline and hot-row contention bound
     probes = run_probes(eng.ctx, binding, batch=batch, quick=True)
@@ -602,27 +625,55 @@ def main():
         _, h = workload.hottest_row_writes(batch)
         t_h, h_key = probes["commit_handoff_ns"], "hot_row_writes_H"
     x_cont = batch.n_txns / (h * t_h * 1e-9) if h else float("inf")
+    engine_bound = None
+    if len(eng_txns):
+        # the engine runs before the rest of the batch: the passes' bounds add.
+        # Engine: its hottest row's writes at the engine's hand-off; rest: its
+        # own hottest row at OCC's commit hand-off, or its random accesses.
+        rest = batch.subset(np.setdiff1d(np.arange(batch.n_txns), eng_txns))
+        _, h_rest = workload.hottest_row_writes(rest)
+        acc_r = access_counts(rest)
+        t_rest_roof = (acc_r["word_loads"] / (probes["gather_80MB_Gops"] * 1e9)
+                       + acc_r["value_loads"] / (probes["gather_880MB_Gops"] * 1e9)
+                       + acc_r["word_atomics"] / (probes["atomic_80MB_Gops"] * 1e9)
+                       + acc_r["value_stores"] / (probes["scatter_880MB_Gops"] * 1e9)
+                       + acc_r["word_stores"] / (probes["scatter_80MB_Gops"] * 1e9)
+                       + acc_r["stream_bytes"] / (probes["stream_GBps"] * 1e9))
+        t_eng = h * probes["engine_handoff_ns"] * 1e-9
+        t_rest = max(h_rest * probes["commit_handoff_ns"] * 1e-9, t_rest_roof)
+        x_cont = batch.n_txns / (t_eng + t_rest)
+        engine_bound = {"engine_txns": int(len(eng_txns)), "engine_rows": int(len(eng_rows)),
+                        "t_h_engine_ns": probes["engine_handoff_ns"], "engine_min_ms": round(t_eng * 1e3, 3),
+                        "rest_hot_row_writes": int(h_rest), "rest_min_ms": round(t_rest * 1e3, 3),
+                        "engine_ms": round(float(np.mean(engine_ns)) / 1e6, 3)}
     eff = min(x_roof, x_cont)
     measured = {"random_access_roof_txn_per_s": round(x_roof, 1), h_key: h,
                 "t_h_ns": t_h, "contention_bound_txn_per_s": round(x_cont, 1),
                 "effective_roof_txn_per_s": round(eff, 1), "active_bound": "contention" if x_cont < x_roof else "random-access",
-                "frac_of_effective": round(value / eff, 4), "probes": probes, "per_batch_accesses": acc}
+                "frac_of_effective": round(value / eff, 4), "hot_row_engine": engine_bound, "probes": probes,
+                "per_batch_accesses": acc}
 
     roofline["active_bound"] = measured["active_bound"]
     roofline["active"] = {"achieved": round(value, 1), "peak": round(eff, 1), "unit": "txn/s",
                           "frac": round(value / eff, 4),
-                          "peak_from": ("H x t_h: writes to the hottest row times the measured commit hand-off"
+                          "peak_from": ("hot-row engine, then the rest of the batch: H x the engine's LDS hand-off, "
+                                        "plus the rest's hottest row x the commit hand-off (or its random accesses)"
+                                        if engine_bound and measured["active_bound"] == "contention" else
+                                        "H x t_h: writes to the hottest row times the measured commit hand-off"
                                         if measured["active_bound"] == "contention" else
                                         "random loads, atomics, stores and streamed bytes at the probed rates")}
 
     # the batch's most written row during the last step (OCC's lock-hold counters)
     hot_row = None
     if args.scheme == "occ" and st["hot_acq"]:
-        held = st["hot_hold_ns"] / max(st["kernel_ns"], 1)
+        # with the engine, the row is written only while the engine runs
+        span = st["engine_ns"] if st["engine_txns"] else st["kernel_ns"]
+        held = st["hot_hold_ns"] / max(span, 1)
         hot_row = {"writes_H": st["hot_writes"], "lock_acquisitions": st["hot_acq"],
                    "failed_holds": st["hot_failed"], "held_share": round(held, 4), "idle_share": round(1 - held, 4),
                    "hold_per_acquisition_ns": round(st["hot_hold_ns"] / st["hot_acq"], 1),
-                   "kernel_ns_per_hot_commit": round(st["kernel_ns"] / max(st["hot_writes"], 1), 1)}
+                   "kernel_ns_per_hot_commit": round(span / max(st["hot_writes"], 1), 1),
+                   "in": "engine_kernel" if st["engine_txns"] else "txn_kernel"}
 
     cpu = None
     if not args.no_cpu_baseline:

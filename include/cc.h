@@ -452,6 +452,21 @@ cc_status cc_submit_batch_keyed(cc_ctx *ctx, const cc_txn *txns, uint64_t n_txns
 cc_status cc_fetch_rows(cc_ctx *ctx, uint64_t batch_id, uint32_t *rows);
 
 /*
+ * The OCC hot-row engine's plan for a batch, made at submission (see
+ * CC_RUN_HOT_ENGINE): rows (host array of CC_ENGINE_MAX_ROWS entries)
+ * receives the engine rows as global row ids -- the table's first row in the
+ * shared row space plus the row, tables in creation order -- most written
+ * first; *n_rows their count (0: no engine for this batch: not OCC, keyed,
+ * static, or nothing written often enough); *n_txns the transactions that
+ * write one of them; *by_default 1 if cc_run uses the engine without
+ * CC_RUN_HOT_ENGINE when the batch is contended (every row left out written at
+ * most a quarter as often as the most written).  Host-side; no device work.
+ */
+#define CC_ENGINE_MAX_ROWS 32
+cc_status cc_engine_plan(cc_ctx *ctx, uint64_t batch_id, uint32_t *rows, uint32_t *n_rows, uint64_t *n_txns,
+                         int *by_default);
+
+/*
  * Host-only validation of a batch against table shapes (n_tables tables of
  * n_rows[t] x n_fields[t]), with exactly the checks cc_submit_batch applies.
  * Touches no device; usable without a GPU.  Returns CC_OK or the status
@@ -572,6 +587,12 @@ cc_status cc_run_static(cc_ctx *ctx, const cc_txn *txns, uint64_t n_txns, const 
  *                          value store, publish), alternating between two
  *                          workgroups `peer` apart: ms / n_ops is the hot-row
  *                          hand-off time t_h
+ *   CC_PROBE_ENGINE_HANDOFF n_ops rounds of the OCC hot-row engine's commit
+ *                          critical section on one engine row (LDS lock, LDS
+ *                          ticket, one agent-scope validation load, LDS store
+ *                          and release), alternating between two wavefronts of
+ *                          one workgroup: ms / n_ops is the engine's t_h (peer
+ *                          is ignored)
  * Random addresses are uniform over the footprint_bytes / 8 words of the
  * probe's buffer (rounded down to a multiple of 4).  For the hand-off probes,
  * peer places the second side: 0 in the same workgroup (same CU), 8 in
@@ -589,7 +610,8 @@ enum cc_probe_kind {
   CC_PROBE_SAME_WORD = 5,
   CC_PROBE_WAVE_COUNTER = 6,
   CC_PROBE_HANDOFF = 7,
-  CC_PROBE_COMMIT_HANDOFF = 8
+  CC_PROBE_COMMIT_HANDOFF = 8,
+  CC_PROBE_ENGINE_HANDOFF = 9
 };
 cc_status cc_probe(cc_ctx *ctx, int kind, uint64_t footprint_bytes, uint64_t n_ops, int peer, double *ms);
 

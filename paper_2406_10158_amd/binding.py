@@ -90,6 +90,7 @@ _SIGS = {
                                    ctypes.POINTER(ctypes.c_uint64)]),
     "cc_create_index": (_S, [_P, ctypes.c_uint32, _P, ctypes.c_uint64]),
     "cc_fetch_rows": (_S, [_P, ctypes.c_uint64, _P]),
+    "cc_engine_plan": (_S, [_P, ctypes.c_uint64, _P, _P, _P, _P]),
     "cc_run": (_S, [_P, ctypes.c_uint64, ctypes.POINTER(cc_run_params)]),
     "cc_check_run_params": (_S, [ctypes.c_int, ctypes.POINTER(cc_run_params)]),
     "cc_fetch_outcomes": (_S, [_P, ctypes.c_uint64, _P, _P, ctypes.c_int]),
@@ -164,7 +165,7 @@ def cc_device_info(ctx):
 
 
 PROBES = {"stream": 0, "gather": 1, "gather_plain": 2, "scatter": 3, "atomic": 4, "same_word": 5,
-          "wave_counter": 6, "handoff": 7, "commit_handoff": 8}
+          "wave_counter": 6, "handoff": 7, "commit_handoff": 8, "engine_handoff": 9}
 
 
 def cc_probe(ctx, kind, footprint_bytes: int, n_ops: int, peer: int = 1) -> float:
@@ -269,6 +270,15 @@ def cc_fetch_rows(ctx, batch_id: int, n_ops: int) -> np.ndarray:
     rows = np.zeros(max(n_ops, 1), np.uint32)
     _check(lib.cc_fetch_rows(ctx, batch_id, _ptr(rows)), ctx)
     return rows[:n_ops]
+
+
+def cc_engine_plan(ctx, batch_id: int):
+    """(engine rows as global row ids, engine transactions, used by default) of a submitted batch."""
+    rows = np.zeros(32, np.uint32)
+    n_rows, n_txns, dflt = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_int()
+    _check(lib.cc_engine_plan(ctx, batch_id, _ptr(rows), ctypes.byref(n_rows), ctypes.byref(n_txns),
+                              ctypes.byref(dflt)), ctx)
+    return rows[:n_rows.value].copy(), int(n_txns.value), bool(dflt.value)
 
 
 def run_params(lanes_per_txn=0, waves_per_wg=0, grid=0, mode=CC_MODE_PLAIN, max_attempts=0, max_epochs=0,

@@ -355,7 +355,7 @@ cc_status cc_destroy(cc_ctx *c) {
 
 cc_status cc_probe(cc_ctx *c, int kind, uint64_t footprint_bytes, uint64_t n_ops, int peer, double *ms) {
   if (!c || !ms) return CC_E_INVAL;
-  if (kind < CC_PROBE_STREAM || kind > CC_PROBE_COMMIT_HANDOFF) return fail(c, CC_E_INVAL, "unknown probe");
+  if (kind < CC_PROBE_STREAM || kind > CC_PROBE_ENGINE_HANDOFF) return fail(c, CC_E_INVAL, "unknown probe");
   const bool pair = kind == CC_PROBE_HANDOFF || kind == CC_PROBE_COMMIT_HANDOFF;
   if (footprint_bytes < 4096 || (pair && (peer < 0 || peer > 64)))
     return fail(c, CC_E_INVAL, "bad probe size or peer");
@@ -728,7 +728,7 @@ static void plan_engine(const DevOp *dops, const DevTxn *dtx, uint64_t n_txns, c
   int nc = 0;
   for (uint64_t r = 0; r < cnt.size(); ++r) {
     const uint32_t c = cnt[r];
-    if (c < thr || (nc == NC && c <= cc[NC - 1])) continue;
+    if (c == 0 || (nc == NC && c <= cc[NC - 1])) continue;
     int i = nc < NC ? nc++ : NC - 1;
     while (i > 0 && cc[i - 1] < c) {
       cc[i] = cc[i - 1];
@@ -738,7 +738,7 @@ static void plan_engine(const DevOp *dops, const DevTxn *dtx, uint64_t n_txns, c
     cc[i] = c;
     cr[i] = (uint32_t)r;
   }
-  if (nc == 0) return;
+  if (nc == 0 || cc[0] < thr) return;
   uint32_t left_out = 0;  // writes of the most written row not taken
   bool full = false;
   for (int i = 0; i < nc; ++i) {
@@ -746,7 +746,8 @@ static void plan_engine(const DevOp *dops, const DevTxn *dtx, uint64_t n_txns, c
     const Table *tb = nullptr;
     for (const Table &t : tables)
       if (r >= t.row_base && r < t.row_base + t.n_rows) tb = &t;
-    bool take = !full && tb && tb->n_fields <= (uint32_t)ENG_FIELDS && b.eng.n_vals + tb->n_fields <= (uint32_t)ENG_VALS;
+    bool take = !full && cc[i] >= thr && tb && tb->n_fields <= (uint32_t)ENG_FIELDS &&
+                b.eng.n_vals + tb->n_fields <= (uint32_t)ENG_VALS;
     if (take) {
       const uint32_t k = b.eng.n_rows++;
       b.eng.row[k] = r;
@@ -1261,6 +1262,20 @@ cc_status cc_create_index(cc_ctx *c, uint32_t tid, const int64_t *keys, uint64_t
   if (c->indexes.size() < c->tables.size()) c->indexes.resize(c->tables.size());
   drop(c->indexes[tid]);
   c->indexes[tid] = nx;
+  return CC_OK;
+}
+
+cc_status cc_engine_plan(cc_ctx *c, uint64_t batch_id, uint32_t *rows, uint32_t *n_rows, uint64_t *n_txns,
+                         int *by_default) {
+  if (!c || !rows || !n_rows || !n_txns || !by_default) return CC_E_INVAL;
+  auto it = c->batches.find(batch_id);
+  if (it == c->batches.end()) return fail(c, CC_E_NOBATCH, "unknown batch");
+  const Batch &b = it->second;
+  static_assert(CC_ENGINE_MAX_ROWS == ENG_MAX, "engine rows");
+  for (uint32_t i = 0; i < (uint32_t)ENG_MAX; ++i) rows[i] = i < b.eng.n_rows ? b.eng.row[i] : 0u;
+  *n_rows = b.n_eng_txns ? b.eng.n_rows : 0;
+  *n_txns = b.n_eng_txns;
+  *by_default = b.n_eng_txns && b.eng_gain ? 1 : 0;
   return CC_OK;
 }
 

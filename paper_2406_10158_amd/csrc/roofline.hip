@@ -140,6 +140,50 @@ __global__ void __launch_bounds__(128) probe_commit_handoff(uint64_t *buf, uint6
   }
 }
 
+// The hot-row engine's commit critical section on one engine row, handed
+// back and forth between two wavefronts of one workgroup: wait for the turn
+// (an LDS word, bounded), take the row's LDS lock, draw a ticket from an LDS
+// counter, make one agent-scope validation load and wait for it, store the
+// new value in LDS and release the lock.  The time per round is the shortest
+// interval between two commits on one engine row: the engine's t_h.
+__global__ void __launch_bounds__(128) probe_engine_handoff(uint64_t *buf, uint64_t rounds, uint64_t spin_limit,
+                                                            uint64_t *err) {
+  __shared__ uint32_t lk;
+  __shared__ uint64_t turn, ticket;
+  __shared__ int64_t value;
+  if (threadIdx.x == 0) {
+    lk = 0;
+    turn = 0;
+    ticket = 0;
+    value = 0;
+  }
+  __syncthreads();
+  if (threadIdx.x % 64 != 0) return;
+  const uint64_t side = threadIdx.x / 64;
+  const uint64_t *other = buf + 192 + 16 * side;
+  for (uint64_t r = side; r < rounds; r += 2) {
+    uint64_t spins = 0;
+    while (__hip_atomic_load(&turn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != r) {
+      if (++spins > spin_limit) {
+        __hip_atomic_store(err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+      }
+    }
+    uint32_t expect = 0;
+    const bool got = __hip_atomic_compare_exchange_strong(&lk, &expect, 1u << 31, __ATOMIC_RELAXED,
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    const uint64_t t = __hip_atomic_fetch_add(&ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    const uint64_t o = __hip_atomic_load(other, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0);
+    value = value + 1 + (o == 0x5A5Aull ? (int64_t)t + got : 0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    (void)__hip_atomic_fetch_and(&lk, ~(1u << 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_store(&turn, r + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
 __global__ void fill_kernel(uint64_t *p, uint64_t n, uint64_t v) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
@@ -193,6 +237,9 @@ hipError_t run_probe(hipStream_t s, int kind, uint64_t footprint_bytes, uint64_t
       hipLaunchKernelGGL(probe_commit_handoff, dim3((unsigned)(peer + 1)), dim3(128), 0, s, buf, n_ops, peer,
                          (uint64_t)1 << 20, aux + 4096);
       break;
+    case 9:
+      hipLaunchKernelGGL(probe_engine_handoff, dim3(1), dim3(128), 0, s, buf, n_ops, (uint64_t)1 << 20, aux + 4096);
+      break;
     default:
       break;
   }
@@ -201,7 +248,7 @@ hipError_t run_probe(hipStream_t s, int kind, uint64_t footprint_bytes, uint64_t
   if (e == hipSuccess) e = hipEventSynchronize(b);
   float ms = 0;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-  if (e == hipSuccess && (kind == 7 || kind == 8)) e = hipMemcpy(err_out, aux + 4096, sizeof(uint64_t), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && (kind == 7 || kind == 8 || kind == 9)) e = hipMemcpy(err_out, aux + 4096, sizeof(uint64_t), hipMemcpyDeviceToHost);
   *ms_out = ms;
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);

@@ -82,11 +82,10 @@ class Batch:
         first = np.zeros(len(txn_ids), dtype=np.uint64)
         if len(txn_ids):
             first[1:] = np.cumsum(n[:-1], dtype=np.uint64)
-        if len(txn_ids):
-            idx = np.concatenate([np.arange(int(self.first_op[t]), int(self.first_op[t]) + int(self.n_ops[t]))
-                                  for t in txn_ids]).astype(np.int64)
-        else:
-            idx = np.zeros(0, dtype=np.int64)
+        lens = n.astype(np.int64)
+        starts = self.first_op[txn_ids].astype(np.int64) if len(txn_ids) else np.zeros(0, np.int64)
+        # op j of the k-th chosen transaction: starts[k] + j, laid out one transaction after another
+        idx = np.repeat(starts - (np.cumsum(lens) - lens), lens) + np.arange(int(lens.sum()), dtype=np.int64)
         return Batch(first, n, self.row[idx].copy(), self.table[idx].copy(), self.field[idx].copy(),
                      self.kind[idx].copy(), self.arg[idx].copy(), dict(self.meta))
 

@@ -194,6 +194,8 @@ def test_every_entry_point_rejects_a_null_context(b):
         "cc_run": lambda: lib.cc_run(None, 1, ctypes.byref(params)),
         "cc_fetch_outcomes": lambda: lib.cc_fetch_outcomes(None, 1, None, None, 0),
         "cc_fetch_rows": lambda: lib.cc_fetch_rows(None, 1, ctypes.addressof(buf)),
+        "cc_engine_plan": lambda: lib.cc_engine_plan(None, 1, ctypes.addressof(buf), ctypes.byref(u32),
+                                                      ctypes.byref(u64), ctypes.byref(ctypes.c_int())),
         "cc_set_arrivals": lambda: lib.cc_set_arrivals(None, 1, None, 0),
         "cc_stats": lambda: lib.cc_stats(None, 1, None, 0),
         "cc_release_batch": lambda: lib.cc_release_batch(None, 1),

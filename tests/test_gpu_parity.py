@@ -341,6 +341,30 @@ def test_full_size_kv_config_without_hot_engine():
     assert st["engine_txns"] == 0
 
 
+def test_hot_engine_plan_follows_its_rule():
+    # the engine rows: the most written rows (most first, ties by row), at most 32, each written at
+    # least max(2, n_txns / 4096) times; its transactions: those that write one of them
+    b_ = binding()
+    tabs, b = wl.kv_workload(theta=0.9, seed=0)
+    with b_.Engine(tabs) as eng:
+        bid = eng.submit(b, "occ")
+        rows, n_eng, by_default = b_.cc_engine_plan(eng.ctx, bid)
+        bid2 = eng.submit(b, "tictoc")
+        assert b_.cc_engine_plan(eng.ctx, bid2)[1] == 0  # OCC only
+    w = b.kind != wl.READ
+    cnt = np.bincount(b.row[w].astype(np.int64), minlength=len(tabs[0]))
+    thr = max(2, b.n_txns // 4096)
+    order = np.lexsort((np.arange(len(cnt)), -cnt))
+    exp = [int(r) for r in order[:32] if cnt[r] >= thr]
+    assert rows.tolist() == exp
+    txn_of_op = np.repeat(np.arange(b.n_txns), b.n_ops.astype(np.int64))
+    hit = np.zeros(b.n_txns, bool)
+    hit[txn_of_op[w & np.isin(b.row, exp)]] = True
+    assert n_eng == int(hit.sum())
+    # used by default: the most written row left out is written at most a quarter as often as the first
+    assert by_default == bool(cnt[order[len(exp)]] * 4 <= cnt[order[0]])
+
+
 def test_full_size_kv_config_runs_the_hot_engine_by_default():
     tabs, b = wl.kv_workload(theta=0.9, seed=0)
     _, _, _, st = run_and_check(tabs, b, "occ")
