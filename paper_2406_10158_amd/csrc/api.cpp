@@ -63,7 +63,9 @@ struct Batch {
   uint64_t n_eng_txns = 0;
   bool eng_gain = false;
   uint32_t *d_part = nullptr;
-  std::vector<uint32_t> eng_part;  // host copy until the upload
+  EngineDesc *d_eng_desc = nullptr;  // the engine's transactions with their first op and op count
+  std::vector<uint32_t> eng_part;  // host copies until the upload
+  std::vector<EngineDesc> eng_desc;
 };
 
 }  // namespace
@@ -184,6 +186,8 @@ void free_batch(Batch &b) {
   if (b.d_list) (void)hipFree(b.d_list);
   if (b.d_part) (void)hipFree(b.d_part);
   b.d_part = nullptr;
+  if (b.d_eng_desc) (void)hipFree(b.d_eng_desc);
+  b.d_eng_desc = nullptr;
   if (b.d_nodes) (void)hipFree(b.d_nodes);
   if (b.d_opkeys) (void)hipFree(b.d_opkeys);
   if (b.d_meta) (void)hipFree(b.d_meta);
@@ -721,6 +725,7 @@ static void plan_engine(const DevOp *dops, const DevTxn *dtx, uint64_t n_txns, c
   b.n_eng_txns = 0;
   b.eng_gain = false;
   b.eng_part.clear();
+  b.eng_desc.clear();
   const uint32_t thr = (uint32_t)std::max<uint64_t>(2, n_txns / 4096);
   // candidates: the most written rows (more than fit, to know the best row left out)
   constexpr int NC = ENG_MAX + 16;
@@ -774,13 +779,17 @@ static void plan_engine(const DevOp *dops, const DevTxn *dtx, uint64_t n_txns, c
     }
   b.eng_part.reserve(n_txns);
   for (uint64_t t = 0; t < n_txns; ++t)
-    if (in_eng[t]) b.eng_part.push_back((uint32_t)t);
+    if (in_eng[t]) {
+      b.eng_part.push_back((uint32_t)t);
+      b.eng_desc.push_back(EngineDesc{(uint32_t)t, dtx[t].first, dtx[t].n, 0u});
+    }
   b.n_eng_txns = b.eng_part.size();
   for (uint64_t t = 0; t < n_txns; ++t)
     if (!in_eng[t]) b.eng_part.push_back((uint32_t)t);
   if (b.n_eng_txns == 0) {
     b.eng = EngineArgs{};
     b.eng_part.clear();
+    b.eng_desc.clear();
   }
 }
 
@@ -792,8 +801,13 @@ static hipError_t upload_engine_plan(cc_ctx *c, Batch &b) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(b.d_part, b.eng_part.data(), b.eng_part.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
                        c->stream);
+  if (e == hipSuccess) e = hipMalloc(&b.d_eng_desc, b.eng_desc.size() * sizeof(EngineDesc));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b.d_eng_desc, b.eng_desc.data(), b.eng_desc.size() * sizeof(EngineDesc),
+                       hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   b.eng_part = std::vector<uint32_t>();
+  b.eng_desc = std::vector<EngineDesc>();
   return e;
 }
 
@@ -1547,12 +1561,12 @@ static cc_status run_batch(cc_ctx *c, Batch &b, const cc_run_params &p, bool hos
     // rows run first, alone, in one workgroup; the rest then run as usual
     // (plain mode only: serving also passes here, and the engine knows no arrivals)
     const bool use_eng = b.scheme == CC_OCC && p.mode == CC_MODE_PLAIN && !latch && eng_fits && b.n_eng_txns &&
-                         b.d_part &&
+                         b.d_part && b.d_eng_desc &&
                          ((p.flags & CC_RUN_HOT_ENGINE) ||
                           (!(p.flags & CC_RUN_NO_HOT_ENGINE) && !no_hot_row && b.eng_gain));
     if (use_eng) {
       EngineArgs e = b.eng;
-      e.list = b.d_part;
+      e.desc = b.d_eng_desc;
       e.n_txns = b.n_eng_txns;
       a.defer_after = 0;
       HIP_OR(c, hipEventRecord(c->ev[1], c->stream));

@@ -160,8 +160,11 @@ struct IndexDesc {
 constexpr int ENG_MAX = 32;
 constexpr int ENG_FIELDS = 64;
 constexpr int ENG_VALS = 1024;
+struct EngineDesc {           // one engine transaction: its id, first op and op count
+  uint32_t txn, first, n, pad;
+};
 struct EngineArgs {
-  const uint32_t *list;       // the engine's transactions
+  const EngineDesc *desc;     // the engine's transactions, in batch order
   uint64_t n_txns;
   uint32_t n_rows;            // engine rows (0: no engine)
   uint32_t n_vals;            // their cells

@@ -67,6 +67,21 @@ __device__ __forceinline__ int eng_index(const EngineArgs &e, uint32_t row, uint
 
 __device__ __forceinline__ void lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
 
+// Cold rows in the engine: while the engine runs, only its own workgroup
+// touches any row, so the cold rows' locks and versions live in LDS too, in a
+// table of ENG_BUCKETS words a row hashes into (rows sharing a bucket share
+// its lock: a rare false conflict).  Bucket word: bit 63 locked, bits 47-62
+// the locking team, bits 0-46 a version bumped by every commit that writes a
+// row of the bucket.  The rows' values stay in global memory; the global
+// word of a written row receives the committing ticket (the pass that runs
+// after the engine validates against it).
+constexpr int ENG_BUCKETS = 16384;
+constexpr uint64_t CB_LOCK = 1ull << 63;
+constexpr uint64_t CB_VMASK = (1ull << 47) - 1ull;
+__device__ __forceinline__ uint32_t cold_bucket(uint32_t row) { return (row * 0x9E3779B1u) >> (32 - 14); }
+static_assert(ENG_BUCKETS == 1 << 14, "cold_bucket hashes to 14 bits");
+__device__ __forceinline__ uint32_t cb_owner(uint64_t w) { return (uint32_t)((w >> 47) & 0xFFFFu); }
+
 // One attempt of a team (every lane of the wavefront calls it).  WAITING:
 // an engine row was taken (*wait_j: which, and ENG_WRITER if to write it);
 // the attempt gave back everything it held.
@@ -74,50 +89,62 @@ template <int L, int K, bool STRICT>
 __device__ __forceinline__ int engine_attempt(const Team<L> &t, Slots<K> &s, const int (&ei)[K],
                                               const uint32_t (&cell)[K], uint32_t emask, bool active,
                                               const RunArgs &a, const EngineArgs &e, uint32_t *lk, uint64_t *tid,
-                                              int64_t *val, uint64_t *ticket_ctr, uint64_t *hot_t0,
+                                              int64_t *val, uint64_t *cb, uint64_t *ticket_ctr, uint64_t *hot_t0,
                                               uint64_t *hot_dt, uint32_t *wait_j, uint64_t *key) {
   bool fail = false;
   uint32_t blk = ~0u;
-  bool lock_fail = false;
-  {
-    // R1: the cold rows
-    bool issued[K];
+  const uint32_t me = (uint32_t)threadIdx.x / (uint32_t)L;  // the team in the workgroup
+  // R1: the cold rows' buckets -- a written row's locked (no wait), a
+  // read-only row's version read (held by another team: abort)
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      s.got[k] = false;
-      issued[k] = active && s.valid[k] && op_leader(s.rowk[k]) && ei[k] < 0;
-      if (issued[k]) {
-        uint64_t *w = a.words + op_row(s.rowk[k]);
-        s.v[k] = op_written(s.rowk[k]) ? or_word(w, OCC_LOCK) : ld_word(w);
+  for (int k = 0; k < K; ++k) {
+    s.got[k] = false;
+    if (active && s.valid[k] && op_leader(s.rowk[k]) && ei[k] < 0) {
+      uint64_t *w = cb + cold_bucket(op_row(s.rowk[k]));
+      uint64_t cur = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      bool ok = false;
+      if (op_written(s.rowk[k])) {
+        for (int i = 0; i < 4; ++i) {
+          if (cur & CB_LOCK) {
+            ok = cb_owner(cur) == me;  // another row of ours in the same bucket
+            break;
+          }
+          if (__hip_atomic_compare_exchange_strong(w, &cur, CB_LOCK | ((uint64_t)me << 47) | (cur & CB_VMASK),
+                                                   __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+            ok = true;
+            s.got[k] = true;
+            break;
+          }
+        }
+      } else {
+        ok = !(cur & CB_LOCK) || cb_owner(cur) == me;
       }
+      s.v[k] = cur & CB_VMASK;
+      if (!ok && blk == ~0u) blk = op_row(s.rowk[k]);
+      fail |= !ok;
     }
-    order_point<STRICT>();
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (!issued[k]) continue;
-      const uint64_t o = s.v[k];
-      if ((o & OCC_LOCK) && blk == ~0u) blk = op_row(s.rowk[k]);
-      if (op_written(s.rowk[k])) s.got[k] = !(o & OCC_LOCK);
-      fail |= (o & OCC_LOCK) != 0;
-    }
-    lock_fail = t.any(fail);
-    if (active && lock_fail) {
-#pragma unroll
-      for (int k = 0; k < K; ++k)
-        if (s.got[k]) st_word(a.words + op_row(s.rowk[k]), s.v[k]);
-    }
-    // the cold values: under the locks, after the read-only rows' words
+  }
+  const bool lock_fail = t.any(fail);
+  if (active && lock_fail) {
 #pragma unroll
     for (int k = 0; k < K; ++k)
-      if (active && !lock_fail && s.valid[k] && ei[k] < 0) s.x[k] = ld_val(a.data + s.elem[k]);
+      if (s.got[k]) __hip_atomic_store(cb + cold_bucket(op_row(s.rowk[k])), s.v[k], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   s.block = blocking_row(t, blk);
+  lds_fence();  // the buckets before the values
+  // the cold values, waited for before any engine row is taken, so that no
+  // engine row is held across a global round trip
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (active && !lock_fail && s.valid[k] && ei[k] < 0) s.x[k] = ld_val(a.data + s.elem[k]);
+  if (ballot(active && !lock_fail)) order_point<STRICT>();
 
   // R1b: the engine rows, in decreasing engine index
   const bool go = active && !lock_fail;
   const uint32_t need = go ? emask : 0u;  // team-uniform
   uint32_t held = 0;                      // team-uniform: engine rows taken
-  bool stop = false;                                  // team-uniform: a row was not free
+  bool stop = false;                      // team-uniform: a row was not free
   uint64_t wneed = 0;
   {
     // rows any team of the wavefront still needs (every lane of a team has `need`)
@@ -171,7 +198,8 @@ __device__ __forceinline__ int engine_attempt(const Team<L> &t, Slots<K> &s, con
         else
           (void)__hip_atomic_fetch_sub(lk + ei[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
-      if (s.got[k]) st_word(a.words + op_row(s.rowk[k]), s.v[k]);
+      if (s.got[k])
+        __hip_atomic_store(cb + cold_bucket(op_row(s.rowk[k])), s.v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     held = 0;
   }
@@ -203,25 +231,23 @@ __device__ __forceinline__ int engine_attempt(const Team<L> &t, Slots<K> &s, con
       ticket = base + 1 + (uint64_t)__popcll(m & ((1ull << t.tb) - 1ull));
     }
   }
-  lds_fence();  // the ticket is drawn before the releases and validation loads below
+  lds_fence();  // the ticket is drawn before the releases and validation below
 #pragma unroll
   for (int k = 0; k < K; ++k)
     if (alive && s.valid[k] && op_leader(s.rowk[k]) && ei[k] >= 0 && !op_written(s.rowk[k]))
       (void)__hip_atomic_fetch_sub(lk + ei[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 
-  // R3: validation of the cold rows
-  bool bad = false, vload = false;
+  // R3: validation of the cold read-only rows: their buckets unchanged and
+  // not held by another team
+  bool bad = false;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    if (alive && s.valid[k] && op_leader(s.rowk[k]) && ei[k] < 0) {
-      if (!op_written(s.rowk[k])) {
-        bad |= ld_word(a.words + op_row(s.rowk[k])) != s.v[k];
-        vload = true;
-      }
-      bad |= (s.v[k] & ~OCC_LOCK) >= ticket;
+    if (alive && s.valid[k] && op_leader(s.rowk[k]) && ei[k] < 0 && !op_written(s.rowk[k])) {
+      const uint64_t cur = __hip_atomic_load(cb + cold_bucket(op_row(s.rowk[k])), __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP);
+      bad |= ((cur & CB_LOCK) && cb_owner(cur) != me) || (cur & CB_VMASK) != s.v[k];
     }
   }
-  if (ballot(vload)) order_point<STRICT>();
   const bool valid_fail = t.any(bad);
   const bool commit = alive && !valid_fail;
 
@@ -251,14 +277,22 @@ __device__ __forceinline__ int engine_attempt(const Team<L> &t, Slots<K> &s, con
       (void)__hip_atomic_fetch_and(lk + ei[k], ~ENG_WRITER, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   __builtin_amdgcn_s_setprio(0);
   if (alive && *hot_t0) *hot_dt = wall_clock64() - *hot_t0;
-  // cold rows: values, wait, words
+  // cold rows: values and words to global memory, then the buckets released
+  // with a new version (a workgroup-scope release: another wavefront that
+  // sees the bucket free and then loads a value reads the new one)
 #pragma unroll
   for (int k = 0; k < K; ++k)
     if (commit && s.valid[k] && op_kind(s.rowk[k]) != CC_READ && ei[k] < 0) st_val(a.data + s.elem[k], nv[k]);
-  if (ballot(commit)) order_point<STRICT>();
 #pragma unroll
   for (int k = 0; k < K; ++k)
-    if (alive && s.got[k]) st_word(a.words + op_row(s.rowk[k]), commit ? ticket : s.v[k]);
+    if (commit && s.valid[k] && op_leader(s.rowk[k]) && op_written(s.rowk[k]) && ei[k] < 0)
+      st_word(a.words + op_row(s.rowk[k]), ticket);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (alive && s.got[k])
+      __hip_atomic_store(cb + cold_bucket(op_row(s.rowk[k])), commit ? ((s.v[k] + 1) & CB_VMASK) : s.v[k],
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   *key = ticket;
   if (!active) return COMMIT;
   if (lock_fail) return ABORT_LOCK;
@@ -266,11 +300,62 @@ __device__ __forceinline__ int engine_attempt(const Team<L> &t, Slots<K> &s, con
   return valid_fail ? ABORT_VALID : COMMIT;
 }
 
+// Loads the ops of the staged transaction nx_d into the staging registers.
+template <int L, int K>
+__device__ __forceinline__ void load_next_ops(const Team<L> &t, const RunArgs &a, const EngineDesc &nx_d,
+                                              uint32_t (&nx_rowk)[K], uint32_t (&nx_elem)[K], int64_t (&nx_arg)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t idx = (uint32_t)t.tl + (uint32_t)(k * L);
+    if (idx < nx_d.n) {
+      const DevOp op = a.ops[nx_d.first + idx];
+      nx_rowk[k] = op.rowk;
+      nx_elem[k] = op.elem;
+      nx_arg[k] = op.arg;
+    }
+  }
+}
+
+// A team with no transaction takes the staged one (loading its ops first if
+// they are not in registers yet): its slots, engine indices and LDS cells.
+template <int L, int K>
+__device__ __forceinline__ void take_next(const Team<L> &t, Slots<K> &s, const EngineArgs &e, const RunArgs &a,
+                                          int &nx_state, const EngineDesc &nx_d, uint32_t (&nx_rowk)[K],
+                                          uint32_t (&nx_elem)[K], int64_t (&nx_arg)[K], int (&ei)[K],
+                                          uint32_t (&cell)[K], uint32_t *emask, int64_t *txn, uint32_t *first,
+                                          uint32_t *n) {
+  if (nx_state == 0) return;
+  if (nx_state == 1) load_next_ops<L, K>(t, a, nx_d, nx_rowk, nx_elem, nx_arg);
+  *txn = (int64_t)nx_d.txn;
+  *first = nx_d.first;
+  *n = nx_d.n;
+  uint32_t m = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t idx = (uint32_t)t.tl + (uint32_t)(k * L);
+    s.valid[k] = idx < nx_d.n;
+    s.oi[k] = nx_d.first + idx;
+    s.rowk[k] = s.valid[k] ? nx_rowk[k] : FOLLOWER_BIT;
+    s.elem[k] = s.valid[k] ? nx_elem[k] : 0u;
+    s.arg[k] = s.valid[k] ? nx_arg[k] : 0;
+    s.x[k] = 0;
+    s.v[k] = 0;
+    ei[k] = s.valid[k] ? eng_index(e, op_row(s.rowk[k]), s.elem[k], &cell[k]) : -1;
+    if (ei[k] >= 0 && op_leader(s.rowk[k])) m |= 1u << ei[k];
+  }
+  // OR over the team's lanes
+#pragma unroll
+  for (int o = 1; o < L; o <<= 1) m |= (uint32_t)__shfl_xor((int)m, o, 64);
+  *emask = m;
+  nx_state = 0;
+}
+
 template <int L, int K, bool STRICT>
 __global__ void __launch_bounds__(MaxThreads<K>::value) engine_kernel(RunArgs a, EngineArgs e) {
   __shared__ uint32_t lk[ENG_MAX];
   __shared__ uint64_t tid[ENG_MAX];
   __shared__ int64_t val[ENG_VALS];
+  __shared__ uint64_t cb[ENG_BUCKETS];
   __shared__ uint64_t ticket_ctr;
   __shared__ uint32_t queue_ctr;
   const uint32_t me = threadIdx.x, nthr = blockDim.x;
@@ -284,6 +369,7 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) engine_kernel(RunArgs a,
     while (i + 1 < e.n_rows && e.off[i + 1] <= v) ++i;
     val[v] = ld_val(a.data + e.elem0[i] + (v - e.off[i]));
   }
+  for (uint32_t i = me; i < (uint32_t)ENG_BUCKETS; i += nthr) cb[i] = 0;
   if (me == 0) {
     ticket_ctr = ld_word(&a.ctl->ticket);
     queue_ctr = 0;
@@ -297,13 +383,17 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) engine_kernel(RunArgs a,
   uint32_t emask = 0;     // team-uniform: engine rows the transaction touches
   const uint64_t start_clock = a.ctl->start_clock;
   int64_t txn = -1;
-  uint32_t first = 0, n = 0;  // the transaction's ops, read once when it is claimed
+  uint32_t first = 0, n = 0;  // the transaction's ops
   uint32_t attempts = 0;
   uint64_t ready_at = 0;
   uint32_t wait_j = 0;    // team-uniform: the engine row a waiting team stopped at (ENG_WRITER: to write it)
-  bool done = false;
-  bool staged = false;    // the transaction's ops are in the slots
   bool waiting = false;   // the team waits, holding nothing, for engine row wait_j
+  // the next transaction (team-uniform): 0 none, 1 descriptor loaded, 2 ops loaded too
+  int nx_state = 0;
+  bool nx_end = false;    // no transaction left to claim
+  EngineDesc nx_d{0, 0, 0, 0};
+  uint32_t nx_rowk[K], nx_elem[K];
+  int64_t nx_arg[K];
   uint64_t n_commit = 0, n_att = 0, n_lock = 0, n_valid = 0, n_gave = 0, max_att = 0, n_waits = 0;
   uint64_t t_useful = 0, t_abort = 0, t_wait = 0;
   uint64_t n_hot_acq = 0, n_hot_fail = 0, t_hot = 0;
@@ -315,33 +405,37 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) engine_kernel(RunArgs a,
   }
 
   for (;;) {
-    const bool need = txn < 0 && !done;
-    uint32_t q = 0;
-    {
-      const uint64_t m = ballot(need && t.tl == 0);
-      if (m) {
-        const int first = __ffsll((unsigned long long)m) - 1;
-        uint32_t base = 0;
-        if (t.lane == first)
-          base = __hip_atomic_fetch_add(&queue_ctr, (uint32_t)__popcll(m), __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_WORKGROUP);
-        base = (uint32_t)__builtin_amdgcn_readlane((int)base, first);
-        q = base + (uint32_t)__popcll(m & ((1ull << t.tb) - 1ull));
+    // the next transaction is staged while the current one runs: claimed and
+    // its descriptor loaded in one iteration, its ops loaded after that
+    // iteration's rounds, taken from registers when the current one ends
+    if (txn < 0) {
+      take_next<L, K>(t, s, e, a, nx_state, nx_d, nx_rowk, nx_elem, nx_arg, ei, cell, &emask, &txn, &first, &n);
+      attempts = 0;
+      ready_at = 0;
+      waiting = false;
+    }
+    if (nx_state == 0 && !nx_end) {
+      uint32_t q = 0;
+      const uint64_t m = ballot(t.tl == 0);
+      const int lead = __ffsll((unsigned long long)m) - 1;
+      uint32_t base = 0;
+      if (t.lane == lead)
+        base = __hip_atomic_fetch_add(&queue_ctr, (uint32_t)__popcll(m), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      base = (uint32_t)__builtin_amdgcn_readlane((int)base, lead);
+      q = base + (uint32_t)__popcll(m & ((1ull << t.tb) - 1ull));
+      if (q < e.n_txns) {
+        nx_d = e.desc[q];
+        nx_state = 1;
+      } else {
+        nx_end = true;
       }
     }
-    if (need) {
-      if (q < e.n_txns) {
-        txn = (int64_t)e.list[q];
-        const DevTxn d = a.txns[txn];
-        first = d.first;
-        n = d.n;
-        attempts = 0;
-        ready_at = 0;
-        staged = false;
-        waiting = false;
-      } else {
-        done = true;
-      }
+    if (txn < 0) {
+      // a team with nothing to run (its first transaction): take the one just claimed
+      take_next<L, K>(t, s, e, a, nx_state, nx_d, nx_rowk, nx_elem, nx_arg, ei, cell, &emask, &txn, &first, &n);
+      attempts = 0;
+      ready_at = 0;
+      waiting = false;
     }
     if (ballot(txn >= 0) == 0) break;
     const uint64_t now = wall_clock64();
@@ -352,41 +446,16 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) engine_kernel(RunArgs a,
       active = (wait_j & ENG_WRITER) ? w == 0 : !(w & ENG_WRITER);
     }
     if (ballot(active) == 0) {
+      if (nx_state == 1) {
+        load_next_ops<L, K>(t, a, nx_d, nx_rowk, nx_elem, nx_arg);
+        nx_state = 2;
+      }
       __builtin_amdgcn_s_sleep(1);
       if (txn >= 0 && t.tl == 0) t_wait += wall_clock64() - now;
       continue;
     }
-    if (txn >= 0 && !staged) {
-      // the transaction's ops, once per transaction (team-uniform)
-      uint32_t m = 0;
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const uint32_t idx = (uint32_t)t.tl + (uint32_t)(k * L);
-        s.valid[k] = idx < n;
-        s.oi[k] = first + idx;
-        if (s.valid[k]) {
-          const DevOp op = a.ops[first + idx];
-          s.rowk[k] = op.rowk;
-          s.elem[k] = op.elem;
-          s.arg[k] = op.arg;
-        } else {
-          s.rowk[k] = FOLLOWER_BIT;
-          s.elem[k] = 0;
-          s.arg[k] = 0;
-        }
-        s.x[k] = 0;
-        s.v[k] = 0;
-        ei[k] = s.valid[k] ? eng_index(e, op_row(s.rowk[k]), s.elem[k], &cell[k]) : -1;
-        if (ei[k] >= 0 && op_leader(s.rowk[k])) m |= 1u << ei[k];
-      }
-      // OR over the team's lanes
-#pragma unroll
-      for (int o = 1; o < L; o <<= 1) m |= (uint32_t)__shfl_xor((int)m, o, 64);
-      emask = m;
-      staged = true;
-    }
     uint64_t key = 0, hot_dt = 0;
-    const int r = engine_attempt<L, K, STRICT>(t, s, ei, cell, emask, active, a, e, lk, tid, val, &ticket_ctr,
+    const int r = engine_attempt<L, K, STRICT>(t, s, ei, cell, emask, active, a, e, lk, tid, val, cb, &ticket_ctr,
                                                &hot_t0, &hot_dt, &wait_j, &key);
     if (t.tl == 0 && txn >= 0) {
       const uint64_t dt = wall_clock64() - now;
@@ -444,6 +513,11 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) engine_kernel(RunArgs a,
           ready_at = now + (mix64(((uint64_t)txn << 20) ^ attempts) % (span + 1));
         }
       }
+    }
+    // the next transaction's descriptor arrived during this iteration's rounds: its ops now
+    if (nx_state == 1) {
+      load_next_ops<L, K>(t, a, nx_d, nx_rowk, nx_elem, nx_arg);
+      nx_state = 2;
     }
   }
 
