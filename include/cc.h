@@ -241,10 +241,12 @@ enum cc_mode { CC_MODE_PLAIN = 0, CC_MODE_EPOCH = 1, CC_MODE_SERVE = 2 };
                                      rows, validate read rows) and the ticket comes from an LDS counter.  The rest of the
                                      batch then runs as usual, with the engine rows only read.  Paper
                                      Section 2 "Optimistic Concurrency Control" and Section 3.5 "OCC", with
-                                     hot rows locked pessimistically.  On by default for a contended OCC
-                                     batch (its most written row written by at least 0.1% of its
-                                     transactions) whose rows left out of the engine are written at most a
-                                     quarter as often as the most written one.  The engine runs one
+                                     hot rows locked pessimistically.  On by default for an OCC batch whose
+                                     most written row is written by at least a tenth of its transactions,
+                                     whose transactions have at most 32 ops, and whose rows left out of the
+                                     engine are written at most a quarter as often as the most written one
+                                     (elsewhere one workgroup carrying the hot rows' share loses to the
+                                     whole GPU).  The engine runs one
                                      transaction per wavefront (64 lanes) and as many wavefronts as fit,
                                      unless lanes_per_txn / waves_per_wg are set; it needs at most 4 ops per
                                      lane (CC_E_INVAL at cc_run when forced without) and a batch submitted by
@@ -458,9 +460,10 @@ cc_status cc_fetch_rows(cc_ctx *ctx, uint64_t batch_id, uint32_t *rows);
  * shared row space plus the row, tables in creation order -- most written
  * first; *n_rows their count (0: no engine for this batch: not OCC, keyed,
  * static, or nothing written often enough); *n_txns the transactions that
- * write one of them; *by_default 1 if cc_run uses the engine without
- * CC_RUN_HOT_ENGINE when the batch is contended (every row left out written at
- * most a quarter as often as the most written).  Host-side; no device work.
+ * write one of them; *by_default 1 if no row left out of the engine is
+ * written more than a quarter as often as the most written one -- one of the
+ * conditions under which cc_run uses the engine without CC_RUN_HOT_ENGINE
+ * (see there).  Host-side; no device work.
  */
 #define CC_ENGINE_MAX_ROWS 32
 cc_status cc_engine_plan(cc_ctx *ctx, uint64_t batch_id, uint32_t *rows, uint32_t *n_rows, uint64_t *n_txns,
@@ -589,10 +592,9 @@ cc_status cc_run_static(cc_ctx *ctx, const cc_txn *txns, uint64_t n_txns, const 
  *                          hand-off time t_h
  *   CC_PROBE_ENGINE_HANDOFF n_ops rounds of the OCC hot-row engine's commit
  *                          critical section on one engine row (LDS lock, LDS
- *                          ticket, one agent-scope validation load, LDS store
- *                          and release), alternating between two wavefronts of
- *                          one workgroup: ms / n_ops is the engine's t_h (peer
- *                          is ignored)
+ *                          ticket, LDS validation load, LDS store and release),
+ *                          alternating between two wavefronts of one workgroup:
+ *                          ms / n_ops is the engine's t_h (peer is ignored)
  * Random addresses are uniform over the footprint_bytes / 8 words of the
  * probe's buffer (rounded down to a multiple of 4).  For the hand-off probes,
  * peer places the second side: 0 in the same workgroup (same CU), 8 in

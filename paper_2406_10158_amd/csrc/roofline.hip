@@ -143,24 +143,25 @@ __global__ void __launch_bounds__(128) probe_commit_handoff(uint64_t *buf, uint6
 // The hot-row engine's commit critical section on one engine row, handed
 // back and forth between two wavefronts of one workgroup: wait for the turn
 // (an LDS word, bounded), take the row's LDS lock, draw a ticket from an LDS
-// counter, make one agent-scope validation load and wait for it, store the
-// new value in LDS and release the lock.  The time per round is the shortest
-// interval between two commits on one engine row: the engine's t_h.
+// counter, load a validation word from LDS (the engine validates its other
+// rows in an LDS table), store the new value in LDS and release the lock.
+// The time per round is the shortest interval between two commits on one
+// engine row: the engine's t_h.
 __global__ void __launch_bounds__(128) probe_engine_handoff(uint64_t *buf, uint64_t rounds, uint64_t spin_limit,
                                                             uint64_t *err) {
   __shared__ uint32_t lk;
-  __shared__ uint64_t turn, ticket;
+  __shared__ uint64_t turn, ticket, bucket[2];
   __shared__ int64_t value;
   if (threadIdx.x == 0) {
     lk = 0;
     turn = 0;
     ticket = 0;
     value = 0;
+    bucket[0] = bucket[1] = (uint64_t)buf[0];
   }
   __syncthreads();
   if (threadIdx.x % 64 != 0) return;
   const uint64_t side = threadIdx.x / 64;
-  const uint64_t *other = buf + 192 + 16 * side;
   for (uint64_t r = side; r < rounds; r += 2) {
     uint64_t spins = 0;
     while (__hip_atomic_load(&turn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != r) {
@@ -175,8 +176,7 @@ __global__ void __launch_bounds__(128) probe_engine_handoff(uint64_t *buf, uint6
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     const uint64_t t = __hip_atomic_fetch_add(&ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    const uint64_t o = __hip_atomic_load(other, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_s_waitcnt(0);
+    const uint64_t o = __hip_atomic_load(&bucket[side], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     value = value + 1 + (o == 0x5A5Aull ? (int64_t)t + got : 0);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     (void)__hip_atomic_fetch_and(&lk, ~(1u << 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
