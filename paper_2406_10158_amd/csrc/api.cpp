@@ -769,19 +769,24 @@ static void plan_engine(const DevOp *dops, const DevTxn *dtx, uint64_t n_txns, c
   // a row below the candidates is written at most as often as the last candidate
   if (!left_out && nc == NC) left_out = cc[NC - 1];
   b.eng_gain = (uint64_t)left_out * 4 <= (uint64_t)cc[0];
-  std::vector<uint8_t> is_eng(cnt.size(), 0);
-  for (uint32_t k = 0; k < b.eng.n_rows; ++k) is_eng[b.eng.row[k]] = 1;
+  std::vector<uint8_t> eng_of(cnt.size(), 0);  // engine index + 1 of a row (0: not an engine row)
+  for (uint32_t k = 0; k < b.eng.n_rows; ++k) eng_of[b.eng.row[k]] = (uint8_t)(k + 1);
   std::vector<uint8_t> in_eng(n_txns, 0);
   for (uint64_t t = 0; t < n_txns; ++t)
     for (uint32_t i = 0; i < dtx[t].n && !in_eng[t]; ++i) {
       const uint32_t rk = dops[dtx[t].first + i].rowk;
-      in_eng[t] = (rk & WRITTEN_BIT) && is_eng[rk & ROW_MASK];
+      in_eng[t] = (rk & WRITTEN_BIT) && eng_of[rk & ROW_MASK];
     }
   b.eng_part.reserve(n_txns);
   for (uint64_t t = 0; t < n_txns; ++t)
     if (in_eng[t]) {
+      uint32_t emask = 0;  // the engine rows the transaction touches, read or written
+      for (uint32_t i = 0; i < dtx[t].n; ++i) {
+        const uint32_t k = eng_of[dops[dtx[t].first + i].rowk & ROW_MASK];
+        if (k) emask |= 1u << (k - 1);
+      }
       b.eng_part.push_back((uint32_t)t);
-      b.eng_desc.push_back(EngineDesc{(uint32_t)t, dtx[t].first, dtx[t].n, 0u});
+      b.eng_desc.push_back(EngineDesc{(uint32_t)t, dtx[t].first, dtx[t].n, emask});
     }
   b.n_eng_txns = b.eng_part.size();
   for (uint64_t t = 0; t < n_txns; ++t)

@@ -160,8 +160,8 @@ struct IndexDesc {
 constexpr int ENG_MAX = 32;
 constexpr int ENG_FIELDS = 64;
 constexpr int ENG_VALS = 1024;
-struct EngineDesc {           // one engine transaction: its id, first op and op count
-  uint32_t txn, first, n, pad;
+struct EngineDesc {           // one engine transaction: its id, first op and op count, and the
+  uint32_t txn, first, n, emask;  // engine rows it touches (bit k: engine row k)
 };
 struct EngineArgs {
   const EngineDesc *desc;     // the engine's transactions, in batch order

@@ -146,7 +146,10 @@ __device__ __forceinline__ int engine_attempt(const Team<L> &t, Slots<K> &s, con
   uint32_t held = 0;                      // team-uniform: engine rows taken
   bool stop = false;                      // team-uniform: a row was not free
   uint64_t wneed = 0;
-  {
+  if (L == 64) {
+    // one team per wavefront: its `need` is the wavefront's
+    wneed = (uint32_t)__builtin_amdgcn_readfirstlane((int)need);
+  } else {
     // rows any team of the wavefront still needs (every lane of a team has `need`)
     uint32_t m = need;
 #pragma unroll
@@ -300,6 +303,9 @@ __device__ __forceinline__ int engine_attempt(const Team<L> &t, Slots<K> &s, con
   return valid_fail ? ABORT_VALID : COMMIT;
 }
 
+// Looks a waiting wavefront takes at its row before going round its main loop.
+constexpr int ENG_SPIN = 64;
+
 // Loads the ops of the staged transaction nx_d into the staging registers.
 template <int L, int K>
 __device__ __forceinline__ void load_next_ops(const Team<L> &t, const RunArgs &a, const EngineDesc &nx_d,
@@ -329,7 +335,6 @@ __device__ __forceinline__ void take_next(const Team<L> &t, Slots<K> &s, const E
   *txn = (int64_t)nx_d.txn;
   *first = nx_d.first;
   *n = nx_d.n;
-  uint32_t m = 0;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const uint32_t idx = (uint32_t)t.tl + (uint32_t)(k * L);
@@ -341,12 +346,10 @@ __device__ __forceinline__ void take_next(const Team<L> &t, Slots<K> &s, const E
     s.x[k] = 0;
     s.v[k] = 0;
     ei[k] = s.valid[k] ? eng_index(e, op_row(s.rowk[k]), s.elem[k], &cell[k]) : -1;
-    if (ei[k] >= 0 && op_leader(s.rowk[k])) m |= 1u << ei[k];
   }
-  // OR over the team's lanes
-#pragma unroll
-  for (int o = 1; o < L; o <<= 1) m |= (uint32_t)__shfl_xor((int)m, o, 64);
-  *emask = m;
+  // the engine rows the transaction touches come with its descriptor (a
+  // wavefront-uniform value when the team is the wavefront)
+  *emask = L == 64 ? (uint32_t)__builtin_amdgcn_readfirstlane((int)nx_d.emask) : nx_d.emask;
   nx_state = 0;
 }
 
@@ -438,12 +441,33 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) engine_kernel(RunArgs a,
       waiting = false;
     }
     if (ballot(txn >= 0) == 0) break;
-    const uint64_t now = wall_clock64();
+    uint64_t now = wall_clock64();
     bool active = txn >= 0 && now >= ready_at;
     if (active && waiting) {
       // a waiting team looks only at the row it waits for, and tries again once that row is free
-      const uint32_t w = __hip_atomic_load(lk + (wait_j & (ENG_MAX - 1)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      active = (wait_j & ENG_WRITER) ? w == 0 : !(w & ENG_WRITER);
+      const uint32_t wj = L == 64 ? (uint32_t)__builtin_amdgcn_readfirstlane((int)wait_j) : wait_j;
+      const uint32_t *wl = lk + (wj & (ENG_MAX - 1));
+      const bool wr = (wj & ENG_WRITER) != 0;
+      uint32_t w = __hip_atomic_load(wl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (L == 64 && (wr ? w != 0 : (w & ENG_WRITER) != 0)) {
+        // the wavefront's one team waits: its next transaction's ops are loaded
+        // meanwhile, and it looks at the row in a short loop of its own (a
+        // bounded number of looks, then once round the main loop)
+        if (nx_state == 1) {
+          load_next_ops<L, K>(t, a, nx_d, nx_rowk, nx_elem, nx_arg);
+          nx_state = 2;
+        }
+        w = (uint32_t)__builtin_amdgcn_readfirstlane((int)w);
+        for (int i = 0; i < ENG_SPIN && (wr ? w != 0 : (w & ENG_WRITER) != 0); ++i) {
+          __builtin_amdgcn_s_sleep(1);
+          w = (uint32_t)__builtin_amdgcn_readfirstlane(
+              (int)__hip_atomic_load(wl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+        }
+        const uint64_t now2 = wall_clock64();
+        if (t.tl == 0) t_wait += now2 - now;
+        now = now2;
+      }
+      active = wr ? w == 0 : !(w & ENG_WRITER);
     }
     if (ballot(active) == 0) {
       if (nx_state == 1) {
