@@ -22,6 +22,11 @@ ARCH = "gfx950"
 # Packed FP32 instructions are disabled in all device code.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include")]
+# The OCC sources hold the hot-row engine, whose LDS atomics are issued by one
+# lane that owns the row (or are already aggregated per wavefront by hand): the
+# compiler's wavefront aggregation of atomics would only lengthen its critical
+# sections.
+EXTRA_FLAGS = {"txn_occ.hip": ["-Xarch_device", "-mllvm=-amdgpu-atomic-optimizer-strategy=None"]}
 
 
 def build(verbose: bool = False) -> str:
@@ -33,7 +38,7 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
         cmd = [HIPCC, f"--offload-arch={ARCH}", *COMMON, "-c", src, "-o", obj]
         if src.endswith(".hip"):
-            cmd[1:1] = DEVICE_FLAGS
+            cmd[1:1] = DEVICE_FLAGS + EXTRA_FLAGS.get(os.path.basename(src), [])
         cmds.append((src, cmd))
         objs.append(obj)
 

@@ -156,7 +156,38 @@ __device__ __forceinline__ int engine_attempt(const Team<L> &t, Slots<K> &s, con
     for (int o = 32; o >= 1; o >>= 1) m |= (uint32_t)__shfl_xor((int)m, o, 64);
     wneed = m;
   }
-  while (wneed) {
+  if constexpr (L == 64 && K == 1) {
+    // one team per wavefront and one op per lane: the lane holding an engine
+    // row's op takes that row, and the rest of the loop is wavefront-uniform
+    const bool eop = go && s.valid[0] && op_leader(s.rowk[0]) && ei[0] >= 0;
+    const bool ewr = op_written(s.rowk[0]);
+    while (wneed) {
+      const int j = 63 - __clzll((unsigned long long)wneed);
+      wneed &= ~(1ull << j);
+      const bool mine = eop && ei[0] == j;
+      bool bad = false;
+      if (mine) {
+        if (ewr) {
+          uint32_t expect = 0;
+          bad = !__hip_atomic_compare_exchange_strong(lk + j, &expect, ENG_WRITER, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+          const uint32_t old = __hip_atomic_fetch_add(lk + j, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (old & ENG_WRITER) {
+            (void)__hip_atomic_fetch_sub(lk + j, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            bad = true;
+          }
+        }
+      }
+      if (ballot(bad)) {
+        stop = true;
+        *wait_j = (uint32_t)j | (ballot(mine && ewr) ? ENG_WRITER : 0u);
+        break;
+      }
+      held |= 1u << j;
+    }
+  }
+  while (L < 64 || K > 1 ? wneed : 0) {
     const int j = 63 - __clzll((unsigned long long)wneed);  // wavefront-uniform
     wneed &= ~(1ull << j);
     const bool want = go && !stop && ((need >> j) & 1u);  // team-uniform
@@ -221,20 +252,19 @@ __device__ __forceinline__ int engine_attempt(const Team<L> &t, Slots<K> &s, con
 #pragma unroll
   for (int k = 0; k < K; ++k)
     if (alive && s.valid[k] && ei[k] >= 0) s.x[k] = val[cell[k]];
-  uint64_t ticket = 0;
-  {
-    const uint64_t m = ballot(alive && t.tl == 0);
-    if (m) {
-      const int first = __ffsll((unsigned long long)m) - 1;
-      uint64_t base = 0;
-      if (t.lane == first)
-        base = __hip_atomic_fetch_add(ticket_ctr, (uint64_t)__popcll(m), __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_WORKGROUP);
-      base = readlane64(base, first);
-      ticket = base + 1 + (uint64_t)__popcll(m & ((1ull << t.tb) - 1ull));
-    }
-  }
-  lds_fence();  // the ticket is drawn before the releases and validation below
+  // one LDS add draws the tickets of the wavefront's live teams; its result is
+  // collected after the validation loads below are issued, so that both
+  // come back in one round trip
+  const uint64_t tk_m = ballot(alive && t.tl == 0);
+  const int tk_first = __ffsll((unsigned long long)tk_m) - 1;
+  uint64_t tk_base = 0;
+  if (tk_m && t.lane == tk_first)
+    tk_base = __hip_atomic_fetch_add(ticket_ctr, (uint64_t)__popcll(tk_m), __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+  // the ticket is drawn before the releases and validation below: a
+  // wavefront's LDS operations are performed in the order it issues them, so
+  // only the compiler has to keep that order
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
   for (int k = 0; k < K; ++k)
     if (alive && s.valid[k] && op_leader(s.rowk[k]) && ei[k] >= 0 && !op_written(s.rowk[k]))
@@ -251,6 +281,8 @@ __device__ __forceinline__ int engine_attempt(const Team<L> &t, Slots<K> &s, con
       bad |= ((cur & CB_LOCK) && cb_owner(cur) != me) || (cur & CB_VMASK) != s.v[k];
     }
   }
+  const uint64_t ticket =
+      tk_m ? readlane64(tk_base, tk_first) + 1 + (uint64_t)__popcll(tk_m & ((1ull << t.tb) - 1ull)) : 0;
   const bool valid_fail = t.any(bad);
   const bool commit = alive && !valid_fail;
 
@@ -273,7 +305,9 @@ __device__ __forceinline__ int engine_attempt(const Team<L> &t, Slots<K> &s, con
 #pragma unroll
   for (int k = 0; k < K; ++k)
     if (alive && s.valid[k] && op_leader(s.rowk[k]) && op_written(s.rowk[k]) && ei[k] >= 0 && commit) tid[ei[k]] = ticket;
-  lds_fence();  // values and tickets are in LDS before the locks are free
+  // values and tickets are in LDS before the locks are free (LDS operations
+  // of a wavefront are performed in issue order)
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
   for (int k = 0; k < K; ++k)
     if (alive && s.valid[k] && op_leader(s.rowk[k]) && op_written(s.rowk[k]) && ei[k] >= 0)
