@@ -242,7 +242,9 @@ __device__ __forceinline__ int engine_attempt(const Team<L> &t, Slots<K> &s, con
   bool w0 = false;
 #pragma unroll
   for (int k = 0; k < K; ++k) w0 |= s.valid[k] && op_leader(s.rowk[k]) && op_written(s.rowk[k]) && ei[k] == 0;
-  if (w0 && go && !stop && (held & 1u)) *hot_t0 = wall_clock64();
+  // the time the most written row was taken: read here, collected with the
+  // round trip below instead of waited for inside the hold
+  const uint64_t t_acq = wall_clock64();
   const bool alive = go && !stop;
   // the engine rows' holders issue first on their SIMD until they release them:
   // the waves polling for those rows share it
@@ -283,6 +285,7 @@ __device__ __forceinline__ int engine_attempt(const Team<L> &t, Slots<K> &s, con
   }
   const uint64_t ticket =
       tk_m ? readlane64(tk_base, tk_first) + 1 + (uint64_t)__popcll(tk_m & ((1ull << t.tb) - 1ull)) : 0;
+  if (w0 && go && !stop && (held & 1u)) *hot_t0 = t_acq;
   const bool valid_fail = t.any(bad);
   const bool commit = alive && !valid_fail;
 
@@ -513,6 +516,9 @@ __global__ void __launch_bounds__(MaxThreads<K>::value) engine_kernel(RunArgs a,
       continue;
     }
     uint64_t key = 0, hot_dt = 0;
+    // a transaction on the most written row runs ahead of the others on its
+    // SIMD (its holders go higher still): its attempts are the batch's critical path
+    if (ballot(active && (emask & 1u))) __builtin_amdgcn_s_setprio(2);
     const int r = engine_attempt<L, K, STRICT>(t, s, ei, cell, emask, active, a, e, lk, tid, val, cb, &ticket_ctr,
                                                &hot_t0, &hot_dt, &wait_j, &key);
     if (t.tl == 0 && txn >= 0) {
