@@ -95,13 +95,20 @@ __device__ __forceinline__ int engine_attempt(const Team<L> &t, Slots<K> &s, con
   uint32_t blk = ~0u;
   const uint32_t me = (uint32_t)threadIdx.x / (uint32_t)L;  // the team in the workgroup
   // R1: the cold rows' buckets -- a written row's locked (no wait), a
-  // read-only row's version read (held by another team: abort)
+  // read-only row's version read (held by another team: abort).  A row's
+  // value is loaded as soon as its bucket has been read free (or held by the
+  // team itself), so that the load overlaps the lock's round trip: a lock
+  // taken with the version read confirms that no commit wrote the row
+  // between the two, and a read-only row's version is validated later; a lock
+  // that succeeds only after the version moved loads the value again
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     s.got[k] = false;
     if (active && s.valid[k] && op_leader(s.rowk[k]) && ei[k] < 0) {
       uint64_t *w = cb + cold_bucket(op_row(s.rowk[k]));
       uint64_t cur = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      const uint64_t cur0 = cur;
+      if (!(cur & CB_LOCK) || cb_owner(cur) == me) s.x[k] = ld_val(a.data + s.elem[k]);
       bool ok = false;
       if (op_written(s.rowk[k])) {
         for (int i = 0; i < 4; ++i) {
@@ -116,6 +123,7 @@ __device__ __forceinline__ int engine_attempt(const Team<L> &t, Slots<K> &s, con
             break;
           }
         }
+        if (s.got[k] && cur != cur0) s.x[k] = ld_val(a.data + s.elem[k]);  // the version moved first
       } else {
         ok = !(cur & CB_LOCK) || cb_owner(cur) == me;
       }
@@ -133,11 +141,12 @@ __device__ __forceinline__ int engine_attempt(const Team<L> &t, Slots<K> &s, con
   }
   s.block = blocking_row(t, blk);
   lds_fence();  // the buckets before the values
-  // the cold values, waited for before any engine row is taken, so that no
-  // engine row is held across a global round trip
+  // the values of rows repeated in the transaction (loaded after their first
+  // op's bucket), and every cold value waited for before any engine row is
+  // taken, so that no engine row is held across a global round trip
 #pragma unroll
   for (int k = 0; k < K; ++k)
-    if (active && !lock_fail && s.valid[k] && ei[k] < 0) s.x[k] = ld_val(a.data + s.elem[k]);
+    if (active && !lock_fail && s.valid[k] && ei[k] < 0 && !op_leader(s.rowk[k])) s.x[k] = ld_val(a.data + s.elem[k]);
   if (ballot(active && !lock_fail)) order_point<STRICT>();
 
   // R1b: the engine rows, in decreasing engine index
