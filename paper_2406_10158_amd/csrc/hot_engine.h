@@ -259,71 +259,114 @@ __device__ __forceinline__ int engine_attempt(const Team<L> &t, Slots<K> &s, con
   // the waves polling for those rows share it
   if (ballot(alive)) __builtin_amdgcn_s_setprio(3);
 
-  // R2: engine values, the ticket, read-only engine rows released
-#pragma unroll
-  for (int k = 0; k < K; ++k)
-    if (alive && s.valid[k] && ei[k] >= 0) s.x[k] = val[cell[k]];
-  // one LDS add draws the tickets of the wavefront's live teams; its result is
-  // collected after the validation loads below are issued, so that both
-  // come back in one round trip
-  const uint64_t tk_m = ballot(alive && t.tl == 0);
-  const int tk_first = __ffsll((unsigned long long)tk_m) - 1;
-  uint64_t tk_base = 0;
-  if (tk_m && t.lane == tk_first)
-    tk_base = __hip_atomic_fetch_add(ticket_ctr, (uint64_t)__popcll(tk_m), __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_WORKGROUP);
-  // the ticket is drawn before the releases and validation below: a
-  // wavefront's LDS operations are performed in the order it issues them, so
-  // only the compiler has to keep that order
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-#pragma unroll
-  for (int k = 0; k < K; ++k)
-    if (alive && s.valid[k] && op_leader(s.rowk[k]) && ei[k] >= 0 && !op_written(s.rowk[k]))
-      (void)__hip_atomic_fetch_sub(lk + ei[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-
-  // R3: validation of the cold read-only rows: their buckets unchanged and
-  // not held by another team
-  bool bad = false;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    if (alive && s.valid[k] && op_leader(s.rowk[k]) && ei[k] < 0 && !op_written(s.rowk[k])) {
-      const uint64_t cur = __hip_atomic_load(cb + cold_bucket(op_row(s.rowk[k])), __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_WORKGROUP);
-      bad |= ((cur & CB_LOCK) && cb_owner(cur) != me) || (cur & CB_VMASK) != s.v[k];
-    }
-  }
-  const uint64_t ticket =
-      tk_m ? readlane64(tk_base, tk_first) + 1 + (uint64_t)__popcll(tk_m & ((1ull << t.tb) - 1ull)) : 0;
-  if (w0 && go && !stop && (held & 1u)) *hot_t0 = t_acq;
-  const bool valid_fail = t.any(bad);
-  const bool commit = alive && !valid_fail;
-
-  // R4: new values (WRITE_SLOT sources move between lanes: every lane takes part)
+  uint64_t ticket = 0;
+  bool valid_fail = false;
   int64_t nv[K];
-  {
-    int64_t src_val[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      uint32_t src = (a.has_slot && s.valid[k] && op_kind(s.rowk[k]) == CC_WRITE_SLOT) ? (uint32_t)(s.arg[k] & 0xFF) : 0u;
-      src_val[k] = a.has_slot ? slot_source<L, K>(t, s, src) : 0;
+  if constexpr (L == 64 && K == 1) {
+    // one team per wavefront and one op per lane: each lane's part in the hold
+    // is decided before it, and the hold runs under one wavefront-uniform branch
+    const uint32_t rk = s.rowk[0];
+    const bool lead = s.valid[0] && op_leader(rk), wrt = op_written(rk);
+    const bool e_op = s.valid[0] && ei[0] >= 0;
+    const bool e_rd = e_op && lead && !wrt, e_wr = e_op && lead && wrt;
+    const bool c_rd = lead && ei[0] < 0 && !wrt;
+    const bool e_inst = e_op && op_kind(rk) != CC_READ;
+    const uint32_t src = (a.has_slot && s.valid[0] && op_kind(rk) == CC_WRITE_SLOT) ? (uint32_t)(s.arg[0] & 0xFF) : 0u;
+    nv[0] = 0;
+    if (ballot(alive)) {
+      // R2: engine values and the ticket (one LDS add, collected with the
+      // validation loads), read-only engine rows released after the ticket
+      if (e_op) s.x[0] = val[cell[0]];
+      uint64_t tk = 0;
+      if (t.lane == 0)
+        tk = __hip_atomic_fetch_add(ticket_ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);  // LDS operations are performed in issue order
+      if (e_rd) (void)__hip_atomic_fetch_sub(lk + ei[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      // R3: the cold read-only rows' buckets unchanged and not held by another team
+      bool bad = false;
+      if (c_rd) {
+        const uint64_t cur = __hip_atomic_load(cb + cold_bucket(op_row(rk)), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        bad = ((cur & CB_LOCK) && cb_owner(cur) != me) || (cur & CB_VMASK) != s.v[0];
+      }
+      ticket = readlane64(tk, 0) + 1;
+      if (w0 && (held & 1u)) *hot_t0 = t_acq;
+      valid_fail = ballot(bad) != 0;
+      // R4: new values, engine rows installed, then their locks released
+      const int64_t sv = a.has_slot ? slot_source<L, K>(t, s, src) : 0;
+      nv[0] = apply_op(op_kind(rk), s.x[0], s.arg[0], sv);
+      if (!valid_fail && e_inst) val[cell[0]] = nv[0];
+      if (!valid_fail && e_wr) tid[ei[0]] = ticket;
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);  // values and tickets before the locks are free
+      if (e_wr) (void)__hip_atomic_fetch_and(lk + ei[0], ~ENG_WRITER, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
-#pragma unroll
-    for (int k = 0; k < K; ++k) nv[k] = apply_op(op_kind(s.rowk[k]), s.x[k], s.arg[k], src_val[k]);
+  } else {
+    // R2: engine values, the ticket, read-only engine rows released
+  #pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (alive && s.valid[k] && ei[k] >= 0) s.x[k] = val[cell[k]];
+    // one LDS add draws the tickets of the wavefront's live teams; its result is
+    // collected after the validation loads below are issued, so that both
+    // come back in one round trip
+    const uint64_t tk_m = ballot(alive && t.tl == 0);
+    const int tk_first = __ffsll((unsigned long long)tk_m) - 1;
+    uint64_t tk_base = 0;
+    if (tk_m && t.lane == tk_first)
+      tk_base = __hip_atomic_fetch_add(ticket_ctr, (uint64_t)__popcll(tk_m), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+    // the ticket is drawn before the releases and validation below: a
+    // wavefront's LDS operations are performed in the order it issues them, so
+    // only the compiler has to keep that order
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  #pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (alive && s.valid[k] && op_leader(s.rowk[k]) && ei[k] >= 0 && !op_written(s.rowk[k]))
+        (void)__hip_atomic_fetch_sub(lk + ei[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+
+    // R3: validation of the cold read-only rows: their buckets unchanged and
+    // not held by another team
+    bool bad = false;
+  #pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (alive && s.valid[k] && op_leader(s.rowk[k]) && ei[k] < 0 && !op_written(s.rowk[k])) {
+        const uint64_t cur = __hip_atomic_load(cb + cold_bucket(op_row(s.rowk[k])), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        bad |= ((cur & CB_LOCK) && cb_owner(cur) != me) || (cur & CB_VMASK) != s.v[k];
+      }
+    }
+    ticket =
+        tk_m ? readlane64(tk_base, tk_first) + 1 + (uint64_t)__popcll(tk_m & ((1ull << t.tb) - 1ull)) : 0;
+    if (w0 && go && !stop && (held & 1u)) *hot_t0 = t_acq;
+    valid_fail = t.any(bad);
+    const bool commit = alive && !valid_fail;
+
+    // R4: new values (WRITE_SLOT sources move between lanes: every lane takes part)
+    {
+      int64_t src_val[K];
+  #pragma unroll
+      for (int k = 0; k < K; ++k) {
+        uint32_t src = (a.has_slot && s.valid[k] && op_kind(s.rowk[k]) == CC_WRITE_SLOT) ? (uint32_t)(s.arg[k] & 0xFF) : 0u;
+        src_val[k] = a.has_slot ? slot_source<L, K>(t, s, src) : 0;
+      }
+  #pragma unroll
+      for (int k = 0; k < K; ++k) nv[k] = apply_op(op_kind(s.rowk[k]), s.x[k], s.arg[k], src_val[k]);
+    }
+    // engine rows first: their install and release wait for nothing global
+  #pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (commit && s.valid[k] && op_kind(s.rowk[k]) != CC_READ && ei[k] >= 0) val[cell[k]] = nv[k];
+  #pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (alive && s.valid[k] && op_leader(s.rowk[k]) && op_written(s.rowk[k]) && ei[k] >= 0 && commit) tid[ei[k]] = ticket;
+    // values and tickets are in LDS before the locks are free (LDS operations
+    // of a wavefront are performed in issue order)
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  #pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (alive && s.valid[k] && op_leader(s.rowk[k]) && op_written(s.rowk[k]) && ei[k] >= 0)
+        (void)__hip_atomic_fetch_and(lk + ei[k], ~ENG_WRITER, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
-  // engine rows first: their install and release wait for nothing global
-#pragma unroll
-  for (int k = 0; k < K; ++k)
-    if (commit && s.valid[k] && op_kind(s.rowk[k]) != CC_READ && ei[k] >= 0) val[cell[k]] = nv[k];
-#pragma unroll
-  for (int k = 0; k < K; ++k)
-    if (alive && s.valid[k] && op_leader(s.rowk[k]) && op_written(s.rowk[k]) && ei[k] >= 0 && commit) tid[ei[k]] = ticket;
-  // values and tickets are in LDS before the locks are free (LDS operations
-  // of a wavefront are performed in issue order)
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-#pragma unroll
-  for (int k = 0; k < K; ++k)
-    if (alive && s.valid[k] && op_leader(s.rowk[k]) && op_written(s.rowk[k]) && ei[k] >= 0)
-      (void)__hip_atomic_fetch_and(lk + ei[k], ~ENG_WRITER, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const bool commit = alive && !valid_fail;
   __builtin_amdgcn_s_setprio(0);
   if (alive && *hot_t0) *hot_dt = wall_clock64() - *hot_t0;
   // cold rows: values and words to global memory, then the buckets released
