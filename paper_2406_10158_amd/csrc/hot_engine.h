@@ -287,14 +287,25 @@ __device__ __forceinline__ int engine_attempt(const Team<L> &t, Slots<K> &s, con
       if (c_rd) {
         const uint64_t cur = __hip_atomic_load(cb + cold_bucket(op_row(rk)), __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_WORKGROUP);
-        bad = ((cur & CB_LOCK) && cb_owner(cur) != me) || (cur & CB_VMASK) != s.v[0];
+        bad = (((cur & CB_LOCK) != 0) & (cb_owner(cur) != me)) | ((cur & CB_VMASK) != s.v[0]);
       }
       ticket = readlane64(tk, 0) + 1;
       if (w0 && (held & 1u)) *hot_t0 = t_acq;
       valid_fail = ballot(bad) != 0;
       // R4: new values, engine rows installed, then their locks released
-      const int64_t sv = a.has_slot ? slot_source<L, K>(t, s, src) : 0;
-      nv[0] = apply_op(op_kind(rk), s.x[0], s.arg[0], sv);
+      // the new value without branches on the op's kind (WRITE_SLOT only in
+      // batches that have slot ops)
+      {
+        const uint32_t kind = op_kind(rk);
+        const int64_t pre = s.x[0];
+        const int64_t add = (int64_t)((uint64_t)pre + (uint64_t)s.arg[0]);
+        const int64_t cadd = add < CC_COND_LO ? (int64_t)((uint64_t)add + (uint64_t)CC_COND_HI) : add;
+        nv[0] = kind == CC_ADD ? add : (kind == CC_COND_ADD ? cadd : pre);
+        if (a.has_slot) {
+          const int64_t sv = slot_source<L, K>(t, s, src);
+          if (kind == CC_WRITE_SLOT) nv[0] = apply_op(CC_WRITE_SLOT, pre, s.arg[0], sv);
+        }
+      }
       if (!valid_fail && e_inst) val[cell[0]] = nv[0];
       if (!valid_fail && e_wr) tid[ei[0]] = ticket;
       __atomic_signal_fence(__ATOMIC_SEQ_CST);  // values and tickets before the locks are free
