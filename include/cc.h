@@ -332,11 +332,12 @@ enum cc_stat {
                                  reused; with fewer, the arena is a ring */
   CC_STAT_VERSION_MISSES = 34,/* CC_MVCC: old-version reads whose version's slot the ring had reused
                                  (the attempt aborted and retried with a newer timestamp) */
-  CC_STAT_ENGINE_TXNS = 35,   /* CC_RUN_HOT_ENGINE: transactions the hot-row engine ran (0: no engine) */
-  CC_STAT_ENGINE_ROWS = 36,   /* CC_RUN_HOT_ENGINE: rows the engine held in LDS */
-  CC_STAT_ENGINE_NS = 37,     /* CC_RUN_HOT_ENGINE: the engine's kernel time (part of CC_STAT_KERNEL_NS) */
-  CC_STAT_ENGINE_WAITS = 38,  /* CC_RUN_HOT_ENGINE: loop iterations a transaction spent waiting for an
-                                 engine row, keeping its locks */
+  CC_STAT_ENGINE_TXNS = 35,   /* hot-row engine (CC_RUN_HOT_ENGINE, or by default): transactions it ran
+                                 (0: no engine) */
+  CC_STAT_ENGINE_ROWS = 36,   /* hot-row engine: rows it held in LDS */
+  CC_STAT_ENGINE_NS = 37,     /* hot-row engine: its kernel time (part of CC_STAT_KERNEL_NS) */
+  CC_STAT_ENGINE_WAITS = 38,  /* hot-row engine: times a transaction found an engine row taken, gave back
+                                 every row it held and waited for that row */
   CC_N_STATS = 40
 };
 
